@@ -1,0 +1,189 @@
+"""Throughput of the MD hot path on one MI355X: atom-steps per second.
+
+Workload (default): Lennard-Jones cut and shifted at r_c = 2.5 sigma,
+N = 2,048,000 atoms from an 80^3 FCC lattice at density 0.8442, T = 0.72,
+dt = 0.004, neighbor list with skin 0.3 sigma rebuilt when an atom has moved
+more than skin/2, atoms reordered by cell at every rebuild.  One "step" is a
+whole leapfrog step: kick, drift, rebuild when needed (cells + list),
+forces, kick, and the device-side reductions.  The FP64 path gives `value`;
+the FP32-mixed path is measured on the same input and reported beside it.
+
+Prints one JSON line.  With --gpus above 1 it exits: the build targets one
+GPU.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "atom-steps/sec at N=2.05M LJ (FP64 vs FP32-mixed); adjoint/forward time ratio"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="lj_2048k")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-mixed measurement")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    return ap.parse_args()
+
+
+def force_bytes_per_atom(mean_nl, precision):
+    """Algorithmic HBM bytes of one force pass per atom: the list row
+    (4 B per entry) and its length (4 B), the atom's own position (24 B),
+    and the force written back (24 B in FP64, 12 B in FP32)."""
+    return 4.0 * mean_nl + 4.0 + 24.0 + (24.0 if precision == "fp64" else 12.0)
+
+
+def run_gpu(w, precision, steps, warmup):
+    import torch
+
+    from paper_2003_14061_amd import md
+
+    sim = md.Simulation(w.pos, w.vel, w.L, r_cut=w.r_cut, skin=w.skin, dt=w.dt,
+                        shifted=w.shifted, precision=precision, neighbor_list=w.use_nl)
+    sim.prepare()
+    sim.step(warmup)
+    o0 = sim.reduce()
+    e0 = (o0["U"] + o0["K"]) / w.n
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    f_ms, f_launches = sim.get_timing()
+    sim.set_timing(False)
+    o1 = sim.reduce()
+    e1 = (o1["U"] + o1["K"]) / w.n
+    cnt, _ = sim.neighbor_list()
+    mean_nl = float(cnt[: w.n].mean())
+    wall = t1 - t0
+    res = {
+        "value": w.n * steps / wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "force_ms_avg": f_ms / max(f_launches, 1),
+        "force_launches": f_launches,
+        "mean_nl": mean_nl,
+        "rebuilds": int(o1["n_rebuilds"] - o0["n_rebuilds"]),
+        "energy_drift_per_atom": e1 - e0,
+        "T_end": o1["T"],
+    }
+    bpa = force_bytes_per_atom(mean_nl, precision)
+    achieved = bpa * w.n / (res["force_ms_avg"] * 1e-3) / 1e9
+    res["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                       "traffic": None, "kernel": "k_forces",
+                       "bytes_per_atom": round(bpa, 2)}
+    del sim
+    torch.cuda.synchronize()
+    return res
+
+
+def run_cpu(w, steps):
+    import oracle
+
+    s = oracle.make_sys(w.n, w.L, r_cut=w.r_cut, skin=w.skin, dt=w.dt,
+                        potential=oracle.LJ_SHIFTED if w.shifted else oracle.LJ_TRUNC,
+                        use_nl=w.use_nl)
+    t = time.perf_counter()
+    oracle.run(s, w.pos, w.vel, 0)
+    t_build = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.run(s, w.pos, w.vel, steps)
+    t_run = time.perf_counter() - t
+    per = max(t_run - t_build, 1e-9)
+    return {"value": w.n * steps / per, "unit": "atom-steps/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{w.name}: full N={w.n}, {steps} steps from the FCC start; time of "
+                      f"the run minus the time of its initial cell/list/force build"}
+
+
+def copy_probe(mib):
+    import torch
+
+    a = torch.empty(mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "decomposition is a design note, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2003_14061_amd import inputs
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    w = inputs.preset(args.workload).materialize()
+    fp64 = run_gpu(w, "fp64", args.steps, args.warmup)
+    print(f"[bench] fp64 done: {fp64['value']:.3e} atom-steps/s", file=sys.stderr, flush=True)
+    mixed = None
+    if not args.no_mixed:
+        mixed = run_gpu(w, "fp32", args.steps, args.warmup)
+        print(f"[bench] fp32-mixed done: {mixed['value']:.3e} atom-steps/s", file=sys.stderr,
+              flush=True)
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
+    cpu = None
+    if not args.no_cpu:
+        cpu = run_cpu(w, args.cpu_steps)
+        print(f"[bench] cpu oracle done: {cpu['value']:.3e} atom-steps/s", file=sys.stderr,
+              flush=True)
+    out = {
+        "metric": METRIC,
+        "value": round(fp64["value"], 1),
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(fp64["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.name}: LJ cut and shifted at r_c={w.r_cut:g} sigma, N={w.n} "
+                        f"(FCC), rho={w.rho}, T={w.T}, dt={w.dt}, skin={w.skin}, neighbor list "
+                        f"rebuilt at max displacement > skin/2, reorder by cell at rebuild",
+            "n_atoms": w.n, "precision": "fp64"},
+        "roofline": fp64["roofline"],
+        "cpu_baseline": cpu,
+        "rebuilds": fp64["rebuilds"],
+        "mean_nl": round(fp64["mean_nl"], 2),
+        "energy_drift_per_atom": fp64["energy_drift_per_atom"],
+        "force_ms_avg": round(fp64["force_ms_avg"], 5),
+    }
+    if mixed is not None:
+        out["fp32_mixed"] = {"value": round(mixed["value"], 1),
+                             "ms_per_step": round(mixed["ms_per_step"], 5),
+                             "roofline": mixed["roofline"], "rebuilds": mixed["rebuilds"],
+                             "energy_drift_per_atom": mixed["energy_drift_per_atom"],
+                             "force_ms_avg": round(mixed["force_ms_avg"], 5),
+                             "speedup_vs_fp64": round(mixed["value"] / fp64["value"], 3)}
+    out["adjoint_forward_ratio"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,222 @@
+/*
+ * md.h -- C ABI of libmd, a short-range molecular dynamics engine for AMD
+ * MI355X (gfx950), after Rapaport, "GPU molecular dynamics: Algorithms and
+ * performance", arXiv:2003.14061.
+ *
+ * The calls follow the paper's statement of the problem (section 2.3): atoms
+ * are assigned to cells (steps N1-N4), a neighbor list is built from the 27
+ * surrounding cells (N5), forces are accumulated per atom over the list
+ * without Newton's-third-law sharing (F1), and energies are reduced (F2); the
+ * list is refreshed only every several steps.  Integration is the symplectic
+ * leapfrog (section 4.3) in kick-drift-kick form.
+ *
+ * Memory.  The caller owns every byte of device memory: the per-atom state
+ * arrays and one workspace block whose size md_workspace_bytes() reports.
+ * The library never allocates or frees device memory.  All per-atom arrays
+ * are structure-of-arrays (one array per component), length n_atoms, stored
+ * in the library's current storage order; id[k] is the permanent id of the
+ * atom held in slot k (section 4.1, factor (1)).  With reorder enabled the
+ * slots are permuted into cell order at every rebuild.
+ *
+ * Streams.  Every call except md_init, md_workspace_bytes, md_layout,
+ * md_geometry, md_reduce, md_history and md_destroy only enqueues work on
+ * the stream given to md_bind and returns at once.  md_reduce and md_history
+ * synchronize that stream.  A context is not thread-safe; distinct contexts
+ * on distinct streams are independent.
+ *
+ * Errors.  Calls return md_status.  Argument errors are detected on the host
+ * before anything is enqueued.  Conditions found on the device (list
+ * overflow, non-finite force) are latched in a device flag word and reported
+ * by the next md_reduce; they stay latched until md_bind is called again.
+ * No C++ exception crosses this interface.
+ */
+#ifndef MD_H
+#define MD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct md_ctx md_ctx;
+
+typedef enum {
+    MD_OK = 0,
+    MD_ERR_ARG = -1,            /* invalid argument or parameter */
+    MD_ERR_BOX_TOO_SMALL = -2,  /* fewer than 3 cells per side */
+    MD_ERR_NL_OVERFLOW = -3,    /* an atom had more list entries than nl_capacity */
+    MD_ERR_NONFINITE = -4,      /* a force or energy was not finite */
+    MD_ERR_HIP = -5,            /* a HIP runtime call failed */
+    MD_ERR_NOT_BOUND = -6,      /* md_bind has not been called */
+    MD_ERR_STATE = -7           /* call out of order (e.g. step before forces) */
+} md_status;
+
+enum { MD_LJ_SHIFTED = 0, MD_LJ_TRUNC = 1 };      /* potential */
+enum { MD_FP64 = 0, MD_FP32_MIXED = 1 };          /* precision */
+enum { MD_CELLS_ONLY = 0, MD_NEIGHBOR_LIST = 1 }; /* mode */
+
+/* Device flag bits (md_observables.flags). */
+enum { MD_FLAG_NL_OVERFLOW = 1, MD_FLAG_NONFINITE = 2 };
+
+/* System and method parameters, copied by md_init.  Lengths in the units of
+ * sigma's length, energies in eps's units. */
+typedef struct {
+    int32_t n_atoms;     /* N >= 1 */
+    int32_t potential;   /* MD_LJ_SHIFTED: 12-6 potential cut at r_cut and shifted to
+                            vanish there (soft spheres: r_cut = 2^(1/6) sigma);
+                            MD_LJ_TRUNC: cut, not shifted (forces identical) */
+    double  L;           /* edge of the periodic cube; positions must lie in [0, L) */
+    double  eps, sigma, mass;
+    double  r_cut;       /* cutoff, absolute */
+    double  skin;        /* neighbor shell thickness (the paper's delta); list radius
+                            r_cut + skin; the list is rebuilt when some atom has moved
+                            more than skin/2 since the last build */
+    double  dt;          /* time step */
+    int32_t precision;   /* MD_FP64, or MD_FP32_MIXED: pair forces formed and summed in
+                            FP32 from FP64 separations, cutoff test in FP64; positions,
+                            velocities, integration and energy sums stay FP64 */
+    int32_t mode;        /* MD_NEIGHBOR_LIST (cells of width >= r_cut+skin, list) or
+                            MD_CELLS_ONLY (cells of width >= r_cut, rebuilt every step,
+                            forces straight from the 27 cells) */
+    int32_t newton3;     /* 0: full list, no atomics (the paper's choice, section 2.3);
+                            1: half list, the partner's force added with atomics */
+    int32_t nl_capacity; /* list entries reserved per atom; 0 picks a bound from the
+                            density */
+    int32_t reorder;     /* 1: permute the atom slots into cell order at every rebuild
+                            (section 4.1, factor (1)); 0: never permute */
+    int32_t block;       /* threads per workgroup for per-atom kernels, a multiple of 64
+                            in [64, 1024]; 0 = 256 */
+} md_params;
+
+/* Device buffers supplied by the caller (all device pointers). */
+typedef struct {
+    double*  x;  double* y;  double* z;    /* positions, in [0, L) */
+    double*  vx; double* vy; double* vz;   /* velocities */
+    void*    fx; void*   fy; void*   fz;   /* forces: double (MD_FP64) or float (MD_FP32_MIXED) */
+    int32_t* id;                           /* permanent atom ids */
+    void*    workspace;                    /* md_workspace_bytes() bytes, 256-byte aligned */
+} md_buffers;
+
+/* Derived geometry (host side, filled by md_geometry). */
+typedef struct {
+    int32_t nc;          /* cells per side */
+    int32_t n_cells;     /* nc^3 */
+    int32_t nl_capacity; /* list rows */
+    int32_t n_pad;       /* row pitch of the list, n rounded up to 64 */
+    double  cell_width;  /* L / nc */
+} md_grid;
+
+/* Results of md_reduce.  Energies are totals over the system. */
+typedef struct {
+    double  U;           /* potential energy */
+    double  K;           /* kinetic energy, (m/2) sum v^2 */
+    double  W;           /* pair virial, sum over pairs i<j of r_ij . F_ij */
+    double  P[3];        /* total momentum */
+    double  T;           /* 2K / (3(N-1)) */
+    double  pressure;    /* (2K + W) / (3 L^3) */
+    double  dmax;        /* largest displacement since the last list build, as of the
+                            last drift */
+    int64_t step;        /* steps completed since md_bind */
+    int64_t n_rebuilds;  /* list (or cell) rebuilds triggered by md_step */
+    int32_t max_occupancy; /* largest cell occupancy at the last cell build */
+    int32_t max_nl;        /* longest list at the last list build */
+    int32_t flags;         /* latched MD_FLAG_* bits */
+    int32_t pad;
+} md_observables;
+
+/* One record of the step history (md_history). */
+typedef struct {
+    int64_t step;
+    double  U, K, W, P[3], dmax;
+    int32_t rebuilt;     /* 1 if this step rebuilt the cells/list */
+    int32_t pad;
+} md_record;
+
+/* Array identifiers for md_layout (each lives inside the workspace). */
+enum {
+    MD_ARR_CELL_OF = 0,    /* int32[n]     cell of the atom in slot k (N1) */
+    MD_ARR_CELL_START = 1, /* int32[nc^3+1] first entry of each cell in CELL_ATOMS (N2-N4) */
+    MD_ARR_CELL_ATOMS = 2, /* int32[n]     slots grouped by cell, ascending id in a cell */
+    MD_ARR_NL = 3,         /* int32[cap][n_pad] neighbor slots, row m = m-th neighbors (N5) */
+    MD_ARR_NL_COUNT = 4,   /* int32[n]     list length per slot */
+    MD_ARR_XREF = 5,       /* double[3][n] positions at the last list build */
+    MD_ARR_COUNT_ = 6
+};
+
+/* md_init: validate parameters, derive the cell grid and list capacity.
+ * No device work.  *out receives a new context on MD_OK.  Returns
+ * MD_ERR_ARG for bad values, MD_ERR_BOX_TOO_SMALL when floor(L / cell
+ * width) < 3. */
+md_status md_init(const md_params* params, md_ctx** out);
+
+/* Bytes of workspace the context needs (0 for a NULL context). */
+size_t md_workspace_bytes(const md_ctx* ctx);
+
+/* Geometry derived by md_init. */
+md_status md_geometry(const md_ctx* ctx, md_grid* out);
+
+/* Byte offset and element count of a workspace array (MD_ARR_*). */
+md_status md_layout(const md_ctx* ctx, int32_t which, size_t* offset, size_t* count);
+
+/* md_bind: borrow the caller's buffers and stream (a hipStream_t; NULL means
+ * the null stream).  Clears the device counters and flags (enqueued).  The
+ * buffers must stay valid until the context is destroyed or bound again. */
+md_status md_bind(md_ctx* ctx, const md_buffers* bufs, void* hip_stream);
+
+/* md_build_cells (N1-N4, and the reorder): assign every atom to its cell,
+ * group the slots by cell with ascending id inside a cell, and, with reorder
+ * on, permute positions, velocities, forces and ids into that order.
+ * Enqueued. */
+md_status md_build_cells(md_ctx* ctx);
+
+/* md_build_neighbors (N5): for every atom, the other atoms of the 27
+ * surrounding cells (visited with dz, dy, dx each -1, 0, +1, dz slowest;
+ * inside a cell in ascending id) whose minimum-image separation is below
+ * r_cut + skin, squared separation formed as dx*dx + dy*dy + dz*dz with two
+ * fused multiply-adds.  Records the positions as the displacement
+ * reference.  Requires md_build_cells.  MD_NEIGHBOR_LIST mode only.
+ * Enqueued; overflow is latched. */
+md_status md_build_neighbors(md_ctx* ctx);
+
+/* md_forces (F1): per-atom force over the list (or the 27 cells in
+ * MD_CELLS_ONLY mode), pairs closer than r_cut, plus per-workgroup partial
+ * sums of the potential energy and the virial.  Requires the cells (and
+ * list).  Enqueued. */
+md_status md_forces(md_ctx* ctx);
+
+/* md_step: n_steps leapfrog steps, kick-drift-kick: v += dt/(2m) f; x += dt v,
+ * wrapped into [0, L); rebuild cells (and list) when needed; forces;
+ * v += dt/(2m) f.  Requires md_forces to have run on the current state.
+ * When record_every > 0, every step whose index is a multiple of
+ * record_every is appended to the history (capacity 4096 records, oldest
+ * overwritten).  Enqueued. */
+md_status md_step(md_ctx* ctx, int32_t n_steps, int32_t record_every);
+
+/* md_reduce (F2): finish the reductions on the device (kinetic energy,
+ * momentum, the potential energy and virial of the last force pass) and
+ * copy them to *out.  Synchronizes the stream.  Returns the latched device
+ * condition, if any, as its status (MD_ERR_NL_OVERFLOW, MD_ERR_NONFINITE). */
+md_status md_reduce(md_ctx* ctx, md_observables* out);
+
+/* md_history: copy up to max_records history records, oldest first, to the
+ * host array out; *n_out receives the count.  Synchronizes the stream. */
+md_status md_history(md_ctx* ctx, md_record* out, int32_t max_records, int32_t* n_out);
+
+/* md_set_timing: when enable != 0, bracket every force-pass launch with HIP
+ * events on the bound stream; md_get_timing returns the summed elapsed time
+ * (ms) and the number of timed launches since timing was enabled, and
+ * synchronizes the stream. */
+md_status md_set_timing(md_ctx* ctx, int32_t enable);
+md_status md_get_timing(md_ctx* ctx, double* total_ms, int64_t* launches);
+
+void md_destroy(md_ctx* ctx);
+
+/* Static string for a status code. */
+const char* md_status_str(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

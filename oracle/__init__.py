@@ -48,6 +48,8 @@ def lib():
         L = C.CDLL(path)
         L.or_pair.restype = C.c_double
         L.or_pair.argtypes = [_SP, C.c_double, C.POINTER(C.c_double)]
+        L.or_pair_scale.restype = C.c_double
+        L.or_pair_scale.argtypes = [_SP, C.c_double]
         L.or_shift.restype = C.c_double
         L.or_shift.argtypes = [_SP]
         L.or_wrap.restype = C.c_double
@@ -112,6 +114,11 @@ def pair(s, r2):
     fr = C.c_double()
     u = lib().or_pair(C.byref(s), float(r2), C.byref(fr))
     return u, fr.value
+
+
+def pair_scale(s, r2):
+    """48 eps (sr^12 + sr^6/2) / r: the error scale of one pair force."""
+    return lib().or_pair_scale(C.byref(s), float(r2))
 
 
 def shift(s):

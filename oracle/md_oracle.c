@@ -195,6 +195,18 @@ int32_t or_build_nl(const or_sys* s, int32_t nc,
 /* F1: forces.  Each pair (i, j) contributes to atom i only; it is met again
  * from atom j (full list, section 2.3). */
 
+/* Scale of the rounding error of one pair force: the magnitudes of its
+ * repulsive and attractive parts added, 48 eps (sr^12 + sr^6/2) / r.  Where
+ * the two parts cancel (near the minimum at 2^(1/6) sigma) this stays of the
+ * order of the parts while the force itself goes to zero. */
+double or_pair_scale(const or_sys* s, double r2)
+{
+    if (!(r2 < s->r_cut * s->r_cut)) return 0.0;
+    double sr2 = (s->sigma * s->sigma) / r2;
+    double sr6 = sr2 * sr2 * sr2;
+    return 48.0 * s->eps * (sr6 * sr6 + 0.5 * sr6) / sqrt(r2);
+}
+
 static void pair_into(const or_sys* s, double dx, double dy, double dz,
                       double* f3, double* u, double* w, double* sm)
 {
@@ -207,7 +219,7 @@ static void pair_into(const or_sys* s, double dx, double dy, double dz,
     f3[2] += fr * dz;
     *u += 0.5 * up;
     *w += 0.5 * (fr * r2);
-    *sm += fabs(fr) * sqrt(r2);
+    *sm += or_pair_scale(s, r2);
 }
 
 static void store_atom(int32_t i, const double* f3, double u, double w, double sm,

@@ -85,8 +85,10 @@ int32_t or_build_nl(const or_sys* s, int32_t nc,
                     int32_t* nl_count, int32_t* nl);
 
 /* ---- F1: forces.  u_i gets half of each pair energy, w_i half of each
- *      pair virial, s_i the sum of pair force magnitudes (a scale for
- *      tolerances).  Any of u_i, w_i, s_i may be NULL. ---- */
+ *      pair virial, s_i the sum over pairs of or_pair_scale (the scale of
+ *      the rounding error of the force sum, used for tolerances).  Any of
+ *      u_i, w_i, s_i may be NULL. ---- */
+double or_pair_scale(const or_sys* s, double r2);
 void or_forces_nl(const or_sys* s,
                   const double* x, const double* y, const double* z,
                   const int32_t* nl_count, const int32_t* nl,

@@ -1,0 +1,442 @@
+// md_api.hip -- the C ABI of libmd (declared in include/md.h).
+//
+// Host side only: validation, derived geometry, workspace layout, the
+// kernel-parameter block and the order of launches.  All arithmetic on atoms
+// happens in the kernels of the other translation units.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "md_internal.h"
+
+using namespace md;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+enum Region {
+    R_DEV, R_CELL_COUNT, R_CELL_START, R_CELL_OF, R_SLOT, R_ORDER, R_NL, R_NL_COUNT,
+    R_XR, R_YR, R_ZR, R_SX, R_SY, R_SZ, R_SVX, R_SVY, R_SVZ, R_SFX, R_SFY, R_SFZ, R_SID,
+    R_SCELL, R_FPART, R_IPART, R_SCAN, R_HIST, R_COUNT
+};
+
+}  // namespace
+
+struct md_ctx {
+    md_params prm;
+    md_grid geo;
+    KParams kp;
+    size_t off[R_COUNT];
+    size_t bytes[R_COUNT];
+    size_t ws_bytes;
+    hipStream_t stream = nullptr;
+    bool bound = false, cells_ok = false, nl_ok = false, forces_ok = false;
+    bool timing = false;
+    std::vector<hipEvent_t> ev_free, ev_pending;  // pending holds start/stop pairs
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+};
+
+extern "C" const char* md_status_str(int32_t st)
+{
+    switch (st) {
+        case MD_OK: return "ok";
+        case MD_ERR_ARG: return "invalid argument";
+        case MD_ERR_BOX_TOO_SMALL: return "box too small: fewer than 3 cells per side";
+        case MD_ERR_NL_OVERFLOW: return "neighbor list overflow: raise nl_capacity";
+        case MD_ERR_NONFINITE: return "non-finite force or energy";
+        case MD_ERR_HIP: return "HIP runtime error";
+        case MD_ERR_NOT_BOUND: return "buffers not bound (call md_bind)";
+        case MD_ERR_STATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+static md_status hip_ok(hipError_t e) { return e == hipSuccess ? MD_OK : MD_ERR_HIP; }
+
+static md_status launched() { return hip_ok(hipGetLastError()); }
+
+extern "C" md_status md_init(const md_params* in, md_ctx** out)
+{
+    if (!in || !out) return MD_ERR_ARG;
+    *out = nullptr;
+    md_params p = *in;
+    if (p.block == 0) p.block = 256;
+    const bool finite = isfinite(p.L) && isfinite(p.eps) && isfinite(p.sigma) &&
+                        isfinite(p.mass) && isfinite(p.r_cut) && isfinite(p.skin) &&
+                        isfinite(p.dt);
+    if (!finite || p.n_atoms < 1 || p.L <= 0 || p.eps <= 0 || p.sigma <= 0 || p.mass <= 0 ||
+        p.r_cut <= 0 || p.skin < 0 || p.dt <= 0)
+        return MD_ERR_ARG;
+    if ((p.potential != MD_LJ_SHIFTED && p.potential != MD_LJ_TRUNC) ||
+        (p.precision != MD_FP64 && p.precision != MD_FP32_MIXED) ||
+        (p.mode != MD_CELLS_ONLY && p.mode != MD_NEIGHBOR_LIST) || p.newton3 != 0 ||
+        p.nl_capacity < 0 || (p.reorder != 0 && p.reorder != 1) || p.block % 64 != 0 ||
+        p.block < 64 || p.block > 1024)
+        return MD_ERR_ARG;
+
+    const bool nl = p.mode == MD_NEIGHBOR_LIST;
+    const double r_list = p.r_cut + p.skin;
+    const double r_cell = nl ? r_list : p.r_cut;
+    double ncd = floor(p.L / r_cell);
+    if (ncd > 1290) ncd = 1290;  // keeps nc^3 within int32
+    int nc = (int)ncd;
+    if (nc >= 1 && p.L / nc < r_cell) --nc;
+    if (nc < 3) return MD_ERR_BOX_TOO_SMALL;
+
+    md_ctx* c = new (std::nothrow) md_ctx();
+    if (!c) return MD_ERR_ARG;
+    c->prm = p;
+    const int64_t n = p.n_atoms;
+    const int npad = (int)((n + 63) / 64 * 64);
+    int cap = 0;
+    if (nl) {
+        if (p.nl_capacity > 0) {
+            cap = p.nl_capacity;
+        } else {
+            const double rho = (double)n / (p.L * p.L * p.L);
+            const double mean = 4.0 / 3.0 * M_PI * r_list * r_list * r_list * rho;
+            cap = (int)ceil(mean + 10.0 * sqrt(mean) + 16.0);
+            cap = (cap + 7) / 8 * 8;
+        }
+        if (cap > n - 1) cap = (int)(n - 1 > 0 ? n - 1 : 1);
+    }
+    c->geo.nc = nc;
+    c->geo.n_cells = nc * nc * nc;
+    c->geo.nl_capacity = cap;
+    c->geo.n_pad = npad;
+    c->geo.cell_width = p.L / nc;
+
+    // workspace layout
+    const int64_t ncell = (int64_t)nc * nc * nc;
+    const int nblk_force = (int)((n + p.block - 1) / p.block);
+    const int ntile = (int)((ncell + 1023) / 1024);
+    const size_t fsz = p.precision == MD_FP64 ? sizeof(double) : sizeof(float);
+    size_t* b = c->bytes;
+    b[R_DEV] = sizeof(DevState);
+    b[R_CELL_COUNT] = sizeof(int32_t) * ncell;
+    b[R_CELL_START] = sizeof(int32_t) * (ncell + 1);
+    b[R_CELL_OF] = b[R_SLOT] = b[R_ORDER] = sizeof(int32_t) * n;
+    b[R_NL] = sizeof(int32_t) * (size_t)cap * npad;
+    b[R_NL_COUNT] = sizeof(int32_t) * npad;
+    b[R_XR] = b[R_YR] = b[R_ZR] = nl ? sizeof(double) * n : 0;
+    const size_t perm = p.reorder ? 1 : 0;
+    b[R_SX] = b[R_SY] = b[R_SZ] = b[R_SVX] = b[R_SVY] = b[R_SVZ] = perm * sizeof(double) * n;
+    b[R_SFX] = b[R_SFY] = b[R_SFZ] = perm * fsz * n;
+    b[R_SID] = b[R_SCELL] = perm * sizeof(int32_t) * n;
+    b[R_FPART] = sizeof(double) * 2 * nblk_force;
+    b[R_IPART] = sizeof(double) * 8 * kIntegrateGrid;
+    b[R_SCAN] = sizeof(int32_t) * 2 * (size_t)ntile;
+    b[R_HIST] = sizeof(md_record) * kHistCap;
+    size_t o = 0;
+    for (int r = 0; r < R_COUNT; ++r) {
+        c->off[r] = o;
+        o += align_up(b[r]);
+    }
+    c->ws_bytes = o;
+
+    KParams& k = c->kp;
+    memset(&k, 0, sizeof(k));
+    k.n = (int)n;
+    k.npad = npad;
+    k.nc = nc;
+    k.ncell = (int)ncell;
+    k.cap = cap;
+    k.potential = p.potential;
+    k.precision = p.precision;
+    k.mode = p.mode;
+    k.reorder = p.reorder;
+    k.newton3 = p.newton3;
+    k.L = p.L;
+    k.invL = 1.0 / p.L;
+    k.inv_w = (double)nc / p.L;
+    k.rc2 = p.r_cut * p.r_cut;
+    k.rl2 = r_list * r_list;
+    k.sig2 = p.sigma * p.sigma;
+    k.eps2 = 2.0 * p.eps;
+    k.eps48 = 48.0 * p.eps;
+    double shift = 0.0;
+    if (p.potential == MD_LJ_SHIFTED) {
+        const double sr2 = k.sig2 / k.rc2, sr6 = sr2 * sr2 * sr2;
+        shift = 4.0 * p.eps * (sr6 * sr6 - sr6);
+    }
+    k.half_shift = 0.5 * shift;
+    k.hdt = (0.5 * p.dt) / p.mass;
+    k.dt = p.dt;
+    k.disp_thr2 = (0.5 * p.skin) * (0.5 * p.skin);
+    k.mass = p.mass;
+    // the minimum-image shortcut of the force pass needs partners closer than L/2
+    const double reach = r_list + p.skin;
+    if (nl && 2.0 * reach < 0.999 * p.L) {
+        k.inner_lo = reach;
+        k.inner_hi = p.L - reach;
+    } else {
+        k.inner_lo = 1.0;
+        k.inner_hi = 0.0;  // empty range: always take the minimum image
+    }
+    k.nblk_force = nblk_force;
+    k.block = p.block;
+    *out = c;
+    return MD_OK;
+}
+
+extern "C" size_t md_workspace_bytes(const md_ctx* c) { return c ? c->ws_bytes : 0; }
+
+extern "C" md_status md_geometry(const md_ctx* c, md_grid* out)
+{
+    if (!c || !out) return MD_ERR_ARG;
+    *out = c->geo;
+    return MD_OK;
+}
+
+extern "C" md_status md_layout(const md_ctx* c, int32_t which, size_t* offset, size_t* count)
+{
+    if (!c || !offset || !count) return MD_ERR_ARG;
+    const int64_t n = c->prm.n_atoms;
+    switch (which) {
+        case MD_ARR_CELL_OF: *offset = c->off[R_CELL_OF]; *count = n; break;
+        case MD_ARR_CELL_START: *offset = c->off[R_CELL_START]; *count = c->geo.n_cells + 1; break;
+        case MD_ARR_CELL_ATOMS: *offset = c->off[R_ORDER]; *count = n; break;
+        case MD_ARR_NL:
+            *offset = c->off[R_NL];
+            *count = (size_t)c->geo.nl_capacity * c->geo.n_pad;
+            break;
+        case MD_ARR_NL_COUNT: *offset = c->off[R_NL_COUNT]; *count = n; break;
+        case MD_ARR_XREF:
+            if (c->prm.mode != MD_NEIGHBOR_LIST) return MD_ERR_ARG;
+            *offset = c->off[R_XR];  // x, y, z references follow at 256-byte-aligned pitch
+            *count = n;
+            break;
+        default: return MD_ERR_ARG;
+    }
+    return MD_OK;
+}
+
+extern "C" md_status md_bind(md_ctx* c, const md_buffers* bf, void* stream)
+{
+    if (!c || !bf) return MD_ERR_ARG;
+    if (!bf->x || !bf->y || !bf->z || !bf->vx || !bf->vy || !bf->vz || !bf->fx || !bf->fy ||
+        !bf->fz || !bf->id || !bf->workspace)
+        return MD_ERR_ARG;
+    if (((uintptr_t)bf->workspace) % kAlign != 0) return MD_ERR_ARG;
+    KParams& k = c->kp;
+    char* ws = static_cast<char*>(bf->workspace);
+    auto at = [&](int r) -> void* { return c->bytes[r] ? ws + c->off[r] : nullptr; };
+    k.x = bf->x; k.y = bf->y; k.z = bf->z;
+    k.vx = bf->vx; k.vy = bf->vy; k.vz = bf->vz;
+    k.fx = bf->fx; k.fy = bf->fy; k.fz = bf->fz;
+    k.id = bf->id;
+    k.dev = static_cast<DevState*>(at(R_DEV));
+    k.cell_count = static_cast<int32_t*>(at(R_CELL_COUNT));
+    k.cell_start = static_cast<int32_t*>(at(R_CELL_START));
+    k.cell_of = static_cast<int32_t*>(at(R_CELL_OF));
+    k.slot = static_cast<int32_t*>(at(R_SLOT));
+    k.order = static_cast<int32_t*>(at(R_ORDER));
+    k.nl = static_cast<int32_t*>(at(R_NL));
+    k.nl_count = static_cast<int32_t*>(at(R_NL_COUNT));
+    k.xr = static_cast<double*>(at(R_XR));
+    k.yr = static_cast<double*>(at(R_YR));
+    k.zr = static_cast<double*>(at(R_ZR));
+    k.sx = static_cast<double*>(at(R_SX));
+    k.sy = static_cast<double*>(at(R_SY));
+    k.sz = static_cast<double*>(at(R_SZ));
+    k.svx = static_cast<double*>(at(R_SVX));
+    k.svy = static_cast<double*>(at(R_SVY));
+    k.svz = static_cast<double*>(at(R_SVZ));
+    k.sfx = static_cast<double*>(at(R_SFX));
+    k.sfy = static_cast<double*>(at(R_SFY));
+    k.sfz = static_cast<double*>(at(R_SFZ));
+    k.sid = static_cast<int32_t*>(at(R_SID));
+    k.scell = static_cast<int32_t*>(at(R_SCELL));
+    k.fpart = static_cast<double*>(at(R_FPART));
+    k.ipart = static_cast<double*>(at(R_IPART));
+    k.scanpart = static_cast<int32_t*>(at(R_SCAN));
+    k.hist = static_cast<md_record*>(at(R_HIST));
+    c->stream = static_cast<hipStream_t>(stream);
+    c->bound = true;
+    c->cells_ok = c->nl_ok = c->forces_ok = false;
+    launch_clear(k, c->stream);
+    return launched();
+}
+
+extern "C" md_status md_build_cells(md_ctx* c)
+{
+    if (!c) return MD_ERR_ARG;
+    if (!c->bound) return MD_ERR_NOT_BOUND;
+    launch_cells(c->kp, 1, c->stream);
+    c->cells_ok = true;
+    c->nl_ok = false;
+    c->forces_ok = false;
+    return launched();
+}
+
+extern "C" md_status md_build_neighbors(md_ctx* c)
+{
+    if (!c) return MD_ERR_ARG;
+    if (!c->bound) return MD_ERR_NOT_BOUND;
+    if (c->prm.mode != MD_NEIGHBOR_LIST) return MD_ERR_ARG;
+    if (!c->cells_ok) return MD_ERR_STATE;
+    launch_neighbors(c->kp, 1, c->stream);
+    c->nl_ok = true;
+    return launched();
+}
+
+static void timed_forces(md_ctx* c)
+{
+    if (!c->timing) {
+        launch_forces(c->kp, c->stream);
+        return;
+    }
+    hipEvent_t ev[2];
+    for (int k = 0; k < 2; ++k) {
+        if (!c->ev_free.empty()) {
+            ev[k] = c->ev_free.back();
+            c->ev_free.pop_back();
+        } else {
+            (void)hipEventCreate(&ev[k]);
+        }
+    }
+    (void)hipEventRecord(ev[0], c->stream);
+    launch_forces(c->kp, c->stream);
+    (void)hipEventRecord(ev[1], c->stream);
+    c->ev_pending.push_back(ev[0]);
+    c->ev_pending.push_back(ev[1]);
+}
+
+static md_status fold_timing(md_ctx* c)
+{
+    if (c->ev_pending.empty()) return MD_OK;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MD_ERR_HIP;
+    for (size_t k = 0; k + 1 < c->ev_pending.size(); k += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev_pending[k], c->ev_pending[k + 1]) != hipSuccess)
+            return MD_ERR_HIP;
+        c->timed_ms += ms;
+        c->timed_launches += 1;
+        c->ev_free.push_back(c->ev_pending[k]);
+        c->ev_free.push_back(c->ev_pending[k + 1]);
+    }
+    c->ev_pending.clear();
+    return MD_OK;
+}
+
+extern "C" md_status md_forces(md_ctx* c)
+{
+    if (!c) return MD_ERR_ARG;
+    if (!c->bound) return MD_ERR_NOT_BOUND;
+    if (!c->cells_ok || (c->prm.mode == MD_NEIGHBOR_LIST && !c->nl_ok)) return MD_ERR_STATE;
+    timed_forces(c);
+    c->forces_ok = true;
+    return launched();
+}
+
+extern "C" md_status md_step(md_ctx* c, int32_t n_steps, int32_t record_every)
+{
+    if (!c || n_steps < 0 || record_every < 0) return MD_ERR_ARG;
+    if (!c->bound) return MD_ERR_NOT_BOUND;
+    if (!c->forces_ok) return MD_ERR_STATE;
+    if (n_steps == 0) return MD_OK;
+    KParams k = c->kp;
+    const bool nl = c->prm.mode == MD_NEIGHBOR_LIST;
+    k.record_every = record_every;
+    for (int32_t s = 0; s < n_steps; ++s) {
+        launch_integrate(k, s == 0 ? 0 : 1, c->stream);
+        launch_cells(k, 0, c->stream);
+        if (nl) launch_neighbors(k, 0, c->stream);
+        timed_forces(c);
+        if (c->timing && c->ev_pending.size() >= 8192) {
+            md_status st = fold_timing(c);
+            if (st != MD_OK) return st;
+        }
+    }
+    launch_integrate(k, 2, c->stream);
+    return launched();
+}
+
+extern "C" md_status md_reduce(md_ctx* c, md_observables* out)
+{
+    if (!c || !out) return MD_ERR_ARG;
+    if (!c->bound) return MD_ERR_NOT_BOUND;
+    launch_observe(c->kp, c->stream);
+    md_status st = launched();
+    if (st != MD_OK) return st;
+    DevState d;
+    if (hipMemcpyAsync(&d, c->kp.dev, sizeof(d), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        return MD_ERR_HIP;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MD_ERR_HIP;
+    const double n = c->prm.n_atoms;
+    const double V = c->prm.L * c->prm.L * c->prm.L;
+    memset(out, 0, sizeof(*out));
+    out->U = d.obs[0];
+    out->K = d.obs[1];
+    out->W = d.obs[2];
+    out->P[0] = d.obs[3];
+    out->P[1] = d.obs[4];
+    out->P[2] = d.obs[5];
+    out->T = n > 1 ? 2.0 * out->K / (3.0 * (n - 1)) : 0.0;
+    out->pressure = (2.0 * out->K + out->W) / (3.0 * V);
+    out->dmax = sqrt(d.dmax2);
+    out->step = d.step;
+    out->n_rebuilds = d.n_rebuilds;
+    out->max_occupancy = d.max_occ;
+    out->max_nl = d.max_nl;
+    out->flags = d.flags;
+    if (d.flags & MD_FLAG_NL_OVERFLOW) return MD_ERR_NL_OVERFLOW;
+    if (d.flags & MD_FLAG_NONFINITE) return MD_ERR_NONFINITE;
+    return MD_OK;
+}
+
+extern "C" md_status md_history(md_ctx* c, md_record* out, int32_t max_records, int32_t* n_out)
+{
+    if (!c || !n_out || max_records < 0 || (max_records > 0 && !out)) return MD_ERR_ARG;
+    if (!c->bound) return MD_ERR_NOT_BOUND;
+    DevState d;
+    if (hipMemcpyAsync(&d, c->kp.dev, sizeof(d), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        return MD_ERR_HIP;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MD_ERR_HIP;
+    std::vector<md_record> ring(kHistCap);
+    if (hipMemcpy(ring.data(), c->kp.hist, sizeof(md_record) * kHistCap,
+                  hipMemcpyDeviceToHost) != hipSuccess)
+        return MD_ERR_HIP;
+    const int64_t total = d.hist_count;
+    const int64_t avail = total < kHistCap ? total : kHistCap;
+    const int64_t take = avail < max_records ? avail : max_records;
+    const int64_t first = total - avail;  // oldest record still held
+    for (int64_t r = 0; r < take; ++r) out[r] = ring[(first + r) % kHistCap];
+    *n_out = (int32_t)take;
+    return MD_OK;
+}
+
+extern "C" md_status md_set_timing(md_ctx* c, int32_t enable)
+{
+    if (!c) return MD_ERR_ARG;
+    md_status st = fold_timing(c);
+    c->timing = enable != 0;
+    c->timed_ms = 0.0;
+    c->timed_launches = 0;
+    return st;
+}
+
+extern "C" md_status md_get_timing(md_ctx* c, double* total_ms, int64_t* launches)
+{
+    if (!c || !total_ms || !launches) return MD_ERR_ARG;
+    md_status st = fold_timing(c);
+    *total_ms = c->timed_ms;
+    *launches = c->timed_launches;
+    return st;
+}
+
+extern "C" void md_destroy(md_ctx* c)
+{
+    if (!c) return;
+    if (!c->ev_pending.empty()) (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ev_pending) (void)hipEventDestroy(e);
+    delete c;
+}

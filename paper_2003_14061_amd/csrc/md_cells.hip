@@ -1,0 +1,282 @@
+// md_cells.hip -- steps N1-N4 of section 2.3 as a counting sort, plus the
+// reorder of section 2.4 item (4) done on the GPU with the prefix-scan the
+// paper names as the alternative to its CPU pass.
+//
+//   k_bin        N1/N2: cell of every atom; atomic occupancy count gives the
+//                atom's (unordered) rank in its cell
+//   k_scan_*     N3/N4: exclusive scan of the counts -> cell_start, and the
+//                largest occupancy; clears the counts for the next build
+//   k_scatter    slots grouped by cell
+//   k_cellsort   inside each cell, ascending permanent id (the paper leaves
+//                the order open; a fixed order makes the list reproducible)
+//   k_permute /  with reorder on: atom data permuted into cell order
+//   k_copyback
+//
+// Every kernel returns at once unless the rebuild flag is set (or the call
+// forces the build), so a step's launch sequence is fixed.
+#include "md_device.h"
+
+namespace md {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 4;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+__device__ __forceinline__ bool rebuild_on(const KParams& p, int force)
+{
+    return force || p.dev->rebuild;
+}
+
+__global__ void k_clear(KParams p)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < p.ncell) p.cell_count[i] = 0;
+    if (i == 0) {
+        DevState* d = p.dev;
+        d->step = 0;
+        d->n_rebuilds = 0;
+        d->hist_count = 0;
+        d->dmax2 = 0.0;
+        d->rebuild = 0;
+        d->blocks_done = 0;
+        d->flags = 0;
+        d->max_occ = 0;
+        d->max_nl = 0;
+        for (int k = 0; k < 8; ++k) d->obs[k] = 0.0;
+    }
+}
+
+__global__ void k_bin(KParams p, int force)
+{
+    if (!rebuild_on(p, force)) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n) return;
+    int c = cell_of_pos(p.x[i], p.y[i], p.z[i], p);
+    p.cell_of[i] = c;
+    p.slot[i] = atomicAdd(&p.cell_count[c], 1);
+}
+
+// Inclusive scan across a wave64.
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        int t = __shfl_up(v, o, kWave);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread across the workgroup (kScanThreads).
+__device__ __forceinline__ int block_excl_scan(int v, int* total)
+{
+    __shared__ int wsum[kScanThreads / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    int inc = wave_incl_scan(v);
+    if (lane == kWave - 1) wsum[wid] = inc;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / kWave; ++w) {
+        if (w < wid) off += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+// Per tile: sum and max of the counts.
+__global__ __launch_bounds__(kScanThreads) void k_scan_partial(KParams p, int force)
+{
+    if (!rebuild_on(p, force)) return;
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+    int s = 0, m = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        int c = base + k;
+        int v = c < p.ncell ? p.cell_count[c] : 0;
+        s += v;
+        m = v > m ? v : m;
+    }
+    s = wave_sum(s);
+    m = wave_max(m);
+    __shared__ int ss[kScanThreads / kWave], sm[kScanThreads / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (lane == 0) {
+        ss[wid] = s;
+        sm[wid] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ts = 0, tm = 0;
+        for (int w = 0; w < kScanThreads / kWave; ++w) {
+            ts += ss[w];
+            tm = sm[w] > tm ? sm[w] : tm;
+        }
+        p.scanpart[2 * blockIdx.x] = ts;
+        p.scanpart[2 * blockIdx.x + 1] = tm;
+    }
+}
+
+// One workgroup: exclusive scan of the tile sums (in place), largest occupancy.
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(KParams p, int ntile, int force)
+{
+    if (!rebuild_on(p, force)) return;
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    int m = 0;
+    for (int base = 0; base < ntile; base += kScanThreads) {
+        int t = base + threadIdx.x;
+        int v = t < ntile ? p.scanpart[2 * t] : 0;
+        int mv = t < ntile ? p.scanpart[2 * t + 1] : 0;
+        m = mv > m ? mv : m;
+        int total;
+        int ex = block_excl_scan(v, &total);
+        if (t < ntile) p.scanpart[2 * t] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += total;
+        __syncthreads();
+    }
+    m = wave_max(m);
+    __shared__ int sm[kScanThreads / kWave];
+    if ((threadIdx.x & (kWave - 1)) == 0) sm[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tm = 0;
+        for (int w = 0; w < kScanThreads / kWave; ++w) tm = sm[w] > tm ? sm[w] : tm;
+        p.dev->max_occ = tm;
+        p.dev->max_nl = 0;
+        p.cell_start[p.ncell] = carry;
+    }
+}
+
+// Per tile: local exclusive scan plus the tile offset -> cell_start; clear counts.
+__global__ __launch_bounds__(kScanThreads) void k_scan_final(KParams p, int force)
+{
+    if (!rebuild_on(p, force)) return;
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+    int v[kScanPer], s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        int c = base + k;
+        v[k] = c < p.ncell ? p.cell_count[c] : 0;
+        s += v[k];
+    }
+    int total;
+    int ex = block_excl_scan(s, &total) + p.scanpart[2 * blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        int c = base + k;
+        if (c < p.ncell) {
+            p.cell_start[c] = ex;
+            p.cell_count[c] = 0;
+        }
+        ex += v[k];
+    }
+}
+
+__global__ void k_scatter(KParams p, int force)
+{
+    if (!rebuild_on(p, force)) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n) return;
+    p.order[p.cell_start[p.cell_of[i]] + p.slot[i]] = i;
+}
+
+// Insertion sort of each cell's slots by permanent id (cells hold tens of atoms).
+__global__ void k_cellsort(KParams p, int force)
+{
+    if (!rebuild_on(p, force)) return;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= p.ncell) return;
+    const int a = p.cell_start[c], b = p.cell_start[c + 1];
+    for (int k = a + 1; k < b; ++k) {
+        int s = p.order[k];
+        int key = p.id[s];
+        int q = k - 1;
+        while (q >= a) {
+            int t = p.order[q];
+            if (p.id[t] <= key) break;
+            p.order[q + 1] = t;
+            --q;
+        }
+        p.order[q + 1] = s;
+    }
+}
+
+template <typename F>
+__global__ void k_permute(KParams p, int force)
+{
+    if (!rebuild_on(p, force)) return;
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= p.n) return;
+    const int o = p.order[q];
+    p.sx[q] = p.x[o];
+    p.sy[q] = p.y[o];
+    p.sz[q] = p.z[o];
+    p.svx[q] = p.vx[o];
+    p.svy[q] = p.vy[o];
+    p.svz[q] = p.vz[o];
+    reinterpret_cast<F*>(p.sfx)[q] = static_cast<const F*>(p.fx)[o];
+    reinterpret_cast<F*>(p.sfy)[q] = static_cast<const F*>(p.fy)[o];
+    reinterpret_cast<F*>(p.sfz)[q] = static_cast<const F*>(p.fz)[o];
+    p.sid[q] = p.id[o];
+    p.scell[q] = p.cell_of[o];
+}
+
+template <typename F>
+__global__ void k_copyback(KParams p, int force)
+{
+    if (!rebuild_on(p, force)) return;
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= p.n) return;
+    p.x[q] = p.sx[q];
+    p.y[q] = p.sy[q];
+    p.z[q] = p.sz[q];
+    p.vx[q] = p.svx[q];
+    p.vy[q] = p.svy[q];
+    p.vz[q] = p.svz[q];
+    static_cast<F*>(p.fx)[q] = reinterpret_cast<const F*>(p.sfx)[q];
+    static_cast<F*>(p.fy)[q] = reinterpret_cast<const F*>(p.sfy)[q];
+    static_cast<F*>(p.fz)[q] = reinterpret_cast<const F*>(p.sfz)[q];
+    p.id[q] = p.sid[q];
+    p.cell_of[q] = p.scell[q];
+    p.order[q] = q;
+}
+
+static inline unsigned nblocks(int64_t n, int b)
+{
+    return (unsigned)((n + b - 1) / b);
+}
+
+void launch_clear(const KParams& p, hipStream_t s)
+{
+    int n = p.ncell > 1 ? p.ncell : 1;
+    hipLaunchKernelGGL(k_clear, dim3(nblocks(n, 256)), dim3(256), 0, s, p);
+}
+
+void launch_cells(const KParams& p, int force, hipStream_t s)
+{
+    const int b = p.block;
+    const int ntile = (int)nblocks(p.ncell, kScanTile);
+    hipLaunchKernelGGL(k_bin, dim3(nblocks(p.n, b)), dim3(b), 0, s, p, force);
+    hipLaunchKernelGGL(k_scan_partial, dim3(ntile), dim3(kScanThreads), 0, s, p, force);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, p, ntile, force);
+    hipLaunchKernelGGL(k_scan_final, dim3(ntile), dim3(kScanThreads), 0, s, p, force);
+    hipLaunchKernelGGL(k_scatter, dim3(nblocks(p.n, b)), dim3(b), 0, s, p, force);
+    hipLaunchKernelGGL(k_cellsort, dim3(nblocks(p.ncell, 256)), dim3(256), 0, s, p, force);
+    if (p.reorder) {
+        if (p.precision == MD_FP64) {
+            hipLaunchKernelGGL(k_permute<double>, dim3(nblocks(p.n, b)), dim3(b), 0, s, p, force);
+            hipLaunchKernelGGL(k_copyback<double>, dim3(nblocks(p.n, b)), dim3(b), 0, s, p, force);
+        } else {
+            hipLaunchKernelGGL(k_permute<float>, dim3(nblocks(p.n, b)), dim3(b), 0, s, p, force);
+            hipLaunchKernelGGL(k_copyback<float>, dim3(nblocks(p.n, b)), dim3(b), 0, s, p, force);
+        }
+    }
+}
+
+}  // namespace md

@@ -1,0 +1,161 @@
+// md_device.h -- device helpers shared by the libmd kernels.
+//
+// The arithmetic that decides membership (cells, neighbor list, cutoff,
+// rebuild) is written so that it rounds exactly as specified in md.h:
+//   minimum image   d - L*rint(d/L), with 1/L formed on the host
+//   squared length  dx*dx then two fused multiply-adds
+//   cell index      floor(x * (nc/L)) clamped to nc-1
+//   kick / drift    v + (dt/2m)*f and x + dt*v, multiply then add
+// Contraction is switched off inside those helpers so the compiler cannot
+// fuse them differently.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "md_internal.h"
+
+namespace md {
+
+__device__ __forceinline__ double minimg(double d, double L, double invL)
+{
+#pragma clang fp contract(off)
+    return d - L * rint(d * invL);
+}
+
+__device__ __forceinline__ double dist2(double dx, double dy, double dz)
+{
+#pragma clang fp contract(off)
+    return __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+}
+
+__device__ __forceinline__ double wrap(double x, double L)
+{
+#pragma clang fp contract(off)
+    if (x >= L) {
+        x -= L;
+    } else if (x < 0.0) {
+        x += L;
+        if (x >= L) x = 0.0;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int cell_1d(double x, double inv_w, int nc)
+{
+#pragma clang fp contract(off)
+    int c = (int)floor(x * inv_w);
+    c = c < 0 ? 0 : c;
+    return c > nc - 1 ? nc - 1 : c;
+}
+
+__device__ __forceinline__ int cell_of_pos(double x, double y, double z, const KParams& p)
+{
+    int cx = cell_1d(x, p.inv_w, p.nc);
+    int cy = cell_1d(y, p.inv_w, p.nc);
+    int cz = cell_1d(z, p.inv_w, p.nc);
+    return (cz * p.nc + cy) * p.nc + cx;
+}
+
+__device__ __forceinline__ int wrap_cell(int c, int nc)
+{
+    return c < 0 ? c + nc : (c >= nc ? c - nc : c);
+}
+
+__device__ __forceinline__ double kick(double v, double hdt, double f)
+{
+#pragma clang fp contract(off)
+    return v + hdt * f;
+}
+
+__device__ __forceinline__ double drift(double x, double dt, double v)
+{
+#pragma clang fp contract(off)
+    return x + dt * v;
+}
+
+// Reciprocal: hardware estimate refined by two Newton-Raphson steps
+// y <- y + y(1 - a y), each roughly squaring the relative error.
+__device__ __forceinline__ double recip(double a)
+{
+    double y = __builtin_amdgcn_rcp(a);
+    double e = __builtin_fma(-a, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-a, y, 1.0);
+    return __builtin_fma(y, e, y);
+}
+
+// ---- wave64 and workgroup reductions (fixed order: deterministic) ----
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o, kWave);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+// Sum K values across the workgroup; the result is valid in thread 0.
+// red must hold (blockDim.x / 64) * K doubles of LDS.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* red)
+{
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[wid * K + k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double t = 0.0;
+            for (int w = 0; w < nw; ++w) t += red[w * K + k];
+            v[k] = t;
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ double load_coherent(const double* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int load_coherent(const int* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Last-workgroup-done (the paper's completion scheme, section 2.3): every
+// workgroup publishes its partial, bumps a counter, and the one that sees
+// the final count finishes the reduction.  Returns true in every thread of
+// that last workgroup.
+__device__ __forceinline__ bool last_block(DevState* dev)
+{
+    __shared__ int is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned t = atomicAdd(&dev->blocks_done, 1u);
+        is_last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (is_last) __threadfence();
+    return is_last != 0;
+}
+
+}  // namespace md

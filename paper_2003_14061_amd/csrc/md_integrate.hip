@@ -1,0 +1,226 @@
+// md_integrate.hip -- leapfrog integration and the global reductions.
+//
+// The leapfrog (section 4.3) is kick-drift-kick with two separate half
+// kicks.  The second half kick of step s and the first of step s+1 use the
+// same force, so one pass over the atoms does both (in that order, each
+// rounded on its own) and measures the kinetic energy and momentum at the
+// full step in between.  The drift wraps positions into [0, L) and measures
+// each atom's displacement from the list reference; the largest one decides
+// whether the cells and list are rebuilt before the next force pass (the
+// paper refreshes "at intervals of several time steps", section 2.3, from a
+// bound on the maximal velocity; here the bound is the displacement itself).
+//
+// Reductions (section 2.3, F2 and the completion scheme that follows it):
+// each workgroup writes its partial sums, and the last workgroup to finish,
+// found with an atomic counter and a memory fence, sums all partials in
+// workgroup order and publishes the result on the device.
+#include "md_device.h"
+
+namespace md {
+
+constexpr int kIntThreads = 256;
+
+// Sum partials [nb][stride] (component k) over workgroups in a fixed order.
+__device__ double finish_sum(const double* part, int nb, int stride, int k, double* red)
+{
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) v[0] += load_coherent(part + b * stride + k);
+    block_sum<1>(v, red);
+    return v[0];
+}
+
+__device__ double finish_max(const double* part, int nb, int stride, int k, double* red)
+{
+    double m = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        double t = load_coherent(part + b * stride + k);
+        m = t > m ? t : m;
+    }
+    m = wave_max(m);
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) red[wid] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)blockDim.x / kWave; ++w) t = red[w] > t ? red[w] : t;
+        m = t;
+    }
+    __syncthreads();
+    return m;
+}
+
+// Finish a completed step: sum U, W (last force pass) and K, P (this
+// kernel's partials) and append to the history when requested.
+__device__ void record_step(const KParams& p, double* red)
+{
+    const double U = finish_sum(p.fpart, p.nblk_force, 2, 0, red);
+    const double W = finish_sum(p.fpart, p.nblk_force, 2, 1, red);
+    const double K = finish_sum(p.ipart, gridDim.x, 8, 0, red);
+    const double Px = finish_sum(p.ipart, gridDim.x, 8, 1, red);
+    const double Py = finish_sum(p.ipart, gridDim.x, 8, 2, red);
+    const double Pz = finish_sum(p.ipart, gridDim.x, 8, 3, red);
+    if (threadIdx.x == 0) {
+        DevState* d = p.dev;
+        d->step += 1;
+        d->obs[0] = U;
+        d->obs[1] = 0.5 * p.mass * K;
+        d->obs[2] = W;
+        d->obs[3] = p.mass * Px;
+        d->obs[4] = p.mass * Py;
+        d->obs[5] = p.mass * Pz;
+        d->obs[6] = d->dmax2;
+        if (p.record_every > 0 && d->step % p.record_every == 0) {
+            md_record* r = p.hist + (d->hist_count % kHistCap);
+            r->step = d->step;
+            r->U = U;
+            r->K = 0.5 * p.mass * K;
+            r->W = W;
+            r->P[0] = p.mass * Px;
+            r->P[1] = p.mass * Py;
+            r->P[2] = p.mass * Pz;
+            r->dmax = sqrt(d->dmax2);
+            r->rebuilt = d->rebuild;
+            r->pad = 0;
+            d->hist_count += 1;
+        }
+    }
+}
+
+template <typename F>
+__global__ __launch_bounds__(kIntThreads) void k_integrate(KParams p, int phase)
+{
+    __shared__ double red[(kIntThreads / kWave) * 5];
+    const F* fx = static_cast<const F*>(p.fx);
+    const F* fy = static_cast<const F*>(p.fy);
+    const F* fz = static_cast<const F*>(p.fz);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // v^2, Px, Py, Pz, (unused)
+    double dmax2 = 0.0;
+    const int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += stride) {
+        const double gx = (double)fx[i], gy = (double)fy[i], gz = (double)fz[i];
+        double vx = p.vx[i], vy = p.vy[i], vz = p.vz[i];
+        if (phase >= 1) {  // second half kick of the finished step
+            vx = kick(vx, p.hdt, gx);
+            vy = kick(vy, p.hdt, gy);
+            vz = kick(vz, p.hdt, gz);
+            acc[0] += (vx * vx + vy * vy) + vz * vz;
+            acc[1] += vx;
+            acc[2] += vy;
+            acc[3] += vz;
+        }
+        if (phase <= 1) {  // first half kick and drift of the next step
+            vx = kick(vx, p.hdt, gx);
+            vy = kick(vy, p.hdt, gy);
+            vz = kick(vz, p.hdt, gz);
+            const double x = wrap(drift(p.x[i], p.dt, vx), p.L);
+            const double y = wrap(drift(p.y[i], p.dt, vy), p.L);
+            const double z = wrap(drift(p.z[i], p.dt, vz), p.L);
+            p.x[i] = x;
+            p.y[i] = y;
+            p.z[i] = z;
+            if (p.mode == MD_NEIGHBOR_LIST) {
+                const double d2 = dist2(minimg(x - p.xr[i], p.L, p.invL),
+                                        minimg(y - p.yr[i], p.L, p.invL),
+                                        minimg(z - p.zr[i], p.L, p.invL));
+                dmax2 = d2 > dmax2 ? d2 : dmax2;
+            }
+        }
+        p.vx[i] = vx;
+        p.vy[i] = vy;
+        p.vz[i] = vz;
+    }
+    block_sum<5>(acc, red);
+    dmax2 = wave_max(dmax2);
+    {
+        const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+        if (lane == 0) red[wid] = dmax2;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < (int)blockDim.x / kWave; ++w) t = red[w] > t ? red[w] : t;
+            dmax2 = t;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double* o = p.ipart + 8 * blockIdx.x;
+        o[0] = acc[0];
+        o[1] = acc[1];
+        o[2] = acc[2];
+        o[3] = acc[3];
+        o[4] = dmax2;
+    }
+    if (!last_block(p.dev)) return;
+    if (phase >= 1) record_step(p, red);
+    if (phase <= 1) {
+        const double m = finish_max(p.ipart, gridDim.x, 8, 4, red);
+        if (threadIdx.x == 0) {
+            DevState* d = p.dev;
+            d->dmax2 = m;
+            const int rb = p.mode == MD_CELLS_ONLY ? 1 : (m > p.disp_thr2 ? 1 : 0);
+            d->rebuild = rb;
+            if (rb) d->n_rebuilds += 1;
+        }
+    }
+    if (threadIdx.x == 0) p.dev->blocks_done = 0;
+}
+
+// Observables of the current state: K and P from the velocities, U and W
+// from the partials of the last force pass.
+__global__ __launch_bounds__(kIntThreads) void k_observe(KParams p)
+{
+    __shared__ double red[(kIntThreads / kWave) * 4];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += stride) {
+        const double vx = p.vx[i], vy = p.vy[i], vz = p.vz[i];
+        acc[0] += (vx * vx + vy * vy) + vz * vz;
+        acc[1] += vx;
+        acc[2] += vy;
+        acc[3] += vz;
+    }
+    block_sum<4>(acc, red);
+    if (threadIdx.x == 0) {
+        double* o = p.ipart + 8 * blockIdx.x;
+        for (int k = 0; k < 4; ++k) o[k] = acc[k];
+    }
+    if (!last_block(p.dev)) return;
+    const double U = finish_sum(p.fpart, p.nblk_force, 2, 0, red);
+    const double W = finish_sum(p.fpart, p.nblk_force, 2, 1, red);
+    double s[4];
+    for (int k = 0; k < 4; ++k) s[k] = finish_sum(p.ipart, gridDim.x, 8, k, red);
+    if (threadIdx.x == 0) {
+        DevState* d = p.dev;
+        d->obs[0] = U;
+        d->obs[1] = 0.5 * p.mass * s[0];
+        d->obs[2] = W;
+        d->obs[3] = p.mass * s[1];
+        d->obs[4] = p.mass * s[2];
+        d->obs[5] = p.mass * s[3];
+        d->obs[6] = d->dmax2;
+        d->blocks_done = 0;
+    }
+}
+
+static unsigned grid_for(int n)
+{
+    int g = (n + kIntThreads - 1) / kIntThreads;
+    return (unsigned)(g < kIntegrateGrid ? (g > 0 ? g : 1) : kIntegrateGrid);
+}
+
+void launch_integrate(const KParams& p, int phase, hipStream_t s)
+{
+    const dim3 g(grid_for(p.n)), t(kIntThreads);
+    if (p.precision == MD_FP64)
+        hipLaunchKernelGGL(k_integrate<double>, g, t, 0, s, p, phase);
+    else
+        hipLaunchKernelGGL(k_integrate<float>, g, t, 0, s, p, phase);
+}
+
+void launch_observe(const KParams& p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_observe, dim3(grid_for(p.n)), dim3(kIntThreads), 0, s, p);
+}
+
+}  // namespace md

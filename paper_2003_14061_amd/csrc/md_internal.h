@@ -1,0 +1,70 @@
+// md_internal.h -- shared definitions of libmd (not part of the public ABI).
+//
+// Kernel parameters travel by value as one kernarg block (the paper keeps
+// its unvarying pointers and constants in one small structure in constant
+// memory, section 2.4 item (2); a kernarg block is the gfx950 equivalent).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/md.h"
+
+namespace md {
+
+constexpr int kWave = 64;
+constexpr int kHistCap = 4096;     // history records kept on the device
+constexpr int kIntegrateGrid = 2048;  // fixed grid of the grid-stride per-atom kernels
+
+// Device-resident control block (first bytes of the workspace).
+struct DevState {
+    int64_t  step;         // steps completed since bind
+    int64_t  n_rebuilds;   // rebuilds triggered by the displacement rule
+    int64_t  hist_count;   // records appended to the history
+    double   dmax2;        // largest squared displacement at the last drift
+    int32_t  rebuild;      // 1: the chain after this drift must rebuild
+    uint32_t blocks_done;  // last-workgroup-done counter
+    int32_t  flags;        // MD_FLAG_* latched bits
+    int32_t  max_occ;      // largest cell occupancy at the last build
+    int32_t  max_nl;       // longest list at the last build
+    int32_t  pad[3];
+    double   obs[8];       // U, K, W, Px, Py, Pz, dmax2, spare (md_reduce)
+};
+
+// Everything a kernel needs.
+struct KParams {
+    // sizes
+    int32_t n, npad, nc, ncell, cap, potential, precision, mode, reorder, newton3;
+    // constants (all formed once on the host)
+    double L, invL, inv_w, rc2, rl2, sig2, eps2, eps48, half_shift, hdt, dt, disp_thr2, mass;
+    double inner_lo, inner_hi;  // atoms with every coordinate in [lo, hi] need no minimum image
+    // state (caller-owned)
+    double *x, *y, *z, *vx, *vy, *vz;
+    void *fx, *fy, *fz;
+    int32_t* id;
+    // workspace arrays
+    DevState* dev;
+    int32_t *cell_count, *cell_start, *cell_of, *slot, *order;
+    int32_t *nl, *nl_count;
+    double *xr, *yr, *zr;
+    double *sx, *sy, *sz, *svx, *svy, *svz, *sfx, *sfy, *sfz;  // permutation scratch
+    int32_t *sid, *scell;
+    double *fpart;    // force-pass partials [nblk_force][2]: U, W
+    double *ipart;    // per-atom kernel partials [kIntegrateGrid][8]
+    int32_t *scanpart;  // scan partials [nscan][2]: sum, max
+    md_record* hist;
+    int32_t nblk_force;
+    int32_t block;
+    int32_t record_every;  // history interval of the running md_step (0 = none)
+};
+
+// Host-side launchers (one translation unit per stage).
+void launch_clear(const KParams& p, hipStream_t s);
+void launch_cells(const KParams& p, int force, hipStream_t s);
+void launch_neighbors(const KParams& p, int force, hipStream_t s);
+void launch_forces(const KParams& p, hipStream_t s);
+// phase 0: kick + drift; 1: kick, record, kick + drift; 2: kick, record
+void launch_integrate(const KParams& p, int phase, hipStream_t s);
+void launch_observe(const KParams& p, hipStream_t s);
+
+}  // namespace md

@@ -1,0 +1,339 @@
+"""Python binding of libmd (the C ABI in include/md.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of libmd.so.  PyTorch provides the device memory (tensors) and the stream.
+There is no CPU fallback: if libmd.so is missing or no GPU is present the
+calls raise.
+
+Low-level functions carry the C names (md_init, md_bind, md_build_cells,
+md_build_neighbors, md_forces, md_step, md_reduce, ...).  ``Simulation``
+owns the tensors of one system and calls them in order.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmd.so")
+
+MD_OK = 0
+MD_LJ_SHIFTED, MD_LJ_TRUNC = 0, 1
+MD_FP64, MD_FP32_MIXED = 0, 1
+MD_CELLS_ONLY, MD_NEIGHBOR_LIST = 0, 1
+MD_ARR_CELL_OF, MD_ARR_CELL_START, MD_ARR_CELL_ATOMS, MD_ARR_NL, MD_ARR_NL_COUNT, MD_ARR_XREF = range(6)
+
+EXPORTS = ("md_init", "md_workspace_bytes", "md_geometry", "md_layout", "md_bind",
+           "md_build_cells", "md_build_neighbors", "md_forces", "md_step", "md_reduce",
+           "md_history", "md_set_timing", "md_get_timing", "md_destroy", "md_status_str")
+
+
+class MDError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__(f"{where}: {status_str(status)} ({status})")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32), ("potential", C.c_int32), ("L", C.c_double),
+                ("eps", C.c_double), ("sigma", C.c_double), ("mass", C.c_double),
+                ("r_cut", C.c_double), ("skin", C.c_double), ("dt", C.c_double),
+                ("precision", C.c_int32), ("mode", C.c_int32), ("newton3", C.c_int32),
+                ("nl_capacity", C.c_int32), ("reorder", C.c_int32), ("block", C.c_int32)]
+
+
+class Buffers(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz",
+                                           "id", "workspace")]
+
+
+class Grid(C.Structure):
+    _fields_ = [("nc", C.c_int32), ("n_cells", C.c_int32), ("nl_capacity", C.c_int32),
+                ("n_pad", C.c_int32), ("cell_width", C.c_double)]
+
+
+class Observables(C.Structure):
+    _fields_ = [("U", C.c_double), ("K", C.c_double), ("W", C.c_double),
+                ("P", C.c_double * 3), ("T", C.c_double), ("pressure", C.c_double),
+                ("dmax", C.c_double), ("step", C.c_int64), ("n_rebuilds", C.c_int64),
+                ("max_occupancy", C.c_int32), ("max_nl", C.c_int32), ("flags", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+class Record(C.Structure):
+    _fields_ = [("step", C.c_int64), ("U", C.c_double), ("K", C.c_double), ("W", C.c_double),
+                ("P", C.c_double * 3), ("dmax", C.c_double), ("rebuilt", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libmd.so; raise if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    sig = {
+        "md_init": (C.c_int, [C.POINTER(Params), C.POINTER(P)]),
+        "md_workspace_bytes": (C.c_size_t, [P]),
+        "md_geometry": (C.c_int, [P, C.POINTER(Grid)]),
+        "md_layout": (C.c_int, [P, C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+        "md_bind": (C.c_int, [P, C.POINTER(Buffers), P]),
+        "md_build_cells": (C.c_int, [P]),
+        "md_build_neighbors": (C.c_int, [P]),
+        "md_forces": (C.c_int, [P]),
+        "md_step": (C.c_int, [P, C.c_int32, C.c_int32]),
+        "md_reduce": (C.c_int, [P, C.POINTER(Observables)]),
+        "md_history": (C.c_int, [P, C.POINTER(Record), C.c_int32, C.POINTER(C.c_int32)]),
+        "md_set_timing": (C.c_int, [P, C.c_int32]),
+        "md_get_timing": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "md_destroy": (None, [P]),
+        "md_status_str": (C.c_char_p, [C.c_int32]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = L
+    return L
+
+
+def status_str(st):
+    return lib().md_status_str(int(st)).decode()
+
+
+def _check(st, where):
+    if st != MD_OK:
+        raise MDError(st, where)
+
+
+# ---- C-named wrappers ------------------------------------------------------
+
+def md_init(params: Params):
+    ctx = C.c_void_p()
+    _check(lib().md_init(C.byref(params), C.byref(ctx)), "md_init")
+    return ctx
+
+
+def md_workspace_bytes(ctx) -> int:
+    return int(lib().md_workspace_bytes(ctx))
+
+
+def md_geometry(ctx) -> Grid:
+    g = Grid()
+    _check(lib().md_geometry(ctx, C.byref(g)), "md_geometry")
+    return g
+
+
+def md_layout(ctx, which):
+    off, cnt = C.c_size_t(), C.c_size_t()
+    _check(lib().md_layout(ctx, int(which), C.byref(off), C.byref(cnt)), "md_layout")
+    return off.value, cnt.value
+
+
+def md_bind(ctx, bufs: Buffers, stream_handle: int):
+    _check(lib().md_bind(ctx, C.byref(bufs), C.c_void_p(stream_handle)), "md_bind")
+
+
+def md_build_cells(ctx):
+    _check(lib().md_build_cells(ctx), "md_build_cells")
+
+
+def md_build_neighbors(ctx):
+    _check(lib().md_build_neighbors(ctx), "md_build_neighbors")
+
+
+def md_forces(ctx):
+    _check(lib().md_forces(ctx), "md_forces")
+
+
+def md_step(ctx, n_steps: int, record_every: int = 0):
+    _check(lib().md_step(ctx, int(n_steps), int(record_every)), "md_step")
+
+
+def md_reduce(ctx, check: bool = True) -> Observables:
+    o = Observables()
+    st = lib().md_reduce(ctx, C.byref(o))
+    if check:
+        _check(st, "md_reduce")
+    return o
+
+
+def md_history(ctx, max_records: int = 4096):
+    buf = (Record * max_records)()
+    n = C.c_int32()
+    _check(lib().md_history(ctx, buf, max_records, C.byref(n)), "md_history")
+    return list(buf[: n.value])
+
+
+def md_set_timing(ctx, enable: bool):
+    _check(lib().md_set_timing(ctx, int(bool(enable))), "md_set_timing")
+
+
+def md_get_timing(ctx):
+    ms, n = C.c_double(), C.c_int64()
+    _check(lib().md_get_timing(ctx, C.byref(ms), C.byref(n)), "md_get_timing")
+    return ms.value, n.value
+
+
+def md_destroy(ctx):
+    lib().md_destroy(ctx)
+
+
+# ---- one system ------------------------------------------------------------
+
+class Simulation:
+    """One periodic system on one GPU: tensors, context, and the calls in order.
+
+    pos, vel: (N, 3) arrays in id order.  All per-atom tensors are float64
+    except the forces in FP32-mixed mode (float32).
+    """
+
+    def __init__(self, pos, vel, L, *, r_cut, dt, skin=0.3, eps=1.0, sigma=1.0, mass=1.0,
+                 shifted=True, precision="fp64", neighbor_list=True, reorder=None,
+                 nl_capacity=0, block=256, device="cuda", stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("libmd needs a GPU; none is visible")
+        lib()
+        pos = np.asarray(pos, dtype=np.float64)
+        vel = np.asarray(vel, dtype=np.float64)
+        n = pos.shape[0]
+        if reorder is None:
+            reorder = bool(neighbor_list)
+        self.params = Params(int(n), MD_LJ_SHIFTED if shifted else MD_LJ_TRUNC, float(L),
+                             float(eps), float(sigma), float(mass), float(r_cut), float(skin),
+                             float(dt), MD_FP64 if precision == "fp64" else MD_FP32_MIXED,
+                             MD_NEIGHBOR_LIST if neighbor_list else MD_CELLS_ONLY, 0,
+                             int(nl_capacity), int(bool(reorder)), int(block))
+        self.n = n
+        self.L = float(L)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = md_init(self.params)
+        self.grid = md_geometry(self.ctx)
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=self.device)
+        self.x, self.y, self.z = (t(pos[:, k]) for k in range(3))
+        self.vx, self.vy, self.vz = (t(vel[:, k]) for k in range(3))
+        fdt = torch.float64 if precision == "fp64" else torch.float32
+        self.fx, self.fy, self.fz = (torch.zeros(n, dtype=fdt, device=self.device)
+                                     for _ in range(3))
+        self.id = torch.arange(n, dtype=torch.int32, device=self.device)
+        nbytes = md_workspace_bytes(self.ctx)
+        # 256-byte alignment: torch's caching allocator returns 512-byte aligned blocks
+        self.workspace = torch.zeros(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_shift = (-base) % 256
+        bufs = Buffers(*[v.data_ptr() for v in (self.x, self.y, self.z, self.vx, self.vy,
+                                                 self.vz, self.fx, self.fy, self.fz, self.id)],
+                       base + self._ws_shift)
+        torch.cuda.synchronize(self.device)
+        md_bind(self.ctx, bufs, self.stream.cuda_stream)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            try:
+                md_destroy(ctx)
+            except Exception:
+                pass
+            self.ctx = None
+
+    # -- the calls, in the paper's order
+    def build_cells(self):
+        md_build_cells(self.ctx)
+
+    def build_neighbors(self):
+        md_build_neighbors(self.ctx)
+
+    def forces(self):
+        md_forces(self.ctx)
+
+    def prepare(self):
+        """Cells, list (if any) and forces for the current state."""
+        self.build_cells()
+        if self.params.mode == MD_NEIGHBOR_LIST:
+            self.build_neighbors()
+        self.forces()
+
+    def step(self, n_steps, record_every=0):
+        md_step(self.ctx, n_steps, record_every)
+
+    def reduce(self, check=True) -> dict:
+        o = md_reduce(self.ctx, check=check)
+        return {"U": o.U, "K": o.K, "W": o.W, "P": np.array(o.P[:]), "T": o.T,
+                "pressure": o.pressure, "dmax": o.dmax, "step": o.step,
+                "n_rebuilds": o.n_rebuilds, "max_occupancy": o.max_occupancy,
+                "max_nl": o.max_nl, "flags": o.flags}
+
+    def history(self):
+        recs = md_history(self.ctx)
+        dt = np.dtype([("step", "i8"), ("U", "f8"), ("K", "f8"), ("W", "f8"), ("P", "f8", 3),
+                       ("dmax", "f8"), ("rebuilt", "i4")])
+        out = np.zeros(len(recs), dt)
+        for k, r in enumerate(recs):
+            out[k] = (r.step, r.U, r.K, r.W, tuple(r.P), r.dmax, r.rebuilt)
+        return out
+
+    def set_timing(self, enable=True):
+        md_set_timing(self.ctx, enable)
+
+    def get_timing(self):
+        return md_get_timing(self.ctx)
+
+    # -- views of the device state
+    def ws_array(self, which, dtype):
+        import torch
+
+        off, cnt = md_layout(self.ctx, which)
+        es = torch.empty((), dtype=dtype).element_size()
+        start = self._ws_shift + off
+        return self.workspace[start:start + cnt * es].view(dtype)
+
+    def _host(self, *ts):
+        self.stream.synchronize()
+        return [t.cpu().numpy() for t in ts]
+
+    def ids(self):
+        return self._host(self.id)[0]
+
+    def state(self):
+        """Positions, velocities, forces (float64) in id order."""
+        x, y, z, vx, vy, vz, fx, fy, fz, ids = self._host(self.x, self.y, self.z, self.vx,
+                                                          self.vy, self.vz, self.fx, self.fy,
+                                                          self.fz, self.id)
+        inv = np.empty(self.n, np.int64)
+        inv[ids] = np.arange(self.n)
+        pos = np.stack([x, y, z], 1)[inv]
+        vel = np.stack([vx, vy, vz], 1)[inv]
+        f = np.stack([fx, fy, fz], 1).astype(np.float64)[inv]
+        return {"pos": pos, "vel": vel, "f": f}
+
+    def cells(self):
+        """Cell arrays in slot space plus the slot -> id map."""
+        import torch
+
+        co = self.ws_array(MD_ARR_CELL_OF, torch.int32)
+        cs = self.ws_array(MD_ARR_CELL_START, torch.int32)
+        ca = self.ws_array(MD_ARR_CELL_ATOMS, torch.int32)
+        cell_of, cell_start, cell_atoms, ids = self._host(co, cs, ca, self.id)
+        return {"cell_of": cell_of, "cell_start": cell_start, "cell_atoms": cell_atoms,
+                "id": ids}
+
+    def neighbor_list(self):
+        """(count[n], nl[cap, n_pad]) in slot space."""
+        import torch
+
+        nl = self.ws_array(MD_ARR_NL, torch.int32)
+        cnt = self.ws_array(MD_ARR_NL_COUNT, torch.int32)
+        nl_h, cnt_h = self._host(nl, cnt)
+        return cnt_h, nl_h.reshape(self.grid.nl_capacity, self.grid.n_pad)

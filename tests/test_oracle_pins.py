@@ -31,6 +31,16 @@ def test_pair_at_sigma_is_zero_energy_and_24eps_force():
     assert fr == pytest.approx(24.0, rel=1e-15)
 
 
+def test_pair_error_scale_hand_values():
+    s = lj_sys()
+    # 48 (sr^12 + sr^6 / 2) / r: at r = sigma, 48 * 1.5; at the minimum, 24 / 2^(1/6)
+    assert oracle.pair_scale(s, 1.0) == pytest.approx(72.0, rel=1e-15)
+    assert oracle.pair_scale(s, WCA * WCA) == pytest.approx(24.0 / WCA, rel=1e-14)
+    assert oracle.pair_scale(s, 6.25) == 0.0
+    _, fr = oracle.pair(s, 1.0)
+    assert oracle.pair_scale(s, 1.0) >= abs(fr)
+
+
 def test_pair_at_minimum():
     s = lj_sys()
     u, fr = oracle.pair(s, WCA * WCA)
