@@ -67,7 +67,7 @@ def run_gpu(w, precision, steps, warmup):
     sim.set_timing(False)
     o1 = sim.reduce()
     e1 = (o1["U"] + o1["K"]) / w.n
-    cnt, _ = sim.neighbor_list()
+    cnt = sim.nl_counts()
     mean_nl = float(cnt[: w.n].mean())
     wall = t1 - t0
     res = {

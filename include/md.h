@@ -139,7 +139,10 @@ enum {
     MD_ARR_CELL_OF = 0,    /* int32[n]     cell of the atom in slot k (N1) */
     MD_ARR_CELL_START = 1, /* int32[nc^3+1] first entry of each cell in CELL_ATOMS (N2-N4) */
     MD_ARR_CELL_ATOMS = 2, /* int32[n]     slots grouped by cell, ascending id in a cell */
-    MD_ARR_NL = 3,         /* int32[cap][n_pad] neighbor slots, row m = m-th neighbors (N5) */
+    MD_ARR_NL = 3,         /* uint16[cap][n_pad] in 4-entry chunks: the m-th neighbor of slot k
+                              is 16-bit word m%4 of 8-byte chunk (m/4)*n_pad + k; the word holds
+                              the neighbor's index among its tile's staged atoms (13 bits) and
+                              its periodic wrap bits (3 bits); md_export_neighbors decodes it */
     MD_ARR_NL_COUNT = 4,   /* int32[n]     list length per slot */
     MD_ARR_XREF = 5,       /* double[3][n] positions at the last list build */
     MD_ARR_COUNT_ = 6
@@ -180,15 +183,24 @@ md_status md_build_cells(md_ctx* ctx);
  * Enqueued; overflow is latched. */
 md_status md_build_neighbors(md_ctx* ctx);
 
+/* md_export_neighbors: decode the list into global slots, dst[m * n_pad +
+ * k] = slot of the m-th neighbor of slot k for m < count, -1 for the
+ * remaining rows; dst is a device buffer of nl_capacity * n_pad int32
+ * owned by the caller.  Requires md_build_neighbors.  Enqueued. */
+md_status md_export_neighbors(md_ctx* ctx, int32_t* dst);
+
 /* md_forces (F1): per-atom force over the list (or the 27 cells in
  * MD_CELLS_ONLY mode), pairs closer than r_cut, plus per-workgroup partial
  * sums of the potential energy and the virial.  Requires the cells (and
  * list).  Enqueued. */
 md_status md_forces(md_ctx* ctx);
 
-/* md_step: n_steps leapfrog steps, kick-drift-kick: v += dt/(2m) f; x += dt v,
- * wrapped into [0, L); rebuild cells (and list) when needed; forces;
- * v += dt/(2m) f.  Requires md_forces to have run on the current state.
+/* md_step: n_steps leapfrog steps, kick-drift-kick: v += dt/(2m) f; x += dt v;
+ * rebuild cells (and list) when needed; forces; v += dt/(2m) f.  Positions
+ * are folded into [0, L) at every cell build and may lie outside the box by
+ * less than skin/2 in between (the list's periodic wrap bits stay valid);
+ * separations always use the minimum image.  Requires md_forces to have
+ * run on the current state.
  * When record_every > 0, every step whose index is a multiple of
  * record_every is appended to the history (capacity 4096 records, oldest
  * overwritten).  Enqueued. */
@@ -203,6 +215,28 @@ md_status md_reduce(md_ctx* ctx, md_observables* out);
 /* md_history: copy up to max_records history records, oldest first, to the
  * host array out; *n_out receives the count.  Synchronizes the stream. */
 md_status md_history(md_ctx* ctx, md_record* out, int32_t max_records, int32_t* n_out);
+
+/* Launch shape of the hot kernels.  Every setting gives results within the
+ * parity tolerances; the force pass's summation order depends on
+ * force_lanes, so bitwise reproducibility holds for a fixed tuning. */
+typedef struct {
+    int32_t force_lanes;   /* lanes sharing one atom's list in the force pass: 1, 2, 4 */
+    int32_t force_batch;   /* 4-entry list chunks each lane fetches ahead: 1, 2, 4 */
+    int32_t force_block;   /* threads per workgroup of the force pass: 64..1024, multiple of 64 */
+    int32_t nl_batch;      /* staged candidates each lane loads ahead in the list build: 1, 4 */
+    int32_t nl_block;      /* threads per workgroup of the list build: 64..1024, multiple of 64 */
+    int32_t tile_cells;    /* cells per tile along x in neighbor-list mode; 0 = from density */
+    int32_t stage_cap;     /* atoms a workgroup stages in LDS (0 = 1.5x the mean need); tiles
+                              that hold more read positions from global memory instead */
+} md_tuning;
+
+/* md_set_tuning: change the launch shape (host only; takes effect at the
+ * next launch).  The forces must be recomputed (md_forces) before md_step,
+ * and a change of tile_cells also needs md_build_neighbors, since list
+ * entries index the tile's staged atoms.  md_get_tuning: the current shape
+ * (tile_cells as resolved). */
+md_status md_set_tuning(md_ctx* ctx, const md_tuning* tuning);
+md_status md_get_tuning(const md_ctx* ctx, md_tuning* tuning);
 
 /* md_set_timing: when enable != 0, bracket every force-pass launch with HIP
  * events on the bound stream; md_get_timing returns the summed elapsed time

@@ -7,10 +7,12 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <initializer_list>
 #include <new>
 #include <vector>
 
 #include "md_internal.h"
+#include "md_tiles.h"
 
 using namespace md;
 
@@ -21,7 +23,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 enum Region {
-    R_DEV, R_CELL_COUNT, R_CELL_START, R_CELL_OF, R_SLOT, R_ORDER, R_NL, R_NL_COUNT,
+    R_DEV, R_CELL_COUNT, R_CELL_START, R_CELL_OF, R_SLOT, R_ORDER, R_TMP, R_NL, R_NL_COUNT,
     R_XR, R_YR, R_ZR, R_SX, R_SY, R_SZ, R_SVX, R_SVY, R_SVZ, R_SFX, R_SFY, R_SFZ, R_SID,
     R_SCELL, R_FPART, R_IPART, R_SCAN, R_HIST, R_COUNT
 };
@@ -41,6 +43,9 @@ struct md_ctx {
     std::vector<hipEvent_t> ev_free, ev_pending;  // pending holds start/stop pairs
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
+    size_t lds_limit = 160 * 1024;  // per-workgroup LDS; refreshed from the device at bind
+    int tile_cells = 0;
+    int stage_cap = 0;              // requested staged-atom capacity (0: from density)
 };
 
 extern "C" const char* md_status_str(int32_t st)
@@ -56,6 +61,37 @@ extern "C" const char* md_status_str(int32_t st)
         case MD_ERR_STATE: return "call out of order";
         default: return "unknown status";
     }
+}
+
+// Tiling of the neighbor-list mode: each row of nc cells is cut into
+// tiles_per_row tiles of about `cells` cells (0: enough cells for ~90% of a
+// workgroup's home-atom slots at the mean occupancy).  The LDS capacity
+// allows 1.5x the mean staged count, within the device's per-workgroup LDS.
+static void plan_tiles(md_ctx* c, int cells)
+{
+    KParams& k = c->kp;
+    const int nc = k.nc;
+    const double occ = (double)k.n / ((double)nc * nc * nc);
+    if (cells <= 0) {
+        const double home = 0.9 * k.force_block / k.force_lanes;
+        cells = (int)floor(home / (occ > 1e-9 ? occ : 1e-9) + 0.5);
+    }
+    const int kx_cap = nc < 128 ? nc : 128;
+    cells = cells < 1 ? 1 : (cells > kx_cap ? kx_cap : cells);
+    k.tiles_per_row = (nc + cells - 1) / cells;
+    k.kx_max = (nc + k.tiles_per_row - 1) / k.tiles_per_row;
+    k.n_tiles = nc * nc * k.tiles_per_row;
+    const double s_mean = 9.0 * (k.kx_max + 2) * occ;
+    // tables, the list build's per-wave counters (up to 16 waves) and static LDS
+    const size_t tables = stage_bytes(0, k.kx_max) + 16 * kMaxHomeSweep * sizeof(int) + 1024;
+    const size_t room = c->lds_limit > tables ? c->lds_limit - tables : 0;
+    int scap = c->stage_cap > 0 ? c->stage_cap : (int)(1.5 * s_mean + 128.0);
+    const int scap_max = (int)(room / (3 * sizeof(double)));
+    if (scap > scap_max) scap = scap_max;
+    scap = scap / 64 * 64;
+    k.scap = scap < 64 ? 64 : scap;
+    c->tile_cells = cells;
+    k.nblk_force = force_blocks(k);
 }
 
 static md_status hip_ok(hipError_t e) { return e == hipSuccess ? MD_OK : MD_ERR_HIP; }
@@ -106,6 +142,7 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
             cap = (cap + 7) / 8 * 8;
         }
         if (cap > n - 1) cap = (int)(n - 1 > 0 ? n - 1 : 1);
+        cap = (cap + 3) / 4 * 4;  // whole 4-entry chunks
     }
     c->geo.nc = nc;
     c->geo.n_cells = nc * nc * nc;
@@ -115,22 +152,21 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
 
     // workspace layout
     const int64_t ncell = (int64_t)nc * nc * nc;
-    const int nblk_force = (int)((n + p.block - 1) / p.block);
     const int ntile = (int)((ncell + 1023) / 1024);
     const size_t fsz = p.precision == MD_FP64 ? sizeof(double) : sizeof(float);
     size_t* b = c->bytes;
     b[R_DEV] = sizeof(DevState);
     b[R_CELL_COUNT] = sizeof(int32_t) * ncell;
     b[R_CELL_START] = sizeof(int32_t) * (ncell + 1);
-    b[R_CELL_OF] = b[R_SLOT] = b[R_ORDER] = sizeof(int32_t) * n;
-    b[R_NL] = sizeof(int32_t) * (size_t)cap * npad;
+    b[R_CELL_OF] = b[R_SLOT] = b[R_ORDER] = b[R_TMP] = sizeof(int32_t) * n;
+    b[R_NL] = sizeof(uint16_t) * (size_t)cap * npad;
     b[R_NL_COUNT] = sizeof(int32_t) * npad;
     b[R_XR] = b[R_YR] = b[R_ZR] = nl ? sizeof(double) * n : 0;
     const size_t perm = p.reorder ? 1 : 0;
     b[R_SX] = b[R_SY] = b[R_SZ] = b[R_SVX] = b[R_SVY] = b[R_SVZ] = perm * sizeof(double) * n;
     b[R_SFX] = b[R_SFY] = b[R_SFZ] = perm * fsz * n;
     b[R_SID] = b[R_SCELL] = perm * sizeof(int32_t) * n;
-    b[R_FPART] = sizeof(double) * 2 * nblk_force;
+    b[R_FPART] = sizeof(double) * 2 * (size_t)max_force_blocks(n, ncell);
     b[R_IPART] = sizeof(double) * 8 * kIntegrateGrid;
     b[R_SCAN] = sizeof(int32_t) * 2 * (size_t)ntile;
     b[R_HIST] = sizeof(md_record) * kHistCap;
@@ -180,8 +216,13 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
         k.inner_lo = 1.0;
         k.inner_hi = 0.0;  // empty range: always take the minimum image
     }
-    k.nblk_force = nblk_force;
     k.block = p.block;
+    k.force_lanes = 1;
+    k.force_batch = 2;
+    k.force_block = 256;
+    k.nl_batch = 4;
+    k.nl_block = 256;
+    plan_tiles(c, 0);
     *out = c;
     return MD_OK;
 }
@@ -238,7 +279,8 @@ extern "C" md_status md_bind(md_ctx* c, const md_buffers* bf, void* stream)
     k.cell_of = static_cast<int32_t*>(at(R_CELL_OF));
     k.slot = static_cast<int32_t*>(at(R_SLOT));
     k.order = static_cast<int32_t*>(at(R_ORDER));
-    k.nl = static_cast<int32_t*>(at(R_NL));
+    k.tmp = static_cast<int32_t*>(at(R_TMP));
+    k.nl64 = static_cast<uint64_t*>(at(R_NL));
     k.nl_count = static_cast<int32_t*>(at(R_NL_COUNT));
     k.xr = static_cast<double*>(at(R_XR));
     k.yr = static_cast<double*>(at(R_YR));
@@ -259,6 +301,12 @@ extern "C" md_status md_bind(md_ctx* c, const md_buffers* bf, void* stream)
     k.scanpart = static_cast<int32_t*>(at(R_SCAN));
     k.hist = static_cast<md_record*>(at(R_HIST));
     c->stream = static_cast<hipStream_t>(stream);
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return MD_ERR_HIP;
+    c->lds_limit = (size_t)lds;
+    plan_tiles(c, c->tile_cells);
     c->bound = true;
     c->cells_ok = c->nl_ok = c->forces_ok = false;
     launch_clear(k, c->stream);
@@ -324,6 +372,16 @@ static md_status fold_timing(md_ctx* c)
     }
     c->ev_pending.clear();
     return MD_OK;
+}
+
+extern "C" md_status md_export_neighbors(md_ctx* c, int32_t* dst)
+{
+    if (!c || !dst) return MD_ERR_ARG;
+    if (!c->bound) return MD_ERR_NOT_BOUND;
+    if (c->prm.mode != MD_NEIGHBOR_LIST) return MD_ERR_ARG;
+    if (!c->nl_ok) return MD_ERR_STATE;
+    launch_nl_export(c->kp, dst, c->stream);
+    return launched();
 }
 
 extern "C" md_status md_forces(md_ctx* c)
@@ -410,6 +468,50 @@ extern "C" md_status md_history(md_ctx* c, md_record* out, int32_t max_records, 
     const int64_t first = total - avail;  // oldest record still held
     for (int64_t r = 0; r < take; ++r) out[r] = ring[(first + r) % kHistCap];
     *n_out = (int32_t)take;
+    return MD_OK;
+}
+
+static bool one_of(int v, std::initializer_list<int> set)
+{
+    for (int s : set)
+        if (v == s) return true;
+    return false;
+}
+
+extern "C" md_status md_set_tuning(md_ctx* c, const md_tuning* t)
+{
+    if (!c || !t) return MD_ERR_ARG;
+    if (!one_of(t->force_lanes, {1, 2, 4}) || !one_of(t->force_batch, {1, 2, 4}) ||
+        !one_of(t->nl_batch, {1, 4}) || t->force_block % 64 != 0 || t->force_block < 64 ||
+        t->force_block > 1024 || t->nl_block % 64 != 0 || t->nl_block < 64 ||
+        t->nl_block > 1024 || t->tile_cells < 0 || t->stage_cap < 0)
+        return MD_ERR_ARG;
+    KParams& k = c->kp;
+    const int old_tiles = k.n_tiles, old_cells = c->tile_cells;
+    k.force_lanes = t->force_lanes;
+    k.force_batch = t->force_batch;
+    k.force_block = t->force_block;
+    k.nl_batch = t->nl_batch;
+    k.nl_block = t->nl_block;
+    c->stage_cap = t->stage_cap;
+    plan_tiles(c, t->tile_cells);
+    // the list encoding depends on the tiling
+    if (k.n_tiles != old_tiles || c->tile_cells != old_cells) c->nl_ok = false;
+    // the partials of the last force pass are laid out for the old grid
+    c->forces_ok = false;
+    return MD_OK;
+}
+
+extern "C" md_status md_get_tuning(const md_ctx* c, md_tuning* t)
+{
+    if (!c || !t) return MD_ERR_ARG;
+    t->force_lanes = c->kp.force_lanes;
+    t->force_batch = c->kp.force_batch;
+    t->force_block = c->kp.force_block;
+    t->nl_batch = c->kp.nl_batch;
+    t->nl_block = c->kp.nl_block;
+    t->tile_cells = c->tile_cells;
+    t->stage_cap = c->kp.scap;
     return MD_OK;
 }
 

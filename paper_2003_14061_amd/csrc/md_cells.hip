@@ -6,7 +6,7 @@
 //                atom's (unordered) rank in its cell
 //   k_scan_*     N3/N4: exclusive scan of the counts -> cell_start, and the
 //                largest occupancy; clears the counts for the next build
-//   k_scatter    slots grouped by cell
+//   k_scatter    slots grouped by cell (in the order the atomics gave)
 //   k_cellsort   inside each cell, ascending permanent id (the paper leaves
 //                the order open; a fixed order makes the list reproducible)
 //   k_permute /  with reorder on: atom data permuted into cell order
@@ -49,9 +49,16 @@ __global__ void k_clear(KParams p)
 __global__ void k_bin(KParams p, int force)
 {
     if (!rebuild_on(p, force)) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= p.n) return;
-    int c = cell_of_pos(p.x[i], p.y[i], p.z[i], p);
+    // positions are folded into [0, L) here, at each cell build, and drift
+    // freely in between (by less than skin/2), so the wrap bits of the
+    // list stay valid until the next build
+    const double x = wrap(p.x[i], p.L), y = wrap(p.y[i], p.L), z = wrap(p.z[i], p.L);
+    p.x[i] = x;
+    p.y[i] = y;
+    p.z[i] = z;
+    int c = cell_of_pos(x, y, z, p);
     p.cell_of[i] = c;
     p.slot[i] = atomicAdd(&p.cell_count[c], 1);
 }
@@ -181,29 +188,33 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_final(KParams p, int forc
 __global__ void k_scatter(KParams p, int force)
 {
     if (!rebuild_on(p, force)) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= p.n) return;
-    p.order[p.cell_start[p.cell_of[i]] + p.slot[i]] = i;
+    p.tmp[p.cell_start[p.cell_of[i]] + p.slot[i]] = i;
 }
 
-// Insertion sort of each cell's slots by permanent id (cells hold tens of atoms).
+// Canonical order inside each cell: ascending permanent id.  One wave per
+// cell; each member's position is its rank, the number of members with a
+// smaller id, counted with wave shuffles (ids are distinct).
 __global__ void k_cellsort(KParams p, int force)
 {
     if (!rebuild_on(p, force)) return;
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int c = xcd_tile(blockIdx.x, gridDim.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (c >= p.ncell) return;
-    const int a = p.cell_start[c], b = p.cell_start[c + 1];
-    for (int k = a + 1; k < b; ++k) {
-        int s = p.order[k];
-        int key = p.id[s];
-        int q = k - 1;
-        while (q >= a) {
-            int t = p.order[q];
-            if (p.id[t] <= key) break;
-            p.order[q + 1] = t;
-            --q;
+    const int a = p.cell_start[c], cnt = p.cell_start[c + 1] - a;
+    for (int i0 = 0; i0 < cnt; i0 += kWave) {
+        const int ii = i0 + lane;
+        const int s = ii < cnt ? p.tmp[a + ii] : 0;
+        const int key = ii < cnt ? p.id[s] : 0x7fffffff;
+        int rank = 0;
+        for (int j0 = 0; j0 < cnt; j0 += kWave) {
+            const int jj = j0 + lane;
+            const int kj = jj < cnt ? p.id[p.tmp[a + jj]] : 0x7fffffff;
+            const int lim = cnt - j0 < kWave ? cnt - j0 : kWave;
+            for (int q = 0; q < lim; ++q) rank += __shfl(kj, q, kWave) < key ? 1 : 0;
         }
-        p.order[q + 1] = s;
+        if (ii < cnt) p.order[a + rank] = s;
     }
 }
 
@@ -211,7 +222,7 @@ template <typename F>
 __global__ void k_permute(KParams p, int force)
 {
     if (!rebuild_on(p, force)) return;
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    int q = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (q >= p.n) return;
     const int o = p.order[q];
     p.sx[q] = p.x[o];
@@ -231,7 +242,7 @@ template <typename F>
 __global__ void k_copyback(KParams p, int force)
 {
     if (!rebuild_on(p, force)) return;
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    int q = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (q >= p.n) return;
     p.x[q] = p.sx[q];
     p.y[q] = p.sy[q];
@@ -267,7 +278,8 @@ void launch_cells(const KParams& p, int force, hipStream_t s)
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, p, ntile, force);
     hipLaunchKernelGGL(k_scan_final, dim3(ntile), dim3(kScanThreads), 0, s, p, force);
     hipLaunchKernelGGL(k_scatter, dim3(nblocks(p.n, b)), dim3(b), 0, s, p, force);
-    hipLaunchKernelGGL(k_cellsort, dim3(nblocks(p.ncell, 256)), dim3(256), 0, s, p, force);
+    hipLaunchKernelGGL(k_cellsort, dim3(nblocks((int64_t)p.ncell * kWave, 256)), dim3(256), 0, s,
+                       p, force);
     if (p.reorder) {
         if (p.precision == MD_FP64) {
             hipLaunchKernelGGL(k_permute<double>, dim3(nblocks(p.n, b)), dim3(b), 0, s, p, force);

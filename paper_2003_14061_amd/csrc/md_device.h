@@ -84,6 +84,19 @@ __device__ __forceinline__ double recip(double a)
     return __builtin_fma(y, e, y);
 }
 
+// ---- XCD-aware tile order ----
+// MI355X deals workgroup b to XCD (b mod 8).  Atoms are stored in cell
+// order, so giving each XCD one contiguous range of tiles keeps the
+// neighborhoods its workgroups gather from inside its own L2.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_tile(int b, int nblocks)
+{
+    const int per = nblocks / kXcds, rem = nblocks % kXcds;
+    const int x = b % kXcds, k = b / kXcds;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
 // ---- wave64 and workgroup reductions (fixed order: deterministic) ----
 
 template <typename T>

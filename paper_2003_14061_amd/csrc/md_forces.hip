@@ -1,21 +1,26 @@
 // md_forces.hip -- step F1 of section 2.3 (and the per-workgroup part of F2).
 //
-// One lane per atom walks its row of the neighbor matrix (or, in cells-only
-// mode, the 27 surrounding cells) and accumulates the force on that atom
-// alone: every pair is met twice, once from each side, so no atomics are
-// needed (the paper's choice).  Pairs at r^2 >= r_cut^2 are skipped.  The
-// potential energy and virial are reduced per workgroup (wave64 shuffles,
-// then LDS) and written as partials for the reduction kernels.
+// Neighbor-list mode: one workgroup per tile (md_tiles.h).  `lanes` lanes
+// per home atom walk its row of the neighbor matrix (lane s takes chunks s,
+// s+lanes, ...; a chunk is 4 entries).  The first `batch` chunks of every
+// lane are requested as soon as the tile's cell tables are known, so they
+// arrive while the tile's 27-cell neighborhoods are being staged in LDS;
+// the partners are then gathered from LDS and the force on the home atom
+// alone is accumulated.  Every pair is met twice,
+// once from each side, so no atomics are needed (the paper's choice).
+// Pairs at r^2 >= r_cut^2 are skipped.  Separations take the minimum image
+// from the wrap bits carried by each entry (section 4.1, factor (4)); tiles
+// with no periodic wrap skip even that.
+//
+// Cells-only mode: one lane per atom walks the 27 surrounding cells.
 //
 // Precision: FP64 forms everything in double.  FP32-mixed forms the pair
 // separation and the cutoff test in double, then the pair force, energy and
 // virial and the per-atom sums in float.
 //
-// Atoms whose coordinates all lie at least r_cut + skin from every face
-// (and whose partners therefore cannot straddle the periodic boundary)
-// skip the minimum-image step when the whole wave qualifies; there the
-// image correction is exactly zero.
-#include "md_device.h"
+// The energy and virial are reduced per workgroup (wave64 shuffles, then
+// LDS) and written as partials for the reduction kernels.
+#include "md_tiles.h"
 
 namespace md {
 
@@ -66,27 +71,155 @@ __device__ __forceinline__ void pair_acc(const KParams& p, double dx, double dy,
     a.np += 1;
 }
 
-template <bool kInterior, typename Acc>
-__device__ __forceinline__ void visit(const KParams& p, double xi, double yi, double zi, int j,
-                                      Acc& a)
+template <int LANES, typename T>
+__device__ __forceinline__ T lane_group_sum(T v)
 {
-    double dx = xi - p.x[j], dy = yi - p.y[j], dz = zi - p.z[j];
+#pragma unroll
+    for (int o = LANES / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Entries of one 4-entry chunk.  Entries past the list length are masked
+// (and their index clamped: the tail of a chunk may hold a stale value).
+template <bool kFlags, bool kFits, typename Acc>
+__device__ __forceinline__ void chunk_pairs(const KParams& p, const Stage& s, uint64_t ch,
+                                            int mbase, int cnt, double xi, double yi, double zi,
+                                            Acc& a)
+{
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+        const bool valid = mbase + k < cnt;
+        const uint32_t v = valid ? (uint32_t)(ch >> (16 * k)) & 0xffffu : 0u;
+        const int e = (int)(v & kEntryMask);
+        double xj, yj, zj;
+        if (kFits) {
+            xj = s.xs[e];
+            yj = s.ys[e];
+            zj = s.zs[e];
+        } else {
+            const int j = staged_slot(p, s, e < s.total ? e : 0);
+            xj = p.x[j];
+            yj = p.y[j];
+            zj = p.z[j];
+        }
+        double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+        image<kFlags>(p, (int)(v >> kEntryBits), dx, dy, dz);
+        const double r2 = dist2(dx, dy, dz);
+        if (valid && r2 < p.rc2) pair_acc(p, dx, dy, dz, r2, a);
+    }
+}
+
+// Chunks c = sub + LANES*j of one home atom: the first PF were fetched into
+// `pre` before the tile was staged; the rest are read here.
+template <int LANES, int PF, bool kFlags, bool kFits, typename Acc>
+__device__ __forceinline__ void walk_tile_list(const KParams& p, const Stage& s, int slot_i,
+                                               int sub, int cnt, const uint64_t (&pre)[PF],
+                                               double xi, double yi, double zi, Acc& a)
+{
+    const int nchunk = (cnt + kChunk - 1) / kChunk;
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+        const int c = sub + LANES * j;
+        if (c < nchunk) chunk_pairs<kFlags, kFits>(p, s, pre[j], c * kChunk, cnt, xi, yi, zi, a);
+    }
+    const uint64_t* col = p.nl64 + slot_i;
+    for (int c = sub + LANES * PF; c < nchunk; c += LANES)
+        chunk_pairs<kFlags, kFits>(p, s, col[(int64_t)c * p.npad], c * kChunk, cnt, xi, yi, zi, a);
+}
+
+template <typename F, typename Acc, int LANES, int PF>
+__global__ void k_forces_tiles(KParams p)
+{
+    extern __shared__ char smem[];
+    __shared__ double red[(1024 / kWave) * 2];
+    const Tile g = tile_of(p, xcd_tile(blockIdx.x, gridDim.x));
+    Stage s = stage_layout(p, smem);
+    stage_tables(p, g, s);
+    const int nh = home_count(s), h0 = home_first_lds(s), slot0 = home_first_slot(s);
+    const bool flags = !tile_interior(p, g);
+    const int per_pass = blockDim.x / LANES;
+    const int sub = threadIdx.x % LANES;
+    double e[2] = {0.0, 0.0};
+    for (int hb = 0; hb < nh; hb += per_pass) {
+        const int h = hb + threadIdx.x / LANES;
+        // the list's length and first chunks are fetched before the positions
+        // are staged, so both round trips overlap
+        int slot_i = 0, cnt = 0;
+        uint64_t pre[PF];
+        if (h < nh) {
+            slot_i = atom_at(p, slot0 + h);
+            cnt = p.nl_count[slot_i];
+            const uint64_t* col = p.nl64 + slot_i;
+            const int nrow = p.cap / kChunk;
+#pragma unroll
+            for (int j = 0; j < PF; ++j) {
+                const int c = sub + LANES * j;
+                pre[j] = c < nrow ? col[(int64_t)c * p.npad] : 0;
+            }
+        }
+        if (hb == 0) stage_positions(p, s);
+        Acc a;
+        if (h < nh) {
+            double xi, yi, zi;
+            if (s.fits) {
+                xi = s.xs[h0 + h];
+                yi = s.ys[h0 + h];
+                zi = s.zs[h0 + h];
+            } else {
+                xi = p.x[slot_i];
+                yi = p.y[slot_i];
+                zi = p.z[slot_i];
+            }
+            if (s.fits) {
+                if (flags)
+                    walk_tile_list<LANES, PF, true, true>(p, s, slot_i, sub, cnt, pre, xi, yi, zi, a);
+                else
+                    walk_tile_list<LANES, PF, false, true>(p, s, slot_i, sub, cnt, pre, xi, yi, zi, a);
+            } else {
+                walk_tile_list<LANES, PF, true, false>(p, s, slot_i, sub, cnt, pre, xi, yi, zi, a);
+            }
+        }
+        if (LANES > 1) {
+            a.fx = lane_group_sum<LANES>(a.fx);
+            a.fy = lane_group_sum<LANES>(a.fy);
+            a.fz = lane_group_sum<LANES>(a.fz);
+            a.u = lane_group_sum<LANES>(a.u);
+            a.w = lane_group_sum<LANES>(a.w);
+            a.np = lane_group_sum<LANES>(a.np);
+        }
+        if (h < nh && sub == 0) {
+            static_cast<F*>(p.fx)[slot_i] = a.fx;
+            static_cast<F*>(p.fy)[slot_i] = a.fy;
+            static_cast<F*>(p.fz)[slot_i] = a.fz;
+            // per-atom energy: half of each pair's 4 eps (sr12 - sr6) - shift
+            const double ui = p.eps2 * (double)a.u - p.half_shift * (double)a.np;
+            e[0] += ui;
+            e[1] += 0.5 * (double)a.w;
+            if (!isfinite(ui + (double)a.fx + (double)a.fy + (double)a.fz))
+                atomicOr(&p.dev->flags, (int)MD_FLAG_NONFINITE);
+        }
+    }
+    block_sum<2>(e, red);
+    if (threadIdx.x == 0) {
+        p.fpart[2 * blockIdx.x] = e[0];
+        p.fpart[2 * blockIdx.x + 1] = e[1];
+    }
+}
+
+// ---- cells-only mode ----
+
+template <bool kInterior, typename Acc>
+__device__ __forceinline__ void visit(const KParams& p, double xi, double yi, double zi,
+                                      double xj, double yj, double zj, bool valid, Acc& a)
+{
+    double dx = xi - xj, dy = yi - yj, dz = zi - zj;
     if (!kInterior) {
         dx = minimg(dx, p.L, p.invL);
         dy = minimg(dy, p.L, p.invL);
         dz = minimg(dz, p.L, p.invL);
     }
     const double r2 = dist2(dx, dy, dz);
-    if (r2 < p.rc2) pair_acc(p, dx, dy, dz, r2, a);
-}
-
-template <bool kInterior, typename Acc>
-__device__ __forceinline__ void walk_list(const KParams& p, int i, Acc& a)
-{
-    const double xi = p.x[i], yi = p.y[i], zi = p.z[i];
-    const int cnt = p.nl_count[i];
-    const int* row = p.nl + i;
-    for (int m = 0; m < cnt; ++m) visit<kInterior>(p, xi, yi, zi, row[(int64_t)m * p.npad], a);
+    if (valid && r2 < p.rc2) pair_acc(p, dx, dy, dz, r2, a);
 }
 
 template <bool kInterior, typename Acc>
@@ -103,41 +236,32 @@ __device__ __forceinline__ void walk_cells(const KParams& p, int i, Acc& a)
                 const int c2 = (zz * nc + yy) * nc + wrap_cell(cx + dx, nc);
                 for (int k = p.cell_start[c2]; k < p.cell_start[c2 + 1]; ++k) {
                     const int j = p.order[k];
-                    if (j != i) visit<kInterior>(p, xi, yi, zi, j, a);
+                    visit<kInterior>(p, xi, yi, zi, p.x[j], p.y[j], p.z[j], j != i, a);
                 }
             }
         }
     }
 }
 
-template <typename F, typename Acc, bool kCells>
-__global__ void k_forces(KParams p)
+template <typename F, typename Acc>
+__global__ void k_forces_cells(KParams p)
 {
     __shared__ double red[(1024 / kWave) * 2];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     Acc a;
     if (i < p.n) {
-        bool inner;
-        if (kCells) {
-            const int c = p.cell_of[i], nc = p.nc;
-            const int cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
-            inner = nc >= 5 && cx >= 1 && cx <= nc - 2 && cy >= 1 && cy <= nc - 2 && cz >= 1 &&
-                    cz <= nc - 2;
-        } else {
-            const double xi = p.x[i], yi = p.y[i], zi = p.z[i];
-            inner = xi >= p.inner_lo && xi <= p.inner_hi && yi >= p.inner_lo &&
-                    yi <= p.inner_hi && zi >= p.inner_lo && zi <= p.inner_hi;
-        }
-        if (__all(inner)) {
-            if (kCells) walk_cells<true>(p, i, a); else walk_list<true>(p, i, a);
-        } else {
-            if (kCells) walk_cells<false>(p, i, a); else walk_list<false>(p, i, a);
-        }
+        const int c = p.cell_of[i], nc = p.nc;
+        const int cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
+        const bool inner = nc >= 5 && cx >= 1 && cx <= nc - 2 && cy >= 1 && cy <= nc - 2 &&
+                           cz >= 1 && cz <= nc - 2;
+        if (__all(inner))
+            walk_cells<true>(p, i, a);
+        else
+            walk_cells<false>(p, i, a);
         static_cast<F*>(p.fx)[i] = a.fx;
         static_cast<F*>(p.fy)[i] = a.fy;
         static_cast<F*>(p.fz)[i] = a.fz;
     }
-    // per-atom energy: half of each pair's 4 eps (sr12 - sr6) - shift
     double e[2];
     e[0] = i < p.n ? p.eps2 * (double)a.u - p.half_shift * (double)a.np : 0.0;
     e[1] = i < p.n ? 0.5 * (double)a.w : 0.0;
@@ -150,18 +274,48 @@ __global__ void k_forces(KParams p)
     }
 }
 
+template <typename F, typename Acc, int LANES>
+static void launch_tiles_b(const KParams& p, dim3 g, dim3 t, size_t lds, hipStream_t s)
+{
+    switch (p.force_batch) {
+        case 1: hipLaunchKernelGGL((k_forces_tiles<F, Acc, LANES, 1>), g, t, lds, s, p); break;
+        case 4: hipLaunchKernelGGL((k_forces_tiles<F, Acc, LANES, 4>), g, t, lds, s, p); break;
+        default: hipLaunchKernelGGL((k_forces_tiles<F, Acc, LANES, 2>), g, t, lds, s, p); break;
+    }
+}
+
+template <typename F, typename Acc>
+static void launch_tiles(const KParams& p, hipStream_t s)
+{
+    const dim3 g(p.n_tiles), t(p.force_block);
+    const size_t lds = stage_bytes(p.scap, p.kx_max);
+    switch (p.force_lanes) {
+        case 2: launch_tiles_b<F, Acc, 2>(p, g, t, lds, s); break;
+        case 4: launch_tiles_b<F, Acc, 4>(p, g, t, lds, s); break;
+        default: launch_tiles_b<F, Acc, 1>(p, g, t, lds, s); break;
+    }
+}
+
+int force_blocks(const KParams& p)
+{
+    if (p.mode == MD_CELLS_ONLY) return (p.n + p.block - 1) / p.block;
+    return p.n_tiles;
+}
+
 void launch_forces(const KParams& p, hipStream_t s)
 {
-    const int b = p.block;
-    const dim3 g(p.nblk_force), t(b);
-    const bool cells = p.mode == MD_CELLS_ONLY;
-    if (p.precision == MD_FP64) {
-        if (cells) hipLaunchKernelGGL((k_forces<double, AccD, true>), g, t, 0, s, p);
-        else hipLaunchKernelGGL((k_forces<double, AccD, false>), g, t, 0, s, p);
-    } else {
-        if (cells) hipLaunchKernelGGL((k_forces<float, AccF, true>), g, t, 0, s, p);
-        else hipLaunchKernelGGL((k_forces<float, AccF, false>), g, t, 0, s, p);
+    if (p.mode == MD_CELLS_ONLY) {
+        const dim3 g(p.nblk_force), t(p.block);
+        if (p.precision == MD_FP64)
+            hipLaunchKernelGGL((k_forces_cells<double, AccD>), g, t, 0, s, p);
+        else
+            hipLaunchKernelGGL((k_forces_cells<float, AccF>), g, t, 0, s, p);
+        return;
     }
+    if (p.precision == MD_FP64)
+        launch_tiles<double, AccD>(p, s);
+    else
+        launch_tiles<float, AccF>(p, s);
 }
 
 }  // namespace md

@@ -4,8 +4,9 @@
 // kicks.  The second half kick of step s and the first of step s+1 use the
 // same force, so one pass over the atoms does both (in that order, each
 // rounded on its own) and measures the kinetic energy and momentum at the
-// full step in between.  The drift wraps positions into [0, L) and measures
-// each atom's displacement from the list reference; the largest one decides
+// full step in between.  The drift measures each atom's displacement from
+// the list reference (minimum image; positions are folded back into [0, L)
+// only when the cells are rebuilt, see k_bin); the largest one decides
 // whether the cells and list are rebuilt before the next force pass (the
 // paper refreshes "at intervals of several time steps", section 2.3, from a
 // bound on the maximal velocity; here the bound is the displacement itself).
@@ -21,10 +22,12 @@ namespace md {
 constexpr int kIntThreads = 256;
 
 // Sum partials [nb][stride] (component k) over workgroups in a fixed order.
+// Called only by the last workgroup, after the acquire fence of last_block,
+// so plain loads see every other workgroup's partial.
 __device__ double finish_sum(const double* part, int nb, int stride, int k, double* red)
 {
     double v[1] = {0.0};
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) v[0] += load_coherent(part + b * stride + k);
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) v[0] += part[b * stride + k];
     block_sum<1>(v, red);
     return v[0];
 }
@@ -33,7 +36,7 @@ __device__ double finish_max(const double* part, int nb, int stride, int k, doub
 {
     double m = 0.0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        double t = load_coherent(part + b * stride + k);
+        double t = part[b * stride + k];
         m = t > m ? t : m;
     }
     m = wave_max(m);
@@ -50,10 +53,15 @@ __device__ double finish_max(const double* part, int nb, int stride, int k, doub
     return m;
 }
 
-// Finish a completed step: sum U, W (last force pass) and K, P (this
-// kernel's partials) and append to the history when requested.
+// Finish a completed step: count it, and on steps the history asks for, sum
+// U, W (last force pass) and K, P (this kernel's partials) and append them.
 __device__ void record_step(const KParams& p, double* red)
 {
+    DevState* dd = p.dev;
+    const int64_t step = dd->step + 1;
+    __syncthreads();
+    if (threadIdx.x == 0) dd->step = step;
+    if (!(p.record_every > 0 && step % p.record_every == 0)) return;
     const double U = finish_sum(p.fpart, p.nblk_force, 2, 0, red);
     const double W = finish_sum(p.fpart, p.nblk_force, 2, 1, red);
     const double K = finish_sum(p.ipart, gridDim.x, 8, 0, red);
@@ -61,29 +69,18 @@ __device__ void record_step(const KParams& p, double* red)
     const double Py = finish_sum(p.ipart, gridDim.x, 8, 2, red);
     const double Pz = finish_sum(p.ipart, gridDim.x, 8, 3, red);
     if (threadIdx.x == 0) {
-        DevState* d = p.dev;
-        d->step += 1;
-        d->obs[0] = U;
-        d->obs[1] = 0.5 * p.mass * K;
-        d->obs[2] = W;
-        d->obs[3] = p.mass * Px;
-        d->obs[4] = p.mass * Py;
-        d->obs[5] = p.mass * Pz;
-        d->obs[6] = d->dmax2;
-        if (p.record_every > 0 && d->step % p.record_every == 0) {
-            md_record* r = p.hist + (d->hist_count % kHistCap);
-            r->step = d->step;
-            r->U = U;
-            r->K = 0.5 * p.mass * K;
-            r->W = W;
-            r->P[0] = p.mass * Px;
-            r->P[1] = p.mass * Py;
-            r->P[2] = p.mass * Pz;
-            r->dmax = sqrt(d->dmax2);
-            r->rebuilt = d->rebuild;
-            r->pad = 0;
-            d->hist_count += 1;
-        }
+        md_record* r = p.hist + (dd->hist_count % kHistCap);
+        r->step = step;
+        r->U = U;
+        r->K = 0.5 * p.mass * K;
+        r->W = W;
+        r->P[0] = p.mass * Px;
+        r->P[1] = p.mass * Py;
+        r->P[2] = p.mass * Pz;
+        r->dmax = sqrt(dd->dmax2);
+        r->rebuilt = dd->rebuild;
+        r->pad = 0;
+        dd->hist_count += 1;
     }
 }
 
@@ -113,9 +110,9 @@ __global__ __launch_bounds__(kIntThreads) void k_integrate(KParams p, int phase)
             vx = kick(vx, p.hdt, gx);
             vy = kick(vy, p.hdt, gy);
             vz = kick(vz, p.hdt, gz);
-            const double x = wrap(drift(p.x[i], p.dt, vx), p.L);
-            const double y = wrap(drift(p.y[i], p.dt, vy), p.L);
-            const double z = wrap(drift(p.z[i], p.dt, vz), p.L);
+            const double x = drift(p.x[i], p.dt, vx);
+            const double y = drift(p.y[i], p.dt, vy);
+            const double z = drift(p.z[i], p.dt, vz);
             p.x[i] = x;
             p.y[i] = y;
             p.z[i] = z;

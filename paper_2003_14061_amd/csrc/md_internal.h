@@ -44,8 +44,9 @@ struct KParams {
     int32_t* id;
     // workspace arrays
     DevState* dev;
-    int32_t *cell_count, *cell_start, *cell_of, *slot, *order;
-    int32_t *nl, *nl_count;
+    int32_t *cell_count, *cell_start, *cell_of, *slot, *order, *tmp;
+    uint64_t* nl64;       // list chunks: 4 x 16-bit entries, chunk c of slot k at c*npad + k
+    int32_t* nl_count;
     double *xr, *yr, *zr;
     double *sx, *sy, *sz, *svx, *svy, *svz, *sfx, *sfy, *sfz;  // permutation scratch
     int32_t *sid, *scell;
@@ -53,16 +54,33 @@ struct KParams {
     double *ipart;    // per-atom kernel partials [kIntegrateGrid][8]
     int32_t *scanpart;  // scan partials [nscan][2]: sum, max
     md_record* hist;
-    int32_t nblk_force;
+    int32_t nblk_force;     // workgroups of the last-configured force pass
     int32_t block;
-    int32_t record_every;  // history interval of the running md_step (0 = none)
+    int32_t record_every;   // history interval of the running md_step (0 = none)
+    int32_t force_lanes;    // lanes per home atom in the tiled force pass (1, 2, 4)
+    int32_t force_batch;    // list chunks fetched ahead per lane (1, 2, 4)
+    int32_t force_block;    // threads per workgroup of the tiled kernels
+    int32_t nl_batch;       // staged candidates loaded ahead per lane in the list build (1, 4)
+    int32_t nl_block;       // threads per workgroup of the list build
+    // tiling of the neighbor-list mode: rows of nc cells cut into tiles_per_row tiles
+    int32_t tiles_per_row, kx_max, n_tiles;
+    int32_t scap;           // staged atoms a workgroup's LDS holds
 };
+
+// Largest number of force-pass workgroups any tuning can ask for.
+inline int64_t max_force_blocks(int64_t n, int64_t ncell)
+{
+    const int64_t a = (n + 63) / 64 + 1;
+    return a > ncell + 1 ? a : ncell + 1;
+}
 
 // Host-side launchers (one translation unit per stage).
 void launch_clear(const KParams& p, hipStream_t s);
 void launch_cells(const KParams& p, int force, hipStream_t s);
 void launch_neighbors(const KParams& p, int force, hipStream_t s);
+void launch_nl_export(const KParams& p, int32_t* out, hipStream_t s);
 void launch_forces(const KParams& p, hipStream_t s);
+int force_blocks(const KParams& p);  // workgroups of the force pass for the current tuning
 // phase 0: kick + drift; 1: kick, record, kick + drift; 2: kick, record
 void launch_integrate(const KParams& p, int phase, hipStream_t s);
 void launch_observe(const KParams& p, hipStream_t s);

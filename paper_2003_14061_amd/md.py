@@ -27,7 +27,8 @@ MD_ARR_CELL_OF, MD_ARR_CELL_START, MD_ARR_CELL_ATOMS, MD_ARR_NL, MD_ARR_NL_COUNT
 
 EXPORTS = ("md_init", "md_workspace_bytes", "md_geometry", "md_layout", "md_bind",
            "md_build_cells", "md_build_neighbors", "md_forces", "md_step", "md_reduce",
-           "md_history", "md_set_timing", "md_get_timing", "md_destroy", "md_status_str")
+           "md_history", "md_set_tuning", "md_get_tuning", "md_set_timing", "md_get_timing",
+           "md_export_neighbors", "md_destroy", "md_status_str")
 
 
 class MDError(RuntimeError):
@@ -52,6 +53,12 @@ class Buffers(C.Structure):
 class Grid(C.Structure):
     _fields_ = [("nc", C.c_int32), ("n_cells", C.c_int32), ("nl_capacity", C.c_int32),
                 ("n_pad", C.c_int32), ("cell_width", C.c_double)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("force_lanes", C.c_int32), ("force_batch", C.c_int32),
+                ("force_block", C.c_int32), ("nl_batch", C.c_int32), ("nl_block", C.c_int32),
+                ("tile_cells", C.c_int32), ("stage_cap", C.c_int32)]
 
 
 class Observables(C.Structure):
@@ -93,6 +100,9 @@ def lib():
         "md_step": (C.c_int, [P, C.c_int32, C.c_int32]),
         "md_reduce": (C.c_int, [P, C.POINTER(Observables)]),
         "md_history": (C.c_int, [P, C.POINTER(Record), C.c_int32, C.POINTER(C.c_int32)]),
+        "md_export_neighbors": (C.c_int, [P, P]),
+        "md_set_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
+        "md_get_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
         "md_set_timing": (C.c_int, [P, C.c_int32]),
         "md_get_timing": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "md_destroy": (None, [P]),
@@ -151,6 +161,10 @@ def md_build_neighbors(ctx):
     _check(lib().md_build_neighbors(ctx), "md_build_neighbors")
 
 
+def md_export_neighbors(ctx, dst_ptr: int):
+    _check(lib().md_export_neighbors(ctx, C.c_void_p(dst_ptr)), "md_export_neighbors")
+
+
 def md_forces(ctx):
     _check(lib().md_forces(ctx), "md_forces")
 
@@ -172,6 +186,19 @@ def md_history(ctx, max_records: int = 4096):
     n = C.c_int32()
     _check(lib().md_history(ctx, buf, max_records, C.byref(n)), "md_history")
     return list(buf[: n.value])
+
+
+def md_set_tuning(ctx, force_lanes=1, force_batch=2, force_block=256, nl_batch=4, nl_block=256,
+                  tile_cells=0, stage_cap=0):
+    t = Tuning(int(force_lanes), int(force_batch), int(force_block), int(nl_batch), int(nl_block),
+               int(tile_cells), int(stage_cap))
+    _check(lib().md_set_tuning(ctx, C.byref(t)), "md_set_tuning")
+
+
+def md_get_tuning(ctx) -> dict:
+    t = Tuning()
+    _check(lib().md_get_tuning(ctx, C.byref(t)), "md_get_tuning")
+    return {k: getattr(t, k) for k, _ in Tuning._fields_}
 
 
 def md_set_timing(ctx, enable: bool):
@@ -284,6 +311,14 @@ class Simulation:
             out[k] = (r.step, r.U, r.K, r.W, tuple(r.P), r.dmax, r.rebuilt)
         return out
 
+    def set_tuning(self, **kw):
+        cur = md_get_tuning(self.ctx)
+        cur.update(kw)
+        md_set_tuning(self.ctx, **cur)
+
+    def get_tuning(self):
+        return md_get_tuning(self.ctx)
+
     def set_timing(self, enable=True):
         md_set_timing(self.ctx, enable)
 
@@ -329,11 +364,19 @@ class Simulation:
         return {"cell_of": cell_of, "cell_start": cell_start, "cell_atoms": cell_atoms,
                 "id": ids}
 
-    def neighbor_list(self):
-        """(count[n], nl[cap, n_pad]) in slot space."""
+    def nl_counts(self):
+        """List length per slot (host copy)."""
         import torch
 
-        nl = self.ws_array(MD_ARR_NL, torch.int32)
+        return self._host(self.ws_array(MD_ARR_NL_COUNT, torch.int32))[0]
+
+    def neighbor_list(self):
+        """(count[n], nl[cap, n_pad]) in slot space, decoded by md_export_neighbors."""
+        import torch
+
+        out = torch.empty(self.grid.nl_capacity * self.grid.n_pad, dtype=torch.int32,
+                          device=self.device)
+        md_export_neighbors(self.ctx, out.data_ptr())
         cnt = self.ws_array(MD_ARR_NL_COUNT, torch.int32)
-        nl_h, cnt_h = self._host(nl, cnt)
+        nl_h, cnt_h = self._host(out, cnt)
         return cnt_h, nl_h.reshape(self.grid.nl_capacity, self.grid.n_pad)

@@ -223,3 +223,53 @@ def test_positions_on_cell_and_box_edges():
     nc2, cells = check_cells(sim, s, pos)
     sim.build_neighbors()
     check_nl(sim, s, pos, cells)
+
+
+TUNINGS = ([dict(force_lanes=l, force_batch=b) for l in (1, 2, 4) for b in (1, 2, 4)] +
+           [dict(tile_cells=c, nl_batch=nb, nl_block=blk, force_block=fb)
+            for c, nb, blk, fb in ((1, 1, 64, 64), (3, 4, 128, 512), (1000, 4, 256, 1024),
+                                   (2, 1, 512, 128))] +
+           [dict(stage_cap=64), dict(stage_cap=64, force_lanes=4, tile_cells=2)])
+
+
+@pytest.mark.parametrize("name", ["lj32000_nl", "wca13500_nl", "lj5000_random", "wca108_nc3",
+                                  "lj4000_noreorder"])
+def test_every_tuning_matches_the_oracle(name):
+    sim, s, pos, vel = setup(name)
+    sim.build_cells()
+    nc, cells = check_cells(sim, s, pos)
+    o_cnt, o_nl, _ = oracle.build_nl(s, nc, pos, cells)
+    ref = oracle.forces_nl(s, pos, o_cnt, o_nl)
+    base = sim.get_tuning()
+    for tu in TUNINGS:
+        kw = dict(base, tile_cells=0, stage_cap=0)
+        kw.update(tu)
+        sim.set_tuning(**kw)
+        sim.build_neighbors()
+        check_nl(sim, s, pos, cells)
+        sim.forces()
+        obs = sim.reduce()
+        per_atom, normwise = force_errors(sim.state()["f"], ref)
+        assert per_atom <= TOL["fp64"] and normwise <= TOL["fp64"], tu
+        assert energy_error(obs["U"], ref) <= TOL["fp64"], tu
+
+
+def test_tuning_is_validated():
+    sim, s, pos, vel = setup("wca108_nc3")
+    for bad in (dict(force_lanes=3), dict(force_lanes=8), dict(force_batch=8),
+                dict(force_block=96), dict(nl_batch=2), dict(nl_block=32), dict(tile_cells=-1),
+                dict(stage_cap=-5)):
+        with pytest.raises(md.MDError):
+            sim.set_tuning(**bad)
+    sim.prepare()
+    sim.set_tuning(force_lanes=2)
+    with pytest.raises(md.MDError):  # forces must be recomputed for the new layout
+        sim.step(1)
+    sim.forces()
+    sim.step(1)
+    sim.set_tuning(tile_cells=1)
+    with pytest.raises(md.MDError):  # a new tiling needs a new list
+        sim.forces()
+    sim.build_neighbors()
+    sim.forces()
+    sim.step(1)
