@@ -23,7 +23,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 enum Region {
-    R_DEV, R_CELL_COUNT, R_CELL_START, R_CELL_OF, R_SLOT, R_ORDER, R_TMP, R_NL, R_NL_COUNT,
+    R_DEV, R_CELL_COUNT, R_CELL_START, R_CELL_OF, R_SLOT, R_ORDER, R_TMP, R_NL, R_NL_COUNT, R_TILE_ROWS,
     R_XR, R_YR, R_ZR, R_SX, R_SY, R_SZ, R_SVX, R_SVY, R_SVZ, R_SFX, R_SFY, R_SFZ, R_SID,
     R_SCELL, R_FPART, R_IPART, R_SCAN, R_HIST, R_COUNT
 };
@@ -81,15 +81,27 @@ static void plan_tiles(md_ctx* c, int cells)
     k.tiles_per_row = (nc + cells - 1) / cells;
     k.kx_max = (nc + k.tiles_per_row - 1) / k.tiles_per_row;
     k.n_tiles = nc * nc * k.tiles_per_row;
+    // LDS: the staged atoms (1.5x the mean need) and the tile's list chunks
+    // (1.3x the mean home atoms times the rows of a long list)
     const double s_mean = 9.0 * (k.kx_max + 2) * occ;
-    // tables, the list build's per-wave counters (up to 16 waves) and static LDS
-    const size_t tables = stage_bytes(0, k.kx_max) + 16 * kMaxHomeSweep * sizeof(int) + 1024;
+    const double rl = sqrt(k.rl2);
+    const double nl_mean = 4.0 / 3.0 * M_PI * rl * rl * rl * occ / (c->geo.cell_width *
+                           c->geo.cell_width * c->geo.cell_width);
+    int rows = (int)ceil((nl_mean + 4.0 * sqrt(nl_mean) + 4.0) / kChunk);
+    rows = rows < k.cap / kChunk ? rows : k.cap / kChunk;
+    const double home_mean = k.kx_max * occ;
+    // tables, the list build's per-wave scratch (up to 16 waves) and static LDS
+    const size_t tables = stage_bytes(0, k.kx_max) + 16 * kMaxHomeSweep * sizeof(int) + 2048;
     const size_t room = c->lds_limit > tables ? c->lds_limit - tables : 0;
+    int nlcap = (int)ceil(1.3 * home_mean + 16.0) * (rows > 1 ? rows : 1);
     int scap = c->stage_cap > 0 ? c->stage_cap : (int)(1.5 * s_mean + 128.0);
-    const int scap_max = (int)(room / (3 * sizeof(double)));
+    if ((size_t)nlcap * sizeof(uint64_t) > room / 3) nlcap = (int)(room / 3 / sizeof(uint64_t));
+    const size_t room_s = room - (size_t)nlcap * sizeof(uint64_t);
+    const int scap_max = (int)(room_s / (3 * sizeof(double)));
     if (scap > scap_max) scap = scap_max;
     scap = scap / 64 * 64;
     k.scap = scap < 64 ? 64 : scap;
+    k.nlcap = nlcap < 0 ? 0 : nlcap;
     c->tile_cells = cells;
     k.nblk_force = force_blocks(k);
 }
@@ -161,6 +173,7 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
     b[R_CELL_OF] = b[R_SLOT] = b[R_ORDER] = b[R_TMP] = sizeof(int32_t) * n;
     b[R_NL] = sizeof(uint16_t) * (size_t)cap * npad;
     b[R_NL_COUNT] = sizeof(int32_t) * npad;
+    b[R_TILE_ROWS] = nl ? sizeof(int32_t) * ncell : 0;  // tiles never outnumber cells
     b[R_XR] = b[R_YR] = b[R_ZR] = nl ? sizeof(double) * n : 0;
     const size_t perm = p.reorder ? 1 : 0;
     b[R_SX] = b[R_SY] = b[R_SZ] = b[R_SVX] = b[R_SVY] = b[R_SVZ] = perm * sizeof(double) * n;
@@ -282,6 +295,7 @@ extern "C" md_status md_bind(md_ctx* c, const md_buffers* bf, void* stream)
     k.tmp = static_cast<int32_t*>(at(R_TMP));
     k.nl64 = static_cast<uint64_t*>(at(R_NL));
     k.nl_count = static_cast<int32_t*>(at(R_NL_COUNT));
+    k.tile_rows = static_cast<int32_t*>(at(R_TILE_ROWS));
     k.xr = static_cast<double*>(at(R_XR));
     k.yr = static_cast<double*>(at(R_YR));
     k.zr = static_cast<double*>(at(R_ZR));

@@ -1,12 +1,12 @@
 // md_forces.hip -- step F1 of section 2.3 (and the per-workgroup part of F2).
 //
-// Neighbor-list mode: one workgroup per tile (md_tiles.h).  `lanes` lanes
-// per home atom walk its row of the neighbor matrix (lane s takes chunks s,
-// s+lanes, ...; a chunk is 4 entries).  The first `batch` chunks of every
-// lane are requested as soon as the tile's cell tables are known, so they
-// arrive while the tile's 27-cell neighborhoods are being staged in LDS;
-// the partners are then gathered from LDS and the force on the home atom
-// alone is accumulated.  Every pair is met twice,
+// Neighbor-list mode: one workgroup per tile (md_tiles.h).  After the
+// tile's cell tables are known, one round of loads brings the tile's 27-cell
+// neighborhoods and its rows of the neighbor matrix (the chunk rows its
+// longest list uses) into LDS; `lanes` lanes per home atom then walk the
+// atom's list (lane s takes chunks s, s+lanes, ...; a chunk is 4 entries),
+// gather the partners from LDS and accumulate the force on the home atom
+// alone.  Every pair is met twice,
 // once from each side, so no atomics are needed (the paper's choice).
 // Pairs at r^2 >= r_cut^2 are skipped.  Separations take the minimum image
 // from the wrap bits carried by each entry (section 4.1, factor (4)); tiles
@@ -79,87 +79,108 @@ __device__ __forceinline__ T lane_group_sum(T v)
     return v;
 }
 
-// Entries of one 4-entry chunk.  Entries past the list length are masked
-// (and their index clamped: the tail of a chunk may hold a stale value).
-template <bool kFlags, bool kFits, typename Acc>
+// The 4 entries of one chunk.  kMask = false: partners from LDS, padded
+// entries point at the sentinel atom, nothing needs masking (wrap-bit image
+// modes only).  kMask = true: entries past the list are masked; with
+// kFits = false the partners come from global memory.
+template <int kImage, bool kFits, bool kMask, typename Acc>
 __device__ __forceinline__ void chunk_pairs(const KParams& p, const Stage& s, uint64_t ch,
                                             int mbase, int cnt, double xi, double yi, double zi,
                                             Acc& a)
 {
 #pragma unroll
     for (int k = 0; k < kChunk; ++k) {
-        const bool valid = mbase + k < cnt;
-        const uint32_t v = valid ? (uint32_t)(ch >> (16 * k)) & 0xffffu : 0u;
-        const int e = (int)(v & kEntryMask);
+        const uint32_t v = (uint32_t)(ch >> (16 * k)) & 0xffffu;
+        const bool valid = !kMask || mbase + k < cnt;
+        int e = (int)(v & kEntryMask);
         double xj, yj, zj;
         if (kFits) {
+            if (kMask) e = valid ? e : 0;
             xj = s.xs[e];
             yj = s.ys[e];
             zj = s.zs[e];
         } else {
-            const int j = staged_slot(p, s, e < s.total ? e : 0);
+            const int j = staged_slot(p, s, valid && e < s.total ? e : 0);
             xj = p.x[j];
             yj = p.y[j];
             zj = p.z[j];
         }
         double dx = xi - xj, dy = yi - yj, dz = zi - zj;
-        image<kFlags>(p, (int)(v >> kEntryBits), dx, dy, dz);
+        image<kImage>(p, (int)(v >> kEntryBits), dx, dy, dz);
         const double r2 = dist2(dx, dy, dz);
         if (valid && r2 < p.rc2) pair_acc(p, dx, dy, dz, r2, a);
     }
 }
 
-// Chunks c = sub + LANES*j of one home atom: the first PF were fetched into
-// `pre` before the tile was staged; the rest are read here.
-template <int LANES, int PF, bool kFlags, bool kFits, typename Acc>
-__device__ __forceinline__ void walk_tile_list(const KParams& p, const Stage& s, int slot_i,
-                                               int sub, int cnt, const uint64_t (&pre)[PF],
-                                               double xi, double yi, double zi, Acc& a)
+// Chunks c = sub, sub+LANES, ... of one home atom, from the tile's rows in
+// LDS (nlc, row pitch nh) or, when they did not fit, from global memory.
+template <int LANES, int kImage, bool kFits, bool kMask, typename Acc>
+__device__ __forceinline__ void walk_tile_list(const KParams& p, const Stage& s,
+                                               const MD_LDS uint64_t* nlc, int nh, int h,
+                                               int slot_i, int sub, int cnt, double xi, double yi,
+                                               double zi, Acc& a)
 {
     const int nchunk = (cnt + kChunk - 1) / kChunk;
-#pragma unroll
-    for (int j = 0; j < PF; ++j) {
-        const int c = sub + LANES * j;
-        if (c < nchunk) chunk_pairs<kFlags, kFits>(p, s, pre[j], c * kChunk, cnt, xi, yi, zi, a);
+    if (nlc) {
+        for (int c = sub; c < nchunk; c += LANES)
+            chunk_pairs<kImage, kFits, kMask>(p, s, nlc[c * nh + h], c * kChunk, cnt, xi, yi,
+                                              zi, a);
+    } else {
+        const uint64_t* col = p.nl64 + slot_i;
+        for (int c = sub; c < nchunk; c += LANES)
+            chunk_pairs<kImage, kFits, kMask>(p, s, col[(int64_t)c * p.npad], c * kChunk, cnt,
+                                              xi, yi, zi, a);
     }
-    const uint64_t* col = p.nl64 + slot_i;
-    for (int c = sub + LANES * PF; c < nchunk; c += LANES)
-        chunk_pairs<kFlags, kFits>(p, s, col[(int64_t)c * p.npad], c * kChunk, cnt, xi, yi, zi, a);
 }
 
-template <typename F, typename Acc, int LANES, int PF>
+template <typename F, typename Acc, int LANES>
 __global__ void k_forces_tiles(KParams p)
 {
-    extern __shared__ char smem[];
+    extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ double red[(1024 / kWave) * 2];
-    const Tile g = tile_of(p, xcd_tile(blockIdx.x, gridDim.x));
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const Tile g = tile_of(p, t);
     Stage s = stage_layout(p, smem);
+    MD_LDS uint64_t* nlc_area = (MD_LDS uint64_t*)stage_end(p, s);
+    const int rows = p.tile_rows[t];
     stage_tables(p, g, s);
     const int nh = home_count(s), h0 = home_first_lds(s), slot0 = home_first_slot(s);
-    const bool flags = !tile_interior(p, g);
+    const int mode = image_mode(p, tile_interior(p, g));
+    const bool rows_fit = (int64_t)rows * nh <= p.nlcap;
+    // one round of loads: staged positions, the tile's list rows, list lengths
+    if (rows_fit) {
+        constexpr int U = 4;
+        const int n_items = rows * nh;
+        for (int i0 = threadIdx.x; i0 < n_items; i0 += U * blockDim.x) {
+            uint64_t v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = i0 + u * blockDim.x;
+                if (idx < n_items) {
+                    const int c = idx / nh, h = idx - c * nh;
+                    v[u] = p.nl64[(int64_t)c * p.npad + atom_at(p, slot0 + h)];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = i0 + u * blockDim.x;
+                if (idx < n_items) nlc_area[idx] = v[u];
+            }
+        }
+    }
+    stage_positions(p, s);
+    __syncthreads();
+    const MD_LDS uint64_t* nlc = rows_fit ? nlc_area : nullptr;
     const int per_pass = blockDim.x / LANES;
     const int sub = threadIdx.x % LANES;
     double e[2] = {0.0, 0.0};
     for (int hb = 0; hb < nh; hb += per_pass) {
         const int h = hb + threadIdx.x / LANES;
-        // the list's length and first chunks are fetched before the positions
-        // are staged, so both round trips overlap
-        int slot_i = 0, cnt = 0;
-        uint64_t pre[PF];
+        Acc a;
+        int slot_i = 0;
         if (h < nh) {
             slot_i = atom_at(p, slot0 + h);
-            cnt = p.nl_count[slot_i];
-            const uint64_t* col = p.nl64 + slot_i;
-            const int nrow = p.cap / kChunk;
-#pragma unroll
-            for (int j = 0; j < PF; ++j) {
-                const int c = sub + LANES * j;
-                pre[j] = c < nrow ? col[(int64_t)c * p.npad] : 0;
-            }
-        }
-        if (hb == 0) stage_positions(p, s);
-        Acc a;
-        if (h < nh) {
+            const int cnt = p.nl_count[slot_i];
             double xi, yi, zi;
             if (s.fits) {
                 xi = s.xs[h0 + h];
@@ -170,13 +191,17 @@ __global__ void k_forces_tiles(KParams p)
                 yi = p.y[slot_i];
                 zi = p.z[slot_i];
             }
-            if (s.fits) {
-                if (flags)
-                    walk_tile_list<LANES, PF, true, true>(p, s, slot_i, sub, cnt, pre, xi, yi, zi, a);
+            if (!s.fits) {
+                if (mode == 2)
+                    walk_tile_list<LANES, 2, false, true>(p, s, nlc, nh, h, slot_i, sub, cnt, xi, yi, zi, a);
                 else
-                    walk_tile_list<LANES, PF, false, true>(p, s, slot_i, sub, cnt, pre, xi, yi, zi, a);
+                    walk_tile_list<LANES, 1, false, true>(p, s, nlc, nh, h, slot_i, sub, cnt, xi, yi, zi, a);
+            } else if (mode == 0) {
+                walk_tile_list<LANES, 0, true, false>(p, s, nlc, nh, h, slot_i, sub, cnt, xi, yi, zi, a);
+            } else if (mode == 1) {
+                walk_tile_list<LANES, 1, true, false>(p, s, nlc, nh, h, slot_i, sub, cnt, xi, yi, zi, a);
             } else {
-                walk_tile_list<LANES, PF, true, false>(p, s, slot_i, sub, cnt, pre, xi, yi, zi, a);
+                walk_tile_list<LANES, 2, true, true>(p, s, nlc, nh, h, slot_i, sub, cnt, xi, yi, zi, a);
             }
         }
         if (LANES > 1) {
@@ -274,25 +299,15 @@ __global__ void k_forces_cells(KParams p)
     }
 }
 
-template <typename F, typename Acc, int LANES>
-static void launch_tiles_b(const KParams& p, dim3 g, dim3 t, size_t lds, hipStream_t s)
-{
-    switch (p.force_batch) {
-        case 1: hipLaunchKernelGGL((k_forces_tiles<F, Acc, LANES, 1>), g, t, lds, s, p); break;
-        case 4: hipLaunchKernelGGL((k_forces_tiles<F, Acc, LANES, 4>), g, t, lds, s, p); break;
-        default: hipLaunchKernelGGL((k_forces_tiles<F, Acc, LANES, 2>), g, t, lds, s, p); break;
-    }
-}
-
 template <typename F, typename Acc>
 static void launch_tiles(const KParams& p, hipStream_t s)
 {
     const dim3 g(p.n_tiles), t(p.force_block);
-    const size_t lds = stage_bytes(p.scap, p.kx_max);
+    const size_t lds = stage_bytes(p.scap, p.kx_max) + sizeof(uint64_t) * (size_t)p.nlcap;
     switch (p.force_lanes) {
-        case 2: launch_tiles_b<F, Acc, 2>(p, g, t, lds, s); break;
-        case 4: launch_tiles_b<F, Acc, 4>(p, g, t, lds, s); break;
-        default: launch_tiles_b<F, Acc, 1>(p, g, t, lds, s); break;
+        case 2: hipLaunchKernelGGL((k_forces_tiles<F, Acc, 2>), g, t, lds, s, p); break;
+        case 4: hipLaunchKernelGGL((k_forces_tiles<F, Acc, 4>), g, t, lds, s, p); break;
+        default: hipLaunchKernelGGL((k_forces_tiles<F, Acc, 1>), g, t, lds, s, p); break;
     }
 }
 

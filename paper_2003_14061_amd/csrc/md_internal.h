@@ -47,6 +47,7 @@ struct KParams {
     int32_t *cell_count, *cell_start, *cell_of, *slot, *order, *tmp;
     uint64_t* nl64;       // list chunks: 4 x 16-bit entries, chunk c of slot k at c*npad + k
     int32_t* nl_count;
+    int32_t* tile_rows;   // per tile: list chunk rows its longest list uses (set by the list build)
     double *xr, *yr, *zr;
     double *sx, *sy, *sz, *svx, *svy, *svz, *sfx, *sfy, *sfz;  // permutation scratch
     int32_t *sid, *scell;
@@ -65,6 +66,7 @@ struct KParams {
     // tiling of the neighbor-list mode: rows of nc cells cut into tiles_per_row tiles
     int32_t tiles_per_row, kx_max, n_tiles;
     int32_t scap;           // staged atoms a workgroup's LDS holds
+    int32_t nlcap;          // list chunks of a tile the force pass's LDS holds
 };
 
 // Largest number of force-pass workgroups any tuning can ask for.

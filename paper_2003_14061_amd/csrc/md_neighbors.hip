@@ -21,14 +21,25 @@
 
 namespace md {
 
-// LDS bytes of the list build: the staged tile plus per-wave list counters.
+// LDS bytes of the list build: the staged tile plus one int per wave.
 inline size_t nl_lds_bytes(const KParams& p)
 {
-    return stage_bytes(p.scap, p.kx_max) + sizeof(int) * (p.nl_block / kWave) * kMaxHomeSweep;
+    return stage_bytes(p.scap, p.kx_max) + sizeof(int) * (p.nl_block / kWave);
 }
 
-template <bool kFlags>
-__device__ void nl_home_cell(const KParams& p, const Stage& s, int q, int* mh)
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// One home cell q of the tile, by one wave.  Home atoms are taken 64 at a
+// time; lane L keeps home atom h0+L's position and list length in
+// registers, read by the whole wave with readlane while it tests 64
+// candidates at once.  Returns the chunk rows of the cell's longest list.
+template <int kImage>
+__device__ __forceinline__ int nl_home_cell(const KParams& p, const Stage& s, int q)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int home_t = 4 * s.stride + q;
@@ -42,15 +53,29 @@ __device__ void nl_home_cell(const KParams& p, const Stage& s, int q, int* mh)
         wa[sg] = s.off[sg * s.stride + q - 1];
         wp[sg + 1] = wp[sg] + (s.off[sg * s.stride + q + 2] - wa[sg]);
     }
-    const int total = wp[9];
+    const int ncand = wp[9];
     const uint32_t cap = (uint32_t)p.cap;
     uint16_t* nl16 = reinterpret_cast<uint16_t*>(p.nl64);
-    for (int h0 = hb; h0 < he; h0 += kMaxHomeSweep) {
-        const int h1 = he < h0 + kMaxHomeSweep ? he : h0 + kMaxHomeSweep;
-        for (int h = h0 + lane; h < h1; h += kWave) mh[h - h0] = 0;
-        for (int k0 = 0; k0 < total; k0 += kWave) {
+    int rows = 0;
+    for (int h0 = hb; h0 < he; h0 += kWave) {
+        const int nhs = he - h0 < kWave ? he - h0 : kWave;
+        // this lane's home atom
+        const int hl = h0 + (lane < nhs ? lane : 0);
+        const int slot_l = atom_at(p, hslot0 + (hl - hb));
+        double hx, hy, hz;
+        if (s.fits) {
+            hx = s.xs[hl];
+            hy = s.ys[hl];
+            hz = s.zs[hl];
+        } else {
+            hx = p.x[slot_l];
+            hy = p.y[slot_l];
+            hz = p.z[slot_l];
+        }
+        int mcnt = 0;
+        for (int k0 = 0; k0 < ncand; k0 += kWave) {
             const int k = k0 + lane;
-            const bool valid = k < total;
+            const bool valid = k < ncand;
             int sg = 0;
 #pragma unroll
             for (int j = 1; j < 9; ++j) sg += k >= wp[j] ? 1 : 0;
@@ -79,91 +104,96 @@ __device__ void nl_home_cell(const KParams& p, const Stage& s, int q, int* mh)
                 zj = p.z[j];
             }
             const uint32_t enc = (uint32_t)e | ((uint32_t)fl << kEntryBits);
-            for (int h = h0; h < h1; ++h) {
-                double xi, yi, zi;
-                if (s.fits) {
-                    xi = s.xs[h];
-                    yi = s.ys[h];
-                    zi = s.zs[h];
-                } else {
-                    const int i = atom_at(p, hslot0 + (h - hb));
-                    xi = p.x[i];
-                    yi = p.y[i];
-                    zi = p.z[i];
-                }
+            for (int hh = 0; hh < nhs; ++hh) {
+                const double xi = readlane_f64(hx, hh), yi = readlane_f64(hy, hh),
+                             zi = readlane_f64(hz, hh);
                 double dx = xi - xj, dy = yi - yj, dz = zi - zj;
-                image<kFlags>(p, fl, dx, dy, dz);
-                const bool hit = valid && dist2(dx, dy, dz) < p.rl2 && e != h;
+                image<kImage>(p, fl, dx, dy, dz);
+                const bool hit = valid && dist2(dx, dy, dz) < p.rl2 && e != h0 + hh;
                 const uint64_t mask = __ballot(hit);
                 if (mask) {
-                    const int base = mh[h - h0];
+                    const int base = __builtin_amdgcn_readlane(mcnt, hh);
                     if (hit) {
                         const uint32_t m = (uint32_t)base + __builtin_amdgcn_mbcnt_hi(
                             (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
                         if (m < cap) {
-                            const int slot_i = atom_at(p, hslot0 + (h - hb));
+                            const int slot_i =
+                                __builtin_amdgcn_readlane(slot_l, hh);
                             nl16[((int64_t)(m / kChunk) * p.npad + slot_i) * kChunk + m % kChunk] =
                                 (uint16_t)enc;
                         }
                     }
-                    if (lane == 0) mh[h - h0] = base + __popcll(mask);
+                    if (lane == hh) mcnt = base + (int)__popcll(mask);
                 }
             }
         }
-        // lengths, displacement references, overflow
-        int mmax = 0;
-        for (int h = h0 + lane; h < h1; h += kWave) {
-            const int m = mh[h - h0];
-            const int slot_i = atom_at(p, hslot0 + (h - hb));
-            p.nl_count[slot_i] = m < p.cap ? m : p.cap;
-            double xi, yi, zi;
-            if (s.fits) {
-                xi = s.xs[h];
-                yi = s.ys[h];
-                zi = s.zs[h];
-            } else {
-                xi = p.x[slot_i];
-                yi = p.y[slot_i];
-                zi = p.z[slot_i];
-            }
-            p.xr[slot_i] = xi;
-            p.yr[slot_i] = yi;
-            p.zr[slot_i] = zi;
-            mmax = m > mmax ? m : mmax;
+        // lengths, sentinel padding of the last chunk, displacement references
+        int m = 0;
+        if (lane < nhs) {
+            m = mcnt;
+            const int stored = m < p.cap ? m : p.cap;
+            p.nl_count[slot_l] = stored;
+            for (int mm = stored; mm % kChunk != 0; ++mm)
+                nl16[((int64_t)(mm / kChunk) * p.npad + slot_l) * kChunk + mm % kChunk] =
+                    (uint16_t)s.total;
+            p.xr[slot_l] = hx;
+            p.yr[slot_l] = hy;
+            p.zr[slot_l] = hz;
+            const int r = (stored + kChunk - 1) / kChunk;
+            rows = r > rows ? r : rows;
         }
-        mmax = wave_max(mmax);
+        const int mmax = wave_max(m);
         if (lane == 0 && mmax > 0) {
             atomicMax(&p.dev->max_nl, mmax);
             if (mmax > p.cap) atomicOr(&p.dev->flags, (int)MD_FLAG_NL_OVERFLOW);
         }
     }
+    return rows;
 }
 
 __global__ void k_nl_tiles(KParams p, int force)
 {
     if (!force && !p.dev->rebuild) return;
-    extern __shared__ char smem[];
-    const Tile g = tile_of(p, xcd_tile(blockIdx.x, gridDim.x));
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const Tile g = tile_of(p, t);
     Stage s = stage_layout(p, smem);
-    int* mh_all = s.scan + kWave;
+    MD_LDS int* wrows = (MD_LDS int*)stage_end(p, s);
     stage_tables(p, g, s);
-    if (s.total > kMaxStaged) {
-        // the 13-bit entry cannot address this tile: report it as an overflow
+    if (s.total >= kMaxStaged) {
+        // the 13-bit entry cannot address this tile (and its sentinel): report it
+        // as an overflow
         const int nh = home_count(s);
         for (int h = threadIdx.x; h < nh; h += blockDim.x)
             p.nl_count[atom_at(p, home_first_slot(s) + h)] = 0;
-        if (threadIdx.x == 0) atomicOr(&p.dev->flags, (int)MD_FLAG_NL_OVERFLOW);
+        if (threadIdx.x == 0) {
+            atomicOr(&p.dev->flags, (int)MD_FLAG_NL_OVERFLOW);
+            p.tile_rows[t] = 0;
+        }
         return;
     }
     stage_positions(p, s);
+    __syncthreads();
     const int wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    int* mh = mh_all + wid * kMaxHomeSweep;
-    const bool flags = !tile_interior(p, g);
+    const int mode = image_mode(p, tile_interior(p, g));
+    int rows = 0;
     for (int q = 1 + wid; q <= g.kx; q += nw) {
-        if (flags)
-            nl_home_cell<true>(p, s, q, mh);
+        int r;
+        if (mode == 0)
+            r = nl_home_cell<0>(p, s, q);
+        else if (mode == 1)
+            r = nl_home_cell<1>(p, s, q);
         else
-            nl_home_cell<false>(p, s, q, mh);
+            r = nl_home_cell<2>(p, s, q);
+        rows = r > rows ? r : rows;
+    }
+    rows = wave_max(rows);
+    if ((threadIdx.x & (kWave - 1)) == 0) wrows[wid] = rows;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int r = 0;
+        for (int w = 0; w < nw; ++w) r = wrows[w] > r ? wrows[w] : r;
+        p.tile_rows[t] = r;
     }
 }
 
@@ -171,7 +201,7 @@ __global__ void k_nl_tiles(KParams p, int force)
 // -1 elsewhere.
 __global__ void k_nl_export(KParams p, int32_t* out)
 {
-    extern __shared__ char smem[];
+    extern __shared__ __attribute__((aligned(16))) char smem[];
     const Tile g = tile_of(p, xcd_tile(blockIdx.x, gridDim.x));
     Stage s = stage_layout(p, smem);
     stage_tables(p, g, s);

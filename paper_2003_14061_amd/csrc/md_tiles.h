@@ -28,6 +28,8 @@
 
 namespace md {
 
+#define MD_LDS __attribute__((address_space(3)))
+
 constexpr int kEntryBits = 13;
 constexpr int kEntryMask = (1 << kEntryBits) - 1;
 constexpr int kMaxStaged = 1 << kEntryBits;  // virtual layout limit
@@ -57,42 +59,59 @@ __device__ __forceinline__ Tile tile_of(const KParams& p, int t)
     return g;
 }
 
-// LDS view of one staged tile.
+// LDS view of one staged tile.  Entry `total` of xs, ys, zs holds a sentinel
+// atom far outside the box; list chunks are padded with its index, so a
+// padded entry never falls inside the cutoff.
 struct Stage {
-    double *xs, *ys, *zs;  // [scap]
-    int* off;              // [ntab + 1] LDS offset of each staged cell
-    int* slot;             // [ntab] global slot of each staged cell's first atom
-    int* flag;             // [ntab] wrap bits
-    int* scan;             // [kWave] scratch
+    MD_LDS double *xs, *ys, *zs;  // [scap]
+    MD_LDS int* off;              // [ntab + 1] LDS offset of each staged cell
+    MD_LDS int* slot;             // [ntab] global slot of each staged cell's first atom
+    MD_LDS int* flag;             // [ntab] wrap bits
+    MD_LDS int* scan;             // [kWave] scratch
     int ntab, stride, total;
-    bool fits;
+    bool fits;                    // total + 1 <= scap: positions (and sentinel) staged
 };
 
-// Dynamic LDS bytes a tiled kernel needs.
-inline size_t stage_bytes(int scap, int kx_max)
+constexpr double kSentinel = 1.0e30;
+
+// Ints of the table region, rounded up to 16 bytes so that whatever follows
+// it (8-byte list chunks) stays aligned.
+__host__ __device__ __forceinline__ int stage_table_ints(int kx_max)
 {
     const int ntab = 9 * (kx_max + 2);
-    return sizeof(double) * 3 * (size_t)scap + sizeof(int) * (3 * (size_t)ntab + 1 + kWave);
+    return (3 * ntab + 1 + kWave + 3) / 4 * 4;
+}
+
+// Dynamic LDS bytes of the staged tile (what follows it starts 16-byte aligned).
+inline size_t stage_bytes(int scap, int kx_max)
+{
+    return sizeof(double) * 3 * (size_t)scap + sizeof(int) * (size_t)stage_table_ints(kx_max);
 }
 
 __device__ __forceinline__ Stage stage_layout(const KParams& p, char* smem)
 {
     Stage s;
-    s.xs = reinterpret_cast<double*>(smem);
+    s.xs = (MD_LDS double*)smem;
     s.ys = s.xs + p.scap;
     s.zs = s.ys + p.scap;
     const int ntab_max = 9 * (p.kx_max + 2);
-    s.off = reinterpret_cast<int*>(s.zs + p.scap);
+    s.off = (MD_LDS int*)(s.zs + p.scap);
     s.slot = s.off + ntab_max + 1;
     s.flag = s.slot + ntab_max;
     s.scan = s.flag + ntab_max;
     return s;
 }
 
+// First byte after the staged tile's LDS (16-byte aligned).
+__device__ __forceinline__ MD_LDS char* stage_end(const KParams& p, const Stage& s)
+{
+    return (MD_LDS char*)(s.off + stage_table_ints(p.kx_max));
+}
+
 // Cell tables of tile g: slots, wrap bits and LDS offsets of the staged
 // cells (one round of global loads, then a workgroup scan).  Every thread of
 // the workgroup must call it.
-__device__ void stage_tables(const KParams& p, const Tile& g, Stage& s)
+__device__ __forceinline__ void stage_tables(const KParams& p, const Tile& g, Stage& s)
 {
     const int nc = p.nc;
     s.stride = g.kx + 2;
@@ -133,56 +152,92 @@ __device__ void stage_tables(const KParams& p, const Tile& g, Stage& s)
     }
     if (threadIdx.x == 0) s.off[s.ntab] = carry;
     s.total = carry;
-    s.fits = carry <= p.scap;
+    s.fits = carry < p.scap;
     __syncthreads();
 }
 
-// Positions of the staged atoms into LDS (when they fit).  Every thread of
-// the workgroup must call it.
-__device__ void stage_positions(const KParams& p, const Stage& s)
+// Last staged cell t with off[t] <= k (k < total), i.e. the cell holding
+// staged entry k (empty cells are skipped by taking the last match).
+__device__ __forceinline__ int staged_cell(const Stage& s, int k)
+{
+    int lo = 0, hi = s.ntab - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s.off[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Positions of the staged atoms into LDS (when they fit), plus the sentinel.
+// Each thread takes entries tid, tid + blockDim, ... four at a time, so that
+// several loads are in flight per thread.  No barrier: the caller syncs.
+__device__ __forceinline__ void stage_positions(const KParams& p, const Stage& s)
 {
     if (!s.fits) return;
-    for (int k = threadIdx.x; k < s.total; k += blockDim.x) {
-        int lo = 0, hi = s.ntab - 1;  // last t with off[t] <= k
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s.off[mid] <= k) lo = mid; else hi = mid - 1;
+    constexpr int U = 4;
+    for (int k0 = threadIdx.x; k0 < s.total; k0 += U * blockDim.x) {
+        double vx[U], vy[U], vz[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * blockDim.x;
+            if (k < s.total) {
+                const int t = staged_cell(s, k);
+                const int j = atom_at(p, s.slot[t] + (k - s.off[t]));
+                vx[u] = p.x[j];
+                vy[u] = p.y[j];
+                vz[u] = p.z[j];
+            }
         }
-        const int j = atom_at(p, s.slot[lo] + (k - s.off[lo]));
-        s.xs[k] = p.x[j];
-        s.ys[k] = p.y[j];
-        s.zs[k] = p.z[j];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * blockDim.x;
+            if (k < s.total) {
+                s.xs[k] = vx[u];
+                s.ys[k] = vy[u];
+                s.zs[k] = vz[u];
+            }
+        }
     }
-    __syncthreads();
+    if (threadIdx.x == 0) {
+        s.xs[s.total] = kSentinel;
+        s.ys[s.total] = kSentinel;
+        s.zs[s.total] = kSentinel;
+    }
 }
 
 // Atom (storage slot) of staged entry e.
 __device__ __forceinline__ int staged_slot(const KParams& p, const Stage& s, int e)
 {
-    int lo = 0, hi = s.ntab - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s.off[mid] <= e) lo = mid; else hi = mid - 1;
-    }
-    return atom_at(p, s.slot[lo] + (e - s.off[lo]));
+    const int t = staged_cell(s, e);
+    return atom_at(p, s.slot[t] + (e - s.off[t]));
 }
 
-// Minimum image of a staged pair from the raw difference and wrap bits
-// (at least 5 cells per side), or by rint when the grid is smaller.
-template <bool kFlags>
+// Minimum image of a staged pair.  kImage: 0 -- no wrap anywhere in the
+// tile, the raw difference is exact; 1 -- at least 5 cells per side: the raw
+// difference, minus L*sign(d) in each flagged coordinate; 2 -- fewer than 5
+// cells per side: d - L*rint(d/L) in every coordinate.
+template <int kImage>
 __device__ __forceinline__ void image(const KParams& p, int fl, double& dx, double& dy,
                                       double& dz)
 {
 #pragma clang fp contract(off)
-    if (p.nc < 5) {
+    if (kImage == 2) {
         dx = minimg(dx, p.L, p.invL);
         dy = minimg(dy, p.L, p.invL);
         dz = minimg(dz, p.L, p.invL);
-    } else if (kFlags) {
-        if (fl & 1) dx = dx > 0.0 ? dx - p.L : dx + p.L;
-        if (fl & 2) dy = dy > 0.0 ? dy - p.L : dy + p.L;
-        if (fl & 4) dz = dz > 0.0 ? dz - p.L : dz + p.L;
+    } else if (kImage == 1) {
+        if (fl) {
+            if (fl & 1) dx = dx > 0.0 ? dx - p.L : dx + p.L;
+            if (fl & 2) dy = dy > 0.0 ? dy - p.L : dy + p.L;
+            if (fl & 4) dz = dz > 0.0 ? dz - p.L : dz + p.L;
+        }
     }
+}
+
+// Which image rule a tile needs (see image()).
+__device__ __forceinline__ int image_mode(const KParams& p, bool interior)
+{
+    return p.nc < 5 ? 2 : (interior ? 0 : 1);
 }
 
 // Home atoms of a tile: the kx cells q = 1..kx of the middle row (s = 4),
