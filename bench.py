@@ -12,8 +12,8 @@ Prints one JSON line.  With --gpus above 1 it exits: the build targets one
 GPU.
 """
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -23,6 +23,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "atom-steps/sec at N=2.05M LJ (FP64 vs FP32-mixed); adjoint/forward time ratio"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6   # MI355X dense FP64 vector
+FP32_PEAK_TFS = 157.3  # MI355X FP32 vector
+FORCE_SOURCES = ("paper_2003_14061_amd/csrc/md_forces.hip", "paper_2003_14061_amd/csrc/md_tiles.h",
+                 "paper_2003_14061_amd/csrc/md_device.h", "paper_2003_14061_amd/csrc/md_internal.h")
+TRAFFIC_FILE = "profiles/k_forces_tiles_lj_2048k_traffic.txt"
 
 
 def parse():
@@ -41,9 +46,46 @@ def parse():
 
 def force_bytes_per_atom(mean_nl, precision):
     """Algorithmic HBM bytes of one force pass per atom: the list row
-    (4 B per entry) and its length (4 B), the atom's own position (24 B),
-    and the force written back (24 B in FP64, 12 B in FP32)."""
-    return 4.0 * mean_nl + 4.0 + 24.0 + (24.0 if precision == "fp64" else 12.0)
+    (2 B per 16-bit entry) and its length (4 B), the atom's own position
+    (24 B), and the force written back (24 B in FP64, 12 B in FP32)."""
+    return 2.0 * mean_nl + 4.0 + 24.0 + (24.0 if precision == "fp64" else 12.0)
+
+
+def force_flops_per_atom(mean_nl, mean_in_range):
+    """Algorithmic floating-point operations of one force pass per atom:
+    8 per list entry (separation and squared distance) and 19 per pair
+    inside the cutoff (reciprocal, powers, force, energy and virial sums)."""
+    return 8.0 * mean_nl + 19.0 * mean_in_range
+
+
+def force_sources_hash():
+    h = hashlib.sha256()
+    for f in FORCE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n_atoms, precision):
+    """HBM bytes per force-pass launch from the committed rocprofv3 counter
+    summary, or None when it is missing, for another workload or precision,
+    or taken on other kernel sources."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if (kv.get("sources_sha256") != force_sources_hash() or
+                int(kv.get("n_atoms", -1)) != n_atoms or kv.get("precision") != precision):
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def run_gpu(w, precision, steps, warmup):
@@ -69,6 +111,7 @@ def run_gpu(w, precision, steps, warmup):
     e1 = (o1["U"] + o1["K"]) / w.n
     cnt = sim.nl_counts()
     mean_nl = float(cnt[: w.n].mean())
+    mean_in_range = in_range_pairs(sim, w)
     wall = t1 - t0
     res = {
         "value": w.n * steps / wall,
@@ -81,14 +124,55 @@ def run_gpu(w, precision, steps, warmup):
         "T_end": o1["T"],
     }
     bpa = force_bytes_per_atom(mean_nl, precision)
-    achieved = bpa * w.n / (res["force_ms_avg"] * 1e-3) / 1e9
+    t_force = res["force_ms_avg"] * 1e-3
+    achieved = bpa * w.n / t_force / 1e9
+    flops = force_flops_per_atom(mean_nl, mean_in_range) * w.n / t_force / 1e12
+    alu_peak = FP64_PEAK_TFS if precision == "fp64" else FP32_PEAK_TFS
     res["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                       "traffic": None, "kernel": "k_forces",
-                       "bytes_per_atom": round(bpa, 2)}
+                       "traffic": measured_traffic(w.n, precision),
+                       "kernel": "k_forces_tiles", "bytes_per_atom": round(bpa, 2),
+                       "units_per_launch": w.n,
+                       "alu": {"achieved": round(flops, 2), "peak": alu_peak, "unit": "TFLOP/s",
+                               "frac": round(flops / alu_peak, 4),
+                               "flops_per_atom": round(force_flops_per_atom(mean_nl,
+                                                                            mean_in_range), 1)}}
+    res["mean_in_range"] = mean_in_range
     del sim
     torch.cuda.synchronize()
     return res
+
+
+def in_range_pairs(sim, w, sample=20000):
+    """Mean number of list partners inside r_cut, on a strided sample of
+    atoms (host arithmetic on the current state; counts only, for the flop
+    model)."""
+    import numpy as np
+
+    pos = np.mod(sim.state()["pos"], w.L)
+    idx = np.linspace(0, w.n - 1, min(sample, w.n)).astype(np.int64)
+    L, rc2 = w.L, w.r_cut * w.r_cut
+    tot = 0
+    # cell binning of the whole box for the sample's neighborhoods
+    nc = max(int(L // w.r_cut), 3)
+    cell = np.clip((pos * (nc / L)).astype(np.int64), 0, nc - 1)
+    key = (cell[:, 2] * nc + cell[:, 1]) * nc + cell[:, 0]
+    order = np.argsort(key, kind="stable")
+    start = np.searchsorted(key[order], np.arange(nc ** 3 + 1))
+    for i in idx:
+        cx, cy, cz = cell[i]
+        js = []
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    c = (((cz + dz) % nc) * nc + (cy + dy) % nc) * nc + (cx + dx) % nc
+                    js.append(order[start[c]:start[c + 1]])
+        js = np.concatenate(js)
+        d = pos[js] - pos[i]
+        d -= L * np.rint(d / L)
+        r2 = (d * d).sum(1)
+        tot += int(((r2 < rc2) & (js != i)).sum())
+    return tot / len(idx)
 
 
 def run_cpu(w, steps):
@@ -171,6 +255,7 @@ def main():
         "cpu_baseline": cpu,
         "rebuilds": fp64["rebuilds"],
         "mean_nl": round(fp64["mean_nl"], 2),
+        "mean_in_range": round(fp64["mean_in_range"], 2),
         "energy_drift_per_atom": fp64["energy_drift_per_atom"],
         "force_ms_avg": round(fp64["force_ms_avg"], 5),
     }

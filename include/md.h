@@ -220,14 +220,16 @@ md_status md_history(md_ctx* ctx, md_record* out, int32_t max_records, int32_t* 
  * parity tolerances; the force pass's summation order depends on
  * force_lanes, so bitwise reproducibility holds for a fixed tuning. */
 typedef struct {
-    int32_t force_lanes;   /* lanes sharing one atom's list in the force pass: 1, 2, 4 */
-    int32_t force_batch;   /* 4-entry list chunks each lane fetches ahead: 1, 2, 4 */
-    int32_t force_block;   /* threads per workgroup of the force pass: 64..1024, multiple of 64 */
-    int32_t nl_batch;      /* staged candidates each lane loads ahead in the list build: 1, 4 */
-    int32_t nl_block;      /* threads per workgroup of the list build: 64..1024, multiple of 64 */
-    int32_t tile_cells;    /* cells per tile along x in neighbor-list mode; 0 = from density */
-    int32_t stage_cap;     /* atoms a workgroup stages in LDS (0 = 1.5x the mean need); tiles
-                              that hold more read positions from global memory instead */
+    int32_t force_lanes;    /* lanes sharing one atom's list in the force pass: 1, 2, 4, 8 */
+    int32_t force_block;    /* threads per workgroup of the force pass: 64..1024, multiple of 64 */
+    int32_t nl_block;       /* threads per workgroup of the list build: 64..1024, multiple of 64;
+                               0 = one wave per cell of the widest tile */
+    int32_t tile_cells;     /* cells per tile along x in neighbor-list mode; 0 = enough for
+                               about 80% of the force workgroup's home-atom slots */
+    int32_t stage_cap;      /* atoms a workgroup stages in LDS (0 = 1.5x the mean need); tiles
+                               that hold more read positions from global memory instead */
+    int32_t integrate_grid; /* workgroups of the per-atom kernels (integration, observables):
+                               1..4096; 0 = 512 */
 } md_tuning;
 
 /* md_set_tuning: change the launch shape (host only; takes effect at the

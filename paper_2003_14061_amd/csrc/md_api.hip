@@ -23,7 +23,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 enum Region {
-    R_DEV, R_CELL_COUNT, R_CELL_START, R_CELL_OF, R_SLOT, R_ORDER, R_TMP, R_NL, R_NL_COUNT, R_TILE_ROWS,
+    R_DEV, R_CELL_COUNT, R_CELL_START, R_CELL_OF, R_SLOT, R_ORDER, R_TMP, R_NL, R_NL_COUNT,
     R_XR, R_YR, R_ZR, R_SX, R_SY, R_SZ, R_SVX, R_SVY, R_SVZ, R_SFX, R_SFY, R_SFZ, R_SID,
     R_SCELL, R_FPART, R_IPART, R_SCAN, R_HIST, R_COUNT
 };
@@ -39,6 +39,7 @@ struct md_ctx {
     size_t ws_bytes;
     hipStream_t stream = nullptr;
     bool bound = false, cells_ok = false, nl_ok = false, forces_ok = false;
+    int nl_block_req = 0;  // requested list-build workgroup size (0: one wave per tile cell)
     bool timing = false;
     std::vector<hipEvent_t> ev_free, ev_pending;  // pending holds start/stop pairs
     double timed_ms = 0.0;
@@ -64,46 +65,38 @@ extern "C" const char* md_status_str(int32_t st)
 }
 
 // Tiling of the neighbor-list mode: each row of nc cells is cut into
-// tiles_per_row tiles of about `cells` cells (0: enough cells for ~90% of a
-// workgroup's home-atom slots at the mean occupancy).  The LDS capacity
-// allows 1.5x the mean staged count, within the device's per-workgroup LDS.
+// tiles_per_row tiles of about `cells` cells (0: enough cells to fill about
+// 80% of the force workgroup's home-atom slots at the mean occupancy, so that
+// one pass of the workgroup covers the tile).  The LDS capacity allows 1.5x
+// the mean staged count, within the device's per-workgroup LDS.
 static void plan_tiles(md_ctx* c, int cells)
 {
     KParams& k = c->kp;
     const int nc = k.nc;
     const double occ = (double)k.n / ((double)nc * nc * nc);
     if (cells <= 0) {
-        const double home = 0.9 * k.force_block / k.force_lanes;
-        cells = (int)floor(home / (occ > 1e-9 ? occ : 1e-9) + 0.5);
+        const double home = 0.8 * k.force_block / k.force_lanes;
+        cells = (int)floor(home / (occ > 1e-9 ? occ : 1e-9));
     }
     const int kx_cap = nc < 128 ? nc : 128;
     cells = cells < 1 ? 1 : (cells > kx_cap ? kx_cap : cells);
     k.tiles_per_row = (nc + cells - 1) / cells;
     k.kx_max = (nc + k.tiles_per_row - 1) / k.tiles_per_row;
     k.n_tiles = nc * nc * k.tiles_per_row;
-    // LDS: the staged atoms (1.5x the mean need) and the tile's list chunks
-    // (1.3x the mean home atoms times the rows of a long list)
     const double s_mean = 9.0 * (k.kx_max + 2) * occ;
-    const double rl = sqrt(k.rl2);
-    const double nl_mean = 4.0 / 3.0 * M_PI * rl * rl * rl * occ / (c->geo.cell_width *
-                           c->geo.cell_width * c->geo.cell_width);
-    int rows = (int)ceil((nl_mean + 4.0 * sqrt(nl_mean) + 4.0) / kChunk);
-    rows = rows < k.cap / kChunk ? rows : k.cap / kChunk;
-    const double home_mean = k.kx_max * occ;
-    // tables, the list build's per-wave scratch (up to 16 waves) and static LDS
-    const size_t tables = stage_bytes(0, k.kx_max) + 16 * kMaxHomeSweep * sizeof(int) + 2048;
+    // tables, the list build's per-wave scratch and static LDS
+    const size_t tables = stage_bytes(0, k.kx_max) + 2048;
     const size_t room = c->lds_limit > tables ? c->lds_limit - tables : 0;
-    int nlcap = (int)ceil(1.3 * home_mean + 16.0) * (rows > 1 ? rows : 1);
     int scap = c->stage_cap > 0 ? c->stage_cap : (int)(1.5 * s_mean + 128.0);
-    if ((size_t)nlcap * sizeof(uint64_t) > room / 3) nlcap = (int)(room / 3 / sizeof(uint64_t));
-    const size_t room_s = room - (size_t)nlcap * sizeof(uint64_t);
-    const int scap_max = (int)(room_s / (3 * sizeof(double)));
+    const int scap_max = (int)(room / (3 * sizeof(double)));
     if (scap > scap_max) scap = scap_max;
     scap = scap / 64 * 64;
     k.scap = scap < 64 ? 64 : scap;
-    k.nlcap = nlcap < 0 ? 0 : nlcap;
     c->tile_cells = cells;
     k.nblk_force = force_blocks(k);
+    // list build: one wave per home cell of the widest tile unless set
+    const int nlb = c->nl_block_req > 0 ? c->nl_block_req : kWave * k.kx_max;
+    k.nl_block = nlb < kWave ? kWave : (nlb > 1024 ? 1024 : nlb);
 }
 
 static md_status hip_ok(hipError_t e) { return e == hipSuccess ? MD_OK : MD_ERR_HIP; }
@@ -173,14 +166,13 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
     b[R_CELL_OF] = b[R_SLOT] = b[R_ORDER] = b[R_TMP] = sizeof(int32_t) * n;
     b[R_NL] = sizeof(uint16_t) * (size_t)cap * npad;
     b[R_NL_COUNT] = sizeof(int32_t) * npad;
-    b[R_TILE_ROWS] = nl ? sizeof(int32_t) * ncell : 0;  // tiles never outnumber cells
     b[R_XR] = b[R_YR] = b[R_ZR] = nl ? sizeof(double) * n : 0;
     const size_t perm = p.reorder ? 1 : 0;
     b[R_SX] = b[R_SY] = b[R_SZ] = b[R_SVX] = b[R_SVY] = b[R_SVZ] = perm * sizeof(double) * n;
     b[R_SFX] = b[R_SFY] = b[R_SFZ] = perm * fsz * n;
     b[R_SID] = b[R_SCELL] = perm * sizeof(int32_t) * n;
     b[R_FPART] = sizeof(double) * 2 * (size_t)max_force_blocks(n, ncell);
-    b[R_IPART] = sizeof(double) * 8 * kIntegrateGrid;
+    b[R_IPART] = sizeof(double) * 8 * kIntegrateGridMax;
     b[R_SCAN] = sizeof(int32_t) * 2 * (size_t)ntile;
     b[R_HIST] = sizeof(md_record) * kHistCap;
     size_t o = 0;
@@ -230,11 +222,10 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
         k.inner_hi = 0.0;  // empty range: always take the minimum image
     }
     k.block = p.block;
-    k.force_lanes = 1;
-    k.force_batch = 2;
-    k.force_block = 256;
-    k.nl_batch = 4;
-    k.nl_block = 256;
+    k.force_lanes = 4;
+    k.force_block = 512;
+    c->nl_block_req = 0;
+    k.int_grid = kIntegrateGridDefault;
     plan_tiles(c, 0);
     *out = c;
     return MD_OK;
@@ -295,7 +286,6 @@ extern "C" md_status md_bind(md_ctx* c, const md_buffers* bf, void* stream)
     k.tmp = static_cast<int32_t*>(at(R_TMP));
     k.nl64 = static_cast<uint64_t*>(at(R_NL));
     k.nl_count = static_cast<int32_t*>(at(R_NL_COUNT));
-    k.tile_rows = static_cast<int32_t*>(at(R_TILE_ROWS));
     k.xr = static_cast<double*>(at(R_XR));
     k.yr = static_cast<double*>(at(R_YR));
     k.zr = static_cast<double*>(at(R_ZR));
@@ -495,18 +485,17 @@ static bool one_of(int v, std::initializer_list<int> set)
 extern "C" md_status md_set_tuning(md_ctx* c, const md_tuning* t)
 {
     if (!c || !t) return MD_ERR_ARG;
-    if (!one_of(t->force_lanes, {1, 2, 4}) || !one_of(t->force_batch, {1, 2, 4}) ||
-        !one_of(t->nl_batch, {1, 4}) || t->force_block % 64 != 0 || t->force_block < 64 ||
-        t->force_block > 1024 || t->nl_block % 64 != 0 || t->nl_block < 64 ||
-        t->nl_block > 1024 || t->tile_cells < 0 || t->stage_cap < 0)
+    if (!one_of(t->force_lanes, {1, 2, 4, 8}) || t->force_block % 64 != 0 ||
+        t->force_block < 64 || t->force_block > 1024 || t->nl_block % 64 != 0 ||
+        t->nl_block < 0 || t->nl_block > 1024 || t->tile_cells < 0 || t->stage_cap < 0 ||
+        t->integrate_grid < 0 || t->integrate_grid > kIntegrateGridMax)
         return MD_ERR_ARG;
     KParams& k = c->kp;
     const int old_tiles = k.n_tiles, old_cells = c->tile_cells;
     k.force_lanes = t->force_lanes;
-    k.force_batch = t->force_batch;
     k.force_block = t->force_block;
-    k.nl_batch = t->nl_batch;
-    k.nl_block = t->nl_block;
+    c->nl_block_req = t->nl_block;
+    k.int_grid = t->integrate_grid > 0 ? t->integrate_grid : kIntegrateGridDefault;
     c->stage_cap = t->stage_cap;
     plan_tiles(c, t->tile_cells);
     // the list encoding depends on the tiling
@@ -520,10 +509,9 @@ extern "C" md_status md_get_tuning(const md_ctx* c, md_tuning* t)
 {
     if (!c || !t) return MD_ERR_ARG;
     t->force_lanes = c->kp.force_lanes;
-    t->force_batch = c->kp.force_batch;
     t->force_block = c->kp.force_block;
-    t->nl_batch = c->kp.nl_batch;
     t->nl_block = c->kp.nl_block;
+    t->integrate_grid = c->kp.int_grid;
     t->tile_cells = c->tile_cells;
     t->stage_cap = c->kp.scap;
     return MD_OK;

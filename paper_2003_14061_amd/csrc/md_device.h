@@ -157,18 +157,26 @@ __device__ __forceinline__ int load_coherent(const int* p)
 // workgroup publishes its partial, bumps a counter, and the one that sees
 // the final count finishes the reduction.  Returns true in every thread of
 // that last workgroup.
+//
+// The partial must have been stored by thread 0: its counter increment is a
+// release at agent scope, which orders thread 0's own earlier stores before
+// it.  Only the last workgroup issues the matching acquire.  (On gfx950 an
+// agent-scope release writes back the XCD's L2 and an acquire invalidates
+// it, so a fence in every thread of every workgroup would cost far more than
+// the reduction itself.)
 __device__ __forceinline__ bool last_block(DevState* dev)
 {
     __shared__ int is_last;
-    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned t = atomicAdd(&dev->blocks_done, 1u);
+        const unsigned t = __hip_atomic_fetch_add(&dev->blocks_done, 1u, __ATOMIC_RELEASE,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
         is_last = (t == gridDim.x - 1);
     }
     __syncthreads();
-    if (is_last) __threadfence();
-    return is_last != 0;
+    const bool last = is_last != 0;
+    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return last;
 }
 
 }  // namespace md

@@ -2,11 +2,11 @@
 //
 // Neighbor-list mode: one workgroup per tile (md_tiles.h).  After the
 // tile's cell tables are known, one round of loads brings the tile's 27-cell
-// neighborhoods and its rows of the neighbor matrix (the chunk rows its
-// longest list uses) into LDS; `lanes` lanes per home atom then walk the
-// atom's list (lane s takes chunks s, s+lanes, ...; a chunk is 4 entries),
-// gather the partners from LDS and accumulate the force on the home atom
-// alone.  Every pair is met twice,
+// neighborhoods into LDS; `lanes` lanes per home atom then walk the atom's
+// list straight from the neighbor matrix (lane s takes chunks s, s+lanes,
+// ...; a chunk is 4 entries, and each lane loads its next chunk before it
+// works on the current one), gather the partners from LDS and accumulate the
+// force on the home atom alone.  Every pair is met twice,
 // once from each side, so no atomics are needed (the paper's choice).
 // Pairs at r^2 >= r_cut^2 are skipped.  Separations take the minimum image
 // from the wrap bits carried by each entry (section 4.1, factor (4)); tiles
@@ -112,24 +112,22 @@ __device__ __forceinline__ void chunk_pairs(const KParams& p, const Stage& s, ui
     }
 }
 
-// Chunks c = sub, sub+LANES, ... of one home atom, from the tile's rows in
-// LDS (nlc, row pitch nh) or, when they did not fit, from global memory.
+// Chunks c = sub, sub+LANES, ... of one home atom's list, each loaded one
+// step ahead of its use.
 template <int LANES, int kImage, bool kFits, bool kMask, typename Acc>
-__device__ __forceinline__ void walk_tile_list(const KParams& p, const Stage& s,
-                                               const MD_LDS uint64_t* nlc, int nh, int h,
-                                               int slot_i, int sub, int cnt, double xi, double yi,
-                                               double zi, Acc& a)
+__device__ __forceinline__ void walk_list(const KParams& p, const Stage& s, int slot_i, int sub,
+                                          int cnt, double xi, double yi, double zi, Acc& a)
 {
     const int nchunk = (cnt + kChunk - 1) / kChunk;
-    if (nlc) {
-        for (int c = sub; c < nchunk; c += LANES)
-            chunk_pairs<kImage, kFits, kMask>(p, s, nlc[c * nh + h], c * kChunk, cnt, xi, yi,
-                                              zi, a);
-    } else {
-        const uint64_t* col = p.nl64 + slot_i;
-        for (int c = sub; c < nchunk; c += LANES)
-            chunk_pairs<kImage, kFits, kMask>(p, s, col[(int64_t)c * p.npad], c * kChunk, cnt,
-                                              xi, yi, zi, a);
+    const uint64_t* col = p.nl64 + slot_i;
+    int c = sub;
+    uint64_t next = c < nchunk ? col[(int64_t)c * p.npad] : 0;
+    while (c < nchunk) {
+        const uint64_t ch = next;
+        const int cn = c + LANES;
+        if (cn < nchunk) next = col[(int64_t)cn * p.npad];
+        chunk_pairs<kImage, kFits, kMask>(p, s, ch, c * kChunk, cnt, xi, yi, zi, a);
+        c = cn;
     }
 }
 
@@ -138,39 +136,13 @@ __global__ void k_forces_tiles(KParams p)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ double red[(1024 / kWave) * 2];
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const Tile g = tile_of(p, t);
+    const Tile g = tile_of(p, xcd_tile(blockIdx.x, gridDim.x));
     Stage s = stage_layout(p, smem);
-    MD_LDS uint64_t* nlc_area = (MD_LDS uint64_t*)stage_end(p, s);
-    const int rows = p.tile_rows[t];
     stage_tables(p, g, s);
     const int nh = home_count(s), h0 = home_first_lds(s), slot0 = home_first_slot(s);
     const int mode = image_mode(p, tile_interior(p, g));
-    const bool rows_fit = (int64_t)rows * nh <= p.nlcap;
-    // one round of loads: staged positions, the tile's list rows, list lengths
-    if (rows_fit) {
-        constexpr int U = 4;
-        const int n_items = rows * nh;
-        for (int i0 = threadIdx.x; i0 < n_items; i0 += U * blockDim.x) {
-            uint64_t v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int idx = i0 + u * blockDim.x;
-                if (idx < n_items) {
-                    const int c = idx / nh, h = idx - c * nh;
-                    v[u] = p.nl64[(int64_t)c * p.npad + atom_at(p, slot0 + h)];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int idx = i0 + u * blockDim.x;
-                if (idx < n_items) nlc_area[idx] = v[u];
-            }
-        }
-    }
     stage_positions(p, s);
     __syncthreads();
-    const MD_LDS uint64_t* nlc = rows_fit ? nlc_area : nullptr;
     const int per_pass = blockDim.x / LANES;
     const int sub = threadIdx.x % LANES;
     double e[2] = {0.0, 0.0};
@@ -193,15 +165,15 @@ __global__ void k_forces_tiles(KParams p)
             }
             if (!s.fits) {
                 if (mode == 2)
-                    walk_tile_list<LANES, 2, false, true>(p, s, nlc, nh, h, slot_i, sub, cnt, xi, yi, zi, a);
+                    walk_list<LANES, 2, false, true>(p, s, slot_i, sub, cnt, xi, yi, zi, a);
                 else
-                    walk_tile_list<LANES, 1, false, true>(p, s, nlc, nh, h, slot_i, sub, cnt, xi, yi, zi, a);
+                    walk_list<LANES, 1, false, true>(p, s, slot_i, sub, cnt, xi, yi, zi, a);
             } else if (mode == 0) {
-                walk_tile_list<LANES, 0, true, false>(p, s, nlc, nh, h, slot_i, sub, cnt, xi, yi, zi, a);
+                walk_list<LANES, 0, true, false>(p, s, slot_i, sub, cnt, xi, yi, zi, a);
             } else if (mode == 1) {
-                walk_tile_list<LANES, 1, true, false>(p, s, nlc, nh, h, slot_i, sub, cnt, xi, yi, zi, a);
+                walk_list<LANES, 1, true, false>(p, s, slot_i, sub, cnt, xi, yi, zi, a);
             } else {
-                walk_tile_list<LANES, 2, true, true>(p, s, nlc, nh, h, slot_i, sub, cnt, xi, yi, zi, a);
+                walk_list<LANES, 2, true, true>(p, s, slot_i, sub, cnt, xi, yi, zi, a);
             }
         }
         if (LANES > 1) {
@@ -303,8 +275,9 @@ template <typename F, typename Acc>
 static void launch_tiles(const KParams& p, hipStream_t s)
 {
     const dim3 g(p.n_tiles), t(p.force_block);
-    const size_t lds = stage_bytes(p.scap, p.kx_max) + sizeof(uint64_t) * (size_t)p.nlcap;
+    const size_t lds = stage_bytes(p.scap, p.kx_max);
     switch (p.force_lanes) {
+        case 8: hipLaunchKernelGGL((k_forces_tiles<F, Acc, 8>), g, t, lds, s, p); break;
         case 2: hipLaunchKernelGGL((k_forces_tiles<F, Acc, 2>), g, t, lds, s, p); break;
         case 4: hipLaunchKernelGGL((k_forces_tiles<F, Acc, 4>), g, t, lds, s, p); break;
         default: hipLaunchKernelGGL((k_forces_tiles<F, Acc, 1>), g, t, lds, s, p); break;

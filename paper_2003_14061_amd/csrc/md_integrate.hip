@@ -200,15 +200,15 @@ __global__ __launch_bounds__(kIntThreads) void k_observe(KParams p)
     }
 }
 
-static unsigned grid_for(int n)
+static unsigned grid_for(const KParams& p)
 {
-    int g = (n + kIntThreads - 1) / kIntThreads;
-    return (unsigned)(g < kIntegrateGrid ? (g > 0 ? g : 1) : kIntegrateGrid);
+    const int g = (p.n + kIntThreads - 1) / kIntThreads;
+    return (unsigned)(g < p.int_grid ? (g > 0 ? g : 1) : p.int_grid);
 }
 
 void launch_integrate(const KParams& p, int phase, hipStream_t s)
 {
-    const dim3 g(grid_for(p.n)), t(kIntThreads);
+    const dim3 g(grid_for(p)), t(kIntThreads);
     if (p.precision == MD_FP64)
         hipLaunchKernelGGL(k_integrate<double>, g, t, 0, s, p, phase);
     else
@@ -217,7 +217,7 @@ void launch_integrate(const KParams& p, int phase, hipStream_t s)
 
 void launch_observe(const KParams& p, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_observe, dim3(grid_for(p.n)), dim3(kIntThreads), 0, s, p);
+    hipLaunchKernelGGL(k_observe, dim3(grid_for(p)), dim3(kIntThreads), 0, s, p);
 }
 
 }  // namespace md

@@ -14,7 +14,8 @@ namespace md {
 
 constexpr int kWave = 64;
 constexpr int kHistCap = 4096;     // history records kept on the device
-constexpr int kIntegrateGrid = 2048;  // fixed grid of the grid-stride per-atom kernels
+constexpr int kIntegrateGridMax = 4096;  // largest grid of the grid-stride per-atom kernels
+constexpr int kIntegrateGridDefault = 512;
 
 // Device-resident control block (first bytes of the workspace).
 struct DevState {
@@ -47,26 +48,23 @@ struct KParams {
     int32_t *cell_count, *cell_start, *cell_of, *slot, *order, *tmp;
     uint64_t* nl64;       // list chunks: 4 x 16-bit entries, chunk c of slot k at c*npad + k
     int32_t* nl_count;
-    int32_t* tile_rows;   // per tile: list chunk rows its longest list uses (set by the list build)
     double *xr, *yr, *zr;
     double *sx, *sy, *sz, *svx, *svy, *svz, *sfx, *sfy, *sfz;  // permutation scratch
     int32_t *sid, *scell;
     double *fpart;    // force-pass partials [nblk_force][2]: U, W
-    double *ipart;    // per-atom kernel partials [kIntegrateGrid][8]
+    double *ipart;    // per-atom kernel partials [int_grid][8]
     int32_t *scanpart;  // scan partials [nscan][2]: sum, max
     md_record* hist;
     int32_t nblk_force;     // workgroups of the last-configured force pass
     int32_t block;
     int32_t record_every;   // history interval of the running md_step (0 = none)
-    int32_t force_lanes;    // lanes per home atom in the tiled force pass (1, 2, 4)
-    int32_t force_batch;    // list chunks fetched ahead per lane (1, 2, 4)
-    int32_t force_block;    // threads per workgroup of the tiled kernels
-    int32_t nl_batch;       // staged candidates loaded ahead per lane in the list build (1, 4)
+    int32_t force_lanes;    // lanes per home atom in the tiled force pass (1, 2, 4, 8)
+    int32_t force_block;    // threads per workgroup of the tiled force pass
     int32_t nl_block;       // threads per workgroup of the list build
+    int32_t int_grid;       // workgroups of the grid-stride per-atom kernels
     // tiling of the neighbor-list mode: rows of nc cells cut into tiles_per_row tiles
     int32_t tiles_per_row, kx_max, n_tiles;
     int32_t scap;           // staged atoms a workgroup's LDS holds
-    int32_t nlcap;          // list chunks of a tile the force pass's LDS holds
 };
 
 // Largest number of force-pass workgroups any tuning can ask for.

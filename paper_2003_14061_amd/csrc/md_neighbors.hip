@@ -21,11 +21,8 @@
 
 namespace md {
 
-// LDS bytes of the list build: the staged tile plus one int per wave.
-inline size_t nl_lds_bytes(const KParams& p)
-{
-    return stage_bytes(p.scap, p.kx_max) + sizeof(int) * (p.nl_block / kWave);
-}
+// LDS bytes of the list build: the staged tile.
+inline size_t nl_lds_bytes(const KParams& p) { return stage_bytes(p.scap, p.kx_max); }
 
 __device__ __forceinline__ double readlane_f64(double v, int lane)
 {
@@ -37,9 +34,9 @@ __device__ __forceinline__ double readlane_f64(double v, int lane)
 // One home cell q of the tile, by one wave.  Home atoms are taken 64 at a
 // time; lane L keeps home atom h0+L's position and list length in
 // registers, read by the whole wave with readlane while it tests 64
-// candidates at once.  Returns the chunk rows of the cell's longest list.
+// candidates at once.
 template <int kImage>
-__device__ __forceinline__ int nl_home_cell(const KParams& p, const Stage& s, int q)
+__device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, int q)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int home_t = 4 * s.stride + q;
@@ -56,7 +53,6 @@ __device__ __forceinline__ int nl_home_cell(const KParams& p, const Stage& s, in
     const int ncand = wp[9];
     const uint32_t cap = (uint32_t)p.cap;
     uint16_t* nl16 = reinterpret_cast<uint16_t*>(p.nl64);
-    int rows = 0;
     for (int h0 = hb; h0 < he; h0 += kWave) {
         const int nhs = he - h0 < kWave ? he - h0 : kWave;
         // this lane's home atom
@@ -139,8 +135,6 @@ __device__ __forceinline__ int nl_home_cell(const KParams& p, const Stage& s, in
             p.xr[slot_l] = hx;
             p.yr[slot_l] = hy;
             p.zr[slot_l] = hz;
-            const int r = (stored + kChunk - 1) / kChunk;
-            rows = r > rows ? r : rows;
         }
         const int mmax = wave_max(m);
         if (lane == 0 && mmax > 0) {
@@ -148,7 +142,6 @@ __device__ __forceinline__ int nl_home_cell(const KParams& p, const Stage& s, in
             if (mmax > p.cap) atomicOr(&p.dev->flags, (int)MD_FLAG_NL_OVERFLOW);
         }
     }
-    return rows;
 }
 
 __global__ void k_nl_tiles(KParams p, int force)
@@ -158,7 +151,6 @@ __global__ void k_nl_tiles(KParams p, int force)
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const Tile g = tile_of(p, t);
     Stage s = stage_layout(p, smem);
-    MD_LDS int* wrows = (MD_LDS int*)stage_end(p, s);
     stage_tables(p, g, s);
     if (s.total >= kMaxStaged) {
         // the 13-bit entry cannot address this tile (and its sentinel): report it
@@ -166,34 +158,20 @@ __global__ void k_nl_tiles(KParams p, int force)
         const int nh = home_count(s);
         for (int h = threadIdx.x; h < nh; h += blockDim.x)
             p.nl_count[atom_at(p, home_first_slot(s) + h)] = 0;
-        if (threadIdx.x == 0) {
-            atomicOr(&p.dev->flags, (int)MD_FLAG_NL_OVERFLOW);
-            p.tile_rows[t] = 0;
-        }
+        if (threadIdx.x == 0) atomicOr(&p.dev->flags, (int)MD_FLAG_NL_OVERFLOW);
         return;
     }
     stage_positions(p, s);
     __syncthreads();
     const int wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const int mode = image_mode(p, tile_interior(p, g));
-    int rows = 0;
     for (int q = 1 + wid; q <= g.kx; q += nw) {
-        int r;
         if (mode == 0)
-            r = nl_home_cell<0>(p, s, q);
+            nl_home_cell<0>(p, s, q);
         else if (mode == 1)
-            r = nl_home_cell<1>(p, s, q);
+            nl_home_cell<1>(p, s, q);
         else
-            r = nl_home_cell<2>(p, s, q);
-        rows = r > rows ? r : rows;
-    }
-    rows = wave_max(rows);
-    if ((threadIdx.x & (kWave - 1)) == 0) wrows[wid] = rows;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int r = 0;
-        for (int w = 0; w < nw; ++w) r = wrows[w] > r ? wrows[w] : r;
-        p.tile_rows[t] = r;
+            nl_home_cell<2>(p, s, q);
     }
 }
 

@@ -34,7 +34,6 @@ constexpr int kEntryBits = 13;
 constexpr int kEntryMask = (1 << kEntryBits) - 1;
 constexpr int kMaxStaged = 1 << kEntryBits;  // virtual layout limit
 constexpr int kChunk = 4;                    // entries per 8-byte list chunk
-constexpr int kMaxHomeSweep = 128;           // home atoms of one cell per list-build sweep
 
 struct Tile {
     int cz, cy, cx0, kx;
@@ -74,15 +73,14 @@ struct Stage {
 
 constexpr double kSentinel = 1.0e30;
 
-// Ints of the table region, rounded up to 16 bytes so that whatever follows
-// it (8-byte list chunks) stays aligned.
+// Ints of the table region, rounded up to 16 bytes.
 __host__ __device__ __forceinline__ int stage_table_ints(int kx_max)
 {
     const int ntab = 9 * (kx_max + 2);
     return (3 * ntab + 1 + kWave + 3) / 4 * 4;
 }
 
-// Dynamic LDS bytes of the staged tile (what follows it starts 16-byte aligned).
+// Dynamic LDS bytes of the staged tile.
 inline size_t stage_bytes(int scap, int kx_max)
 {
     return sizeof(double) * 3 * (size_t)scap + sizeof(int) * (size_t)stage_table_ints(kx_max);
@@ -100,12 +98,6 @@ __device__ __forceinline__ Stage stage_layout(const KParams& p, char* smem)
     s.flag = s.slot + ntab_max;
     s.scan = s.flag + ntab_max;
     return s;
-}
-
-// First byte after the staged tile's LDS (16-byte aligned).
-__device__ __forceinline__ MD_LDS char* stage_end(const KParams& p, const Stage& s)
-{
-    return (MD_LDS char*)(s.off + stage_table_ints(p.kx_max));
 }
 
 // Cell tables of tile g: slots, wrap bits and LDS offsets of the staged

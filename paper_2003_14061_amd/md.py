@@ -56,9 +56,9 @@ class Grid(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("force_lanes", C.c_int32), ("force_batch", C.c_int32),
-                ("force_block", C.c_int32), ("nl_batch", C.c_int32), ("nl_block", C.c_int32),
-                ("tile_cells", C.c_int32), ("stage_cap", C.c_int32)]
+    _fields_ = [("force_lanes", C.c_int32), ("force_block", C.c_int32),
+                ("nl_block", C.c_int32), ("tile_cells", C.c_int32), ("stage_cap", C.c_int32),
+                ("integrate_grid", C.c_int32)]
 
 
 class Observables(C.Structure):
@@ -188,10 +188,10 @@ def md_history(ctx, max_records: int = 4096):
     return list(buf[: n.value])
 
 
-def md_set_tuning(ctx, force_lanes=1, force_batch=2, force_block=256, nl_batch=4, nl_block=256,
-                  tile_cells=0, stage_cap=0):
-    t = Tuning(int(force_lanes), int(force_batch), int(force_block), int(nl_batch), int(nl_block),
-               int(tile_cells), int(stage_cap))
+def md_set_tuning(ctx, force_lanes=4, force_block=512, nl_block=0, tile_cells=0, stage_cap=0,
+                  integrate_grid=0):
+    t = Tuning(int(force_lanes), int(force_block), int(nl_block), int(tile_cells), int(stage_cap),
+               int(integrate_grid))
     _check(lib().md_set_tuning(ctx, C.byref(t)), "md_set_tuning")
 
 
@@ -247,6 +247,7 @@ class Simulation:
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.ctx = md_init(self.params)
+        self._tuning = None
         self.grid = md_geometry(self.ctx)
         t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=self.device)
         self.x, self.y, self.z = (t(pos[:, k]) for k in range(3))
@@ -312,9 +313,16 @@ class Simulation:
         return out
 
     def set_tuning(self, **kw):
-        cur = md_get_tuning(self.ctx)
-        cur.update(kw)
-        md_set_tuning(self.ctx, **cur)
+        """Change some launch-shape settings; the others keep their last
+        requested values (nl_block, tile_cells, stage_cap and integrate_grid
+        start automatic, 0)."""
+        if self._tuning is None:
+            self._tuning = md_get_tuning(self.ctx)
+            self._tuning.update(nl_block=0, tile_cells=0, stage_cap=0, integrate_grid=0)
+        req = dict(self._tuning)
+        req.update(kw)
+        md_set_tuning(self.ctx, **req)
+        self._tuning = req
 
     def get_tuning(self):
         return md_get_tuning(self.ctx)

@@ -149,6 +149,24 @@ def test_determinism():
     assert np.array_equal(ha, hb)
 
 
+def test_integrate_grid_changes_only_the_reduction_order():
+    # kicks and drifts are per atom, so the trajectory is bitwise the same for
+    # every grid of the integration kernel; K and P are sums in another order
+    outs = []
+    for grid in (1, 7, 4096):
+        sim, s, pos, vel = setup("lj32000_nl")
+        sim.set_tuning(integrate_grid=grid)
+        sim.prepare()
+        sim.step(25, record_every=5)
+        outs.append((sim.state(), sim.history()))
+    (a, ha) = outs[0]
+    for b, hb in outs[1:]:
+        for k in ("pos", "vel", "f"):
+            assert np.array_equal(a[k], b[k])
+        assert np.array_equal(ha["rebuilt"], hb["rebuilt"])
+        assert np.allclose(ha["K"], hb["K"], rtol=1e-13, atol=0)
+
+
 def test_momentum_and_energy_conservation():
     L, pos, vel = state(32000, 0.8, 5)
     sim, s = pair(pos, vel, L, r_cut=2.5, dt=0.004)
@@ -225,11 +243,12 @@ def test_positions_on_cell_and_box_edges():
     check_nl(sim, s, pos, cells)
 
 
-TUNINGS = ([dict(force_lanes=l, force_batch=b) for l in (1, 2, 4) for b in (1, 2, 4)] +
-           [dict(tile_cells=c, nl_batch=nb, nl_block=blk, force_block=fb)
-            for c, nb, blk, fb in ((1, 1, 64, 64), (3, 4, 128, 512), (1000, 4, 256, 1024),
-                                   (2, 1, 512, 128))] +
-           [dict(stage_cap=64), dict(stage_cap=64, force_lanes=4, tile_cells=2)])
+TUNINGS = ([dict(force_lanes=l, force_block=b) for l in (1, 2, 4, 8) for b in (256, 512)] +
+           [dict(tile_cells=c, nl_block=blk, force_block=fb)
+            for c, blk, fb in ((1, 64, 64), (3, 128, 512), (1000, 256, 1024), (2, 512, 128),
+                               (5, 1024, 512))] +
+           [dict(stage_cap=64), dict(stage_cap=64, force_lanes=4, tile_cells=2),
+            dict(force_lanes=8, force_block=64, tile_cells=1)])
 
 
 @pytest.mark.parametrize("name", ["lj32000_nl", "wca13500_nl", "lj5000_random", "wca108_nc3",
@@ -256,9 +275,9 @@ def test_every_tuning_matches_the_oracle(name):
 
 def test_tuning_is_validated():
     sim, s, pos, vel = setup("wca108_nc3")
-    for bad in (dict(force_lanes=3), dict(force_lanes=8), dict(force_batch=8),
-                dict(force_block=96), dict(nl_batch=2), dict(nl_block=32), dict(tile_cells=-1),
-                dict(stage_cap=-5)):
+    for bad in (dict(force_lanes=3), dict(force_lanes=16), dict(force_block=96),
+                dict(force_block=2048), dict(nl_block=32), dict(tile_cells=-1),
+                dict(stage_cap=-5), dict(integrate_grid=-1), dict(integrate_grid=4097)):
         with pytest.raises(md.MDError):
             sim.set_tuning(**bad)
     sim.prepare()
