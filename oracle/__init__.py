@@ -27,6 +27,10 @@ class Sys(C.Structure):
                 ("use_nl", C.c_int32), ("nl_cap", C.c_int32)]
 
 
+class GrSpec(C.Structure):
+    _fields_ = [("n_bins", C.c_int32), ("rmax", C.c_double), ("width", C.c_double)]
+
+
 class Obs(C.Structure):
     _fields_ = [("U", C.c_double), ("K", C.c_double), ("W", C.c_double),
                 ("P", C.c_double * 3), ("dmax2", C.c_double),
@@ -85,6 +89,24 @@ def lib():
         L.or_run.argtypes = [_SP, C.c_int32, _D, _D, _D, _D, _D, _D, _D, _D, _D, C.c_void_p]
         L.or_threads.restype = C.c_int32
         L.or_threads.argtypes = []
+        # reverse mode (md_oracle_adjoint.h)
+        _GP = C.POINTER(GrSpec)
+        _PD = C.POINTER(C.c_double)
+        L.or_pair_deriv.restype = None
+        L.or_pair_deriv.argtypes = [_SP, C.c_double, _PD, _PD, _PD]
+        L.or_hvp.restype = None
+        L.or_hvp.argtypes = [_SP, _D, _D, _D, _I, _I, _D, _D, _D, _D, _D, _D, _PD, _PD]
+        L.or_gr.restype = C.c_int32
+        L.or_gr.argtypes = [_SP, _GP, _D, _D, _D, _I, _I, _D]
+        L.or_gr_allpairs.restype = None
+        L.or_gr_allpairs.argtypes = [_SP, _GP, _D, _D, _D, _D]
+        L.or_gr_grad.restype = None
+        L.or_gr_grad.argtypes = [_SP, _GP, _D, _D, _D, _I, _I, _D, _D, _D, _D]
+        L.or_traj_obs.restype = C.c_int32
+        L.or_traj_obs.argtypes = [_SP, _GP, C.c_int32, _D, _D, _D, _D, _D, _D, _PD, C.c_void_p]
+        L.or_traj_adjoint.restype = C.c_int32
+        L.or_traj_adjoint.argtypes = ([_SP, _GP, C.c_int32, _D, _D, _D, _D, _D, _D, C.c_double,
+                                       C.c_void_p, _PD, C.c_void_p] + [_D] * 6 + [_D])
         _LIB = L
     return _LIB
 
@@ -253,3 +275,86 @@ def run(s, pos, vel, n_steps):
 
 def threads():
     return int(lib().or_threads())
+
+
+# ---------------------------------------------------------------------------
+# Reverse mode (md_oracle_adjoint.h): pair derivatives, Jacobian-vector
+# products of the forces, the soft g(r), and whole-trajectory gradients.
+
+def gr_spec(n_bins=0, rmax=2.5, width=None):
+    """Soft g(r) bins on [0, rmax); width defaults to the bin width."""
+    if width is None:
+        width = rmax / n_bins if n_bins else 0.0
+    return GrSpec(int(n_bins), float(rmax), float(width))
+
+
+def pair_deriv(s, r2):
+    """(fr, gr, fs): -u'/r, (1/r) d fr/dr and d fr/d sigma at r^2 = r2."""
+    fr, gr, fs = C.c_double(), C.c_double(), C.c_double()
+    lib().or_pair_deriv(C.byref(s), float(r2), C.byref(fr), C.byref(gr), C.byref(fs))
+    return fr.value, gr.value, fs.value
+
+
+def hvp(s, pos, nl_count, nl, lam):
+    """(J lam [n,3], sum lam.dF/deps, sum lam.dF/dsigma), J = dF/dx."""
+    x, y, z = _xyz(pos)
+    lx, ly, lz = _xyz(lam)
+    jx, jy, jz = np.zeros(s.n), np.zeros(s.n), np.zeros(s.n)
+    de, ds = C.c_double(), C.c_double()
+    lib().or_hvp(C.byref(s), x, y, z, _c(nl_count, np.int32), _c(nl, np.int32), lx, ly, lz,
+                 jx, jy, jz, C.byref(de), C.byref(ds))
+    return np.stack([jx, jy, jz], 1), de.value, ds.value
+
+
+def gr(s, g, pos, nl_count, nl):
+    out = np.zeros(g.n_bins)
+    r = lib().or_gr(C.byref(s), C.byref(g), *_xyz(pos), _c(nl_count, np.int32),
+                    _c(nl, np.int32), out)
+    if r:
+        raise RuntimeError("g(r) range plus 3 widths exceeds the list radius")
+    return out
+
+
+def gr_allpairs(s, g, pos):
+    out = np.zeros(g.n_bins)
+    lib().or_gr_allpairs(C.byref(s), C.byref(g), *_xyz(pos), out)
+    return out
+
+
+def gr_grad(s, g, pos, nl_count, nl, wgt):
+    gx, gy, gz = np.zeros(s.n), np.zeros(s.n), np.zeros(s.n)
+    lib().or_gr_grad(C.byref(s), C.byref(g), *_xyz(pos), _c(nl_count, np.int32),
+                     _c(nl, np.int32), _c(wgt, np.float64), gx, gy, gz)
+    return np.stack([gx, gy, gz], 1)
+
+
+_TRAJ_ERR = {-1: "bad arguments", -2: "box too small for 3 cells per side",
+             -3: "neighbor list overflow", -4: "g(r) range exceeds the list radius"}
+
+
+def traj_obs(s, g, n_steps, pos, vel):
+    """(ubar, g) of the n_steps trajectory from (pos, vel)."""
+    ub = C.c_double()
+    out = np.zeros(max(g.n_bins, 1))
+    r = lib().or_traj_obs(C.byref(s), C.byref(g), int(n_steps), *_xyz(pos), *_xyz(vel),
+                          C.byref(ub), out.ctypes.data)
+    if r:
+        raise RuntimeError(_TRAJ_ERR.get(r, f"oracle error {r}"))
+    return ub.value, out[: g.n_bins]
+
+
+def traj_adjoint(s, g, n_steps, pos, vel, gU, gG=None):
+    """Gradients of L (dL/dubar = gU, dL/dg = gG) with respect to the initial
+    positions and velocities and (eps, sigma).  Returns a dict with ubar, g,
+    grad_x0 [n,3], grad_v0 [n,3], grad_theta [2]."""
+    ub = C.c_double()
+    out = np.zeros(max(g.n_bins, 1))
+    gG = np.zeros(max(g.n_bins, 1)) if gG is None else _c(gG, np.float64)
+    o = [np.zeros(s.n) for _ in range(6)]
+    th = np.zeros(2)
+    r = lib().or_traj_adjoint(C.byref(s), C.byref(g), int(n_steps), *_xyz(pos), *_xyz(vel),
+                              float(gU), gG.ctypes.data, C.byref(ub), out.ctypes.data, *o, th)
+    if r:
+        raise RuntimeError(_TRAJ_ERR.get(r, f"oracle error {r}"))
+    return {"ubar": ub.value, "g": out[: g.n_bins], "grad_x0": np.stack(o[:3], 1),
+            "grad_v0": np.stack(o[3:], 1), "grad_theta": th}
