@@ -247,6 +247,60 @@ md_status md_get_tuning(const md_ctx* ctx, md_tuning* tuning);
 md_status md_set_timing(md_ctx* ctx, int32_t enable);
 md_status md_get_timing(md_ctx* ctx, double* total_ms, int64_t* launches);
 
+/* ---- Reverse mode: gradients of trajectory observables ----
+ *
+ * Not part of the paper, which has no gradients: the derivative of its
+ * method (pair forces F1 over the neighbor list, section 2.3, inside the
+ * kick-drift-kick leapfrog of section 4.3) with respect to the initial
+ * positions and velocities and the potential parameters (eps, sigma).  The
+ * cutoff is taken to move with sigma (r_cut / sigma fixed); pairs crossing
+ * the cutoff contribute nothing (the pathwise derivative).
+ *
+ * Observables of an S-step trajectory x_0 .. x_S, as a device array obs of
+ * 1 + n_bins doubles:
+ *   obs[0]     = (1/S) sum_{s=1..S} U(x_s) / N
+ *   obs[1 + b] = g_b(x_S) = sum_i sum_{j != i} K(r_ij - r_b) / (N rho 4 pi r_b^2),
+ *                r_b = (b + 1/2) gr_rmax / n_bins, K a unit-area Gaussian of
+ *                standard deviation gr_width, lowered by its value at 3
+ *                widths and zero beyond (continuous in the positions).
+ * The pairs of g come from the neighbor list, so gr_rmax + 3 gr_width must
+ * not exceed r_cut + skin.
+ *
+ * Checkpointing: md_traj_forward keeps (x, v) every checkpoint_every steps
+ * and at the end; md_traj_backward recomputes each segment forward from its
+ * checkpoint, keeping its positions, then walks it backwards.  Both need a
+ * neighbor-list context with reorder = 0 (gradients then come out in the
+ * bound storage order, which never changes), bound buffers, and a
+ * caller-owned device block of md_traj_workspace_bytes() bytes (256-byte
+ * aligned) that md_traj_backward reads as md_traj_forward left it.  n_steps
+ * may not exceed 4096 (the history the mean energy is read from). */
+typedef struct {
+    int32_t n_steps;           /* S >= 1 */
+    int32_t checkpoint_every;  /* >= 1 */
+    int32_t n_bins;            /* 0..1024 (0: obs holds the mean energy only) */
+    int32_t pad;
+    double  gr_rmax;           /* > 0 when n_bins > 0 */
+    double  gr_width;          /* > 0 when n_bins > 0 */
+} md_traj_params;
+
+/* Bytes of the trajectory workspace; 0 on invalid arguments. */
+size_t md_traj_workspace_bytes(const md_ctx* ctx, const md_traj_params* tp);
+
+/* Run n_steps leapfrog steps from the bound state (computing the forces
+ * first if needed), keeping the checkpoints in traj_ws and writing the
+ * observables to obs (device, 1 + n_bins doubles).  Leaves the state at step
+ * n_steps.  Enqueued. */
+md_status md_traj_forward(md_ctx* ctx, const md_traj_params* tp, void* traj_ws, double* obs);
+
+/* Given grad_obs = dL/dobs (device, 1 + n_bins doubles), write dL/dx_0 and
+ * dL/dv_0 (device, 3 * n_atoms doubles each: all x, then all y, then all z)
+ * and dL/d(eps, sigma) (device, 2 doubles).  Uses the checkpoints of the
+ * last md_traj_forward on traj_ws; restores the state at step n_steps before
+ * returning (the step counter also counts the recomputed steps).  Enqueued. */
+md_status md_traj_backward(md_ctx* ctx, const md_traj_params* tp, void* traj_ws,
+                           const double* grad_obs, double* grad_x0, double* grad_v0,
+                           double* grad_theta);
+
 void md_destroy(md_ctx* ctx);
 
 /* Static string for a status code. */

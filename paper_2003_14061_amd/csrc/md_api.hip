@@ -202,6 +202,8 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
     k.sig2 = p.sigma * p.sigma;
     k.eps2 = 2.0 * p.eps;
     k.eps48 = 48.0 * p.eps;
+    k.eps = p.eps;
+    k.sigma = p.sigma;
     double shift = 0.0;
     if (p.potential == MD_LJ_SHIFTED) {
         const double sr2 = k.sig2 / k.rc2, sr6 = sr2 * sr2 * sr2;
@@ -452,6 +454,258 @@ extern "C" md_status md_reduce(md_ctx* c, md_observables* out)
     if (d.flags & MD_FLAG_NL_OVERFLOW) return MD_ERR_NL_OVERFLOW;
     if (d.flags & MD_FLAG_NONFINITE) return MD_ERR_NONFINITE;
     return MD_OK;
+}
+
+// ---- reverse mode ----
+
+namespace {
+
+constexpr int kTrajMaxBins = 1024;
+
+// Byte offsets inside the trajectory workspace.  Every per-atom array has
+// the same 256-byte-aligned pitch.
+struct TrajLayout {
+    int k;         // steps per segment
+    int nseg;      // segments (one checkpoint each, plus the final state)
+    size_t pitch;  // bytes of one per-atom double array
+    size_t ck, snap, lam, theta, tpart, hist, total;
+};
+
+bool traj_layout(const md_ctx* c, const md_traj_params* tp, TrajLayout* L)
+{
+    if (!c || !tp) return false;
+    if (tp->n_steps < 1 || tp->n_steps > kHistCap || tp->checkpoint_every < 1 ||
+        tp->n_bins < 0 || tp->n_bins > kTrajMaxBins)
+        return false;
+    if (tp->n_bins > 0 && !(tp->gr_rmax > 0.0 && tp->gr_width > 0.0 && isfinite(tp->gr_rmax) &&
+                            isfinite(tp->gr_width)))
+        return false;
+    const size_t n = (size_t)c->prm.n_atoms;
+    L->k = tp->checkpoint_every < tp->n_steps ? tp->checkpoint_every : tp->n_steps;
+    L->nseg = (tp->n_steps + L->k - 1) / L->k;
+    L->pitch = align_up(sizeof(double) * n);
+    size_t o = 0;
+    L->ck = o;  // (x, y, z, vx, vy, vz) at the start of every segment and at the end
+    o += (size_t)(L->nseg + 1) * 6 * L->pitch;
+    L->snap = o;  // positions of the recomputed steps inside one segment
+    o += (size_t)(L->k - 1) * 3 * L->pitch;
+    L->lam = o;  // lambda_x, lambda_v (two buffers)
+    o += 9 * L->pitch;
+    L->theta = o;
+    o += align_up(2 * sizeof(double));
+    L->tpart = o;
+    o += align_up(2 * sizeof(double) * (size_t)max_force_blocks(n, c->geo.n_cells));
+    L->hist = o;
+    o += align_up(sizeof(unsigned long long) * (size_t)(tp->n_bins > 0 ? tp->n_bins : 1));
+    L->total = o;
+    return true;
+}
+
+double* arr(void* ws, const TrajLayout& L, size_t off, size_t idx)
+{
+    return reinterpret_cast<double*>(static_cast<char*>(ws) + off + idx * L.pitch);
+}
+
+}  // namespace
+
+static md_status traj_check(md_ctx* c, const md_traj_params* tp, void* ws, TrajLayout* L)
+{
+    if (!c || !tp || !ws || !traj_layout(c, tp, L)) return MD_ERR_ARG;
+    if (!c->bound) return MD_ERR_NOT_BOUND;
+    if (c->prm.mode != MD_NEIGHBOR_LIST || c->prm.reorder != 0) return MD_ERR_ARG;
+    if (((uintptr_t)ws) % kAlign != 0) return MD_ERR_ARG;
+    if (tp->n_bins > 0 && tp->gr_rmax + 3.0 * tp->gr_width > c->prm.r_cut + c->prm.skin)
+        return MD_ERR_ARG;
+    return MD_OK;
+}
+
+static GrArgs gr_args(const md_ctx* c, const md_traj_params* tp, void* ws, const TrajLayout& L)
+{
+    GrArgs g;
+    memset(&g, 0, sizeof(g));
+    g.hist = reinterpret_cast<unsigned long long*>(static_cast<char*>(ws) + L.hist);
+    g.n_bins = tp->n_bins;
+    g.rmax = tp->gr_rmax;
+    g.width = tp->gr_width;
+    // fixed-point units: the largest possible bin sum (every atom, a full
+    // list, each pair at the kernel's peak) stays below 2^62
+    const double kmax = 1.0 / (tp->gr_width * sqrt(2.0 * M_PI));
+    const double bound = (double)c->prm.n_atoms * (double)c->geo.nl_capacity * kmax;
+    int e = (int)floor(log2(ldexp(1.0, 62) / (bound > 1.0 ? bound : 1.0)));
+    g.scale = ldexp(1.0, e < 40 ? e : 40);
+    return g;
+}
+
+// Copy the state (x, y, z, vx, vy, vz) to or from a checkpoint.
+static md_status checkpoint(md_ctx* c, double* const* ck, bool save)
+{
+    const KParams& k = c->kp;
+    double* st[6] = {k.x, k.y, k.z, k.vx, k.vy, k.vz};
+    const size_t bytes = sizeof(double) * (size_t)c->prm.n_atoms;
+    for (int a = 0; a < 6; ++a)
+        if (hipMemcpyAsync(save ? ck[a] : st[a], save ? st[a] : ck[a], bytes,
+                           hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+            return MD_ERR_HIP;
+    return MD_OK;
+}
+
+static void checkpoint_arrays(void* ws, const TrajLayout& L, int seg, double** out)
+{
+    for (int a = 0; a < 6; ++a) out[a] = arr(ws, L, L.ck, (size_t)seg * 6 + a);
+}
+
+// Cells, list and forces from scratch at the current positions.
+static void rebuild_all(md_ctx* c)
+{
+    launch_cells(c->kp, 1, c->stream);
+    launch_neighbors(c->kp, 1, c->stream);
+    launch_forces(c->kp, c->stream);
+    c->cells_ok = c->nl_ok = c->forces_ok = true;
+}
+
+extern "C" size_t md_traj_workspace_bytes(const md_ctx* c, const md_traj_params* tp)
+{
+    TrajLayout L;
+    return traj_layout(c, tp, &L) ? L.total : 0;
+}
+
+extern "C" md_status md_traj_forward(md_ctx* c, const md_traj_params* tp, void* ws, double* obs)
+{
+    TrajLayout L;
+    md_status st = traj_check(c, tp, ws, &L);
+    if (st != MD_OK) return st;
+    if (!obs) return MD_ERR_ARG;
+    if (!c->forces_ok) rebuild_all(c);
+    double* ck[6];
+    for (int seg = 0; seg < L.nseg; ++seg) {
+        checkpoint_arrays(ws, L, seg, ck);
+        if ((st = checkpoint(c, ck, true)) != MD_OK) return st;
+        const int m = tp->n_steps - seg * L.k < L.k ? tp->n_steps - seg * L.k : L.k;
+        if ((st = md_step(c, m, 1)) != MD_OK) return st;
+    }
+    checkpoint_arrays(ws, L, L.nseg, ck);
+    if ((st = checkpoint(c, ck, true)) != MD_OK) return st;
+    launch_traj_ubar(c->kp, tp->n_steps, obs, c->stream);
+    if (tp->n_bins > 0) {
+        // a list built steps ago holds every pair only out to r_cut; the g(r)
+        // range may reach r_cut + skin, so build it afresh at x_S
+        rebuild_all(c);
+        GrArgs g = gr_args(c, tp, ws, L);
+        g.out = obs + 1;
+        launch_gr(c->kp, g, c->stream);
+    }
+    return launched();
+}
+
+extern "C" md_status md_traj_backward(md_ctx* c, const md_traj_params* tp, void* ws,
+                                      const double* grad_obs, double* grad_x0, double* grad_v0,
+                                      double* grad_theta)
+{
+    TrajLayout L;
+    md_status st = traj_check(c, tp, ws, &L);
+    if (st != MD_OK) return st;
+    if (!grad_obs || !grad_x0 || !grad_v0 || !grad_theta) return MD_ERR_ARG;
+    const KParams& k = c->kp;
+    hipStream_t sm = c->stream;
+    const int S = tp->n_steps;
+    const size_t n = (size_t)c->prm.n_atoms;
+    double* lam[3] = {arr(ws, L, L.lam, 0), arr(ws, L, L.lam, 1), arr(ws, L, L.lam, 2)};
+    double* vbuf[2][3] = {{arr(ws, L, L.lam, 3), arr(ws, L, L.lam, 4), arr(ws, L, L.lam, 5)},
+                          {arr(ws, L, L.lam, 6), arr(ws, L, L.lam, 7), arr(ws, L, L.lam, 8)}};
+    double* theta = reinterpret_cast<double*>(static_cast<char*>(ws) + L.theta);
+    AdjArgs a;
+    memset(&a, 0, sizeof(a));
+    a.lx = lam[0];
+    a.ly = lam[1];
+    a.lz = lam[2];
+    a.theta = theta;
+    a.tpart = reinterpret_cast<double*>(static_cast<char*>(ws) + L.tpart);
+    a.gobs = grad_obs;
+    a.cap = adj_stage_cap(k, c->lds_limit);
+    int cur = 0;
+    // one point: lambda_v of buffer cur in, of the other buffer out
+    auto point = [&](double coef, double loss_scale, double drift) {
+        a.vx = vbuf[cur][0];
+        a.vy = vbuf[cur][1];
+        a.vz = vbuf[cur][2];
+        a.nx = vbuf[1 - cur][0];
+        a.ny = vbuf[1 - cur][1];
+        a.nz = vbuf[1 - cur][2];
+        a.coef = coef;
+        a.loss_scale = loss_scale;
+        a.drift = drift;
+        launch_adj_point(k, a, sm);
+        cur = 1 - cur;
+    };
+    const double half = k.hdt;  // dt / 2m: one half kick
+    const double lscale = 1.0 / ((double)S * (double)n);
+    launch_fill(theta, 2, 0.0, sm);
+    for (int d = 0; d < 3; ++d) launch_fill(vbuf[0][d], n, 0.0, sm);
+
+    // the last point: the observables' direct dependence on x_S
+    double* ck[6];
+    checkpoint_arrays(ws, L, L.nseg, ck);
+    launch_adj_reimage(k, ck[0], ck[1], ck[2], sm);
+    launch_cells(k, 1, sm);
+    launch_neighbors(k, 1, sm);
+    if (tp->n_bins > 0) {
+        GrArgs g = gr_args(c, tp, ws, L);
+        g.gobs = grad_obs;
+        g.lx = lam[0];
+        g.ly = lam[1];
+        g.lz = lam[2];
+        launch_gr_grad(k, g, sm);
+    } else {
+        for (int d = 0; d < 3; ++d) launch_fill(lam[d], n, 0.0, sm);
+    }
+    point(0.0, lscale, k.dt);
+
+    for (int seg = L.nseg - 1; seg >= 0; --seg) {
+        const int s0 = seg * L.k;
+        const int s1 = s0 + L.k < S ? s0 + L.k : S;
+        // recompute the segment, keeping the positions of its inner points
+        checkpoint_arrays(ws, L, seg, ck);
+        if ((st = checkpoint(c, ck, false)) != MD_OK) return st;
+        rebuild_all(c);
+        for (int j = 1; j < s1 - s0; ++j) {
+            launch_integrate(k, j == 1 ? 0 : 1, sm);
+            launch_cells(k, 0, sm);
+            launch_neighbors(k, 0, sm);
+            launch_forces(k, sm);
+            for (int d = 0; d < 3; ++d)
+                if (hipMemcpyAsync(arr(ws, L, L.snap, (size_t)(j - 1) * 3 + d),
+                                   d == 0 ? k.x : (d == 1 ? k.y : k.z), sizeof(double) * n,
+                                   hipMemcpyDeviceToDevice, sm) != hipSuccess)
+                    return MD_ERR_HIP;
+        }
+        // walk it backwards
+        for (int s = s1 - 1; s >= s0; --s) {
+            const double* px[3];
+            for (int d = 0; d < 3; ++d)
+                px[d] = s == s0 ? ck[d] : arr(ws, L, L.snap, (size_t)(s - s0 - 1) * 3 + d);
+            launch_adj_reimage(k, px[0], px[1], px[2], sm);
+            launch_cells(k, 0, sm);
+            launch_neighbors(k, 0, sm);
+            // the first half kick of step s and the second of step s-1 (none
+            // before step 0) act together; the mean energy counts x_1 .. x_S
+            point(s == 0 ? half : 2.0 * half, s >= 1 ? lscale : 0.0, s >= 1 ? k.dt : 0.0);
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        if (hipMemcpyAsync(grad_x0 + d * n, lam[d], sizeof(double) * n, hipMemcpyDeviceToDevice,
+                           sm) != hipSuccess ||
+            hipMemcpyAsync(grad_v0 + d * n, vbuf[cur][d], sizeof(double) * n,
+                           hipMemcpyDeviceToDevice, sm) != hipSuccess)
+            return MD_ERR_HIP;
+    }
+    if (hipMemcpyAsync(grad_theta, theta, 2 * sizeof(double), hipMemcpyDeviceToDevice, sm) !=
+        hipSuccess)
+        return MD_ERR_HIP;
+    // back to the state at step S
+    checkpoint_arrays(ws, L, L.nseg, ck);
+    if ((st = checkpoint(c, ck, false)) != MD_OK) return st;
+    rebuild_all(c);
+    return launched();
 }
 
 extern "C" md_status md_history(md_ctx* c, md_record* out, int32_t max_records, int32_t* n_out)

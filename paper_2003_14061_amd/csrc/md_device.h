@@ -84,6 +84,13 @@ __device__ __forceinline__ double recip(double a)
     return __builtin_fma(y, e, y);
 }
 
+// Single-precision reciprocal: estimate plus one Newton-Raphson step.
+__device__ __forceinline__ float recipf(float a)
+{
+    float y = __builtin_amdgcn_rcpf(a);
+    return __builtin_fmaf(y, __builtin_fmaf(-a, y, 1.0f), y);
+}
+
 // ---- XCD-aware tile order ----
 // MI355X deals workgroup b to XCD (b mod 8).  Atoms are stored in cell
 // order, so giving each XCD one contiguous range of tiles keeps the

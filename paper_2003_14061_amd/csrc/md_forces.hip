@@ -49,12 +49,6 @@ __device__ __forceinline__ void pair_acc(const KParams& p, double dx, double dy,
     a.np += 1;
 }
 
-__device__ __forceinline__ float recipf(float a)
-{
-    float y = __builtin_amdgcn_rcpf(a);
-    return __builtin_fmaf(y, __builtin_fmaf(-a, y, 1.0f), y);
-}
-
 __device__ __forceinline__ void pair_acc(const KParams& p, double dx, double dy, double dz,
                                          double r2, AccF& a)
 {
@@ -71,65 +65,18 @@ __device__ __forceinline__ void pair_acc(const KParams& p, double dx, double dy,
     a.np += 1;
 }
 
-template <int LANES, typename T>
-__device__ __forceinline__ T lane_group_sum(T v)
-{
-#pragma unroll
-    for (int o = LANES / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
-// The 4 entries of one chunk.  kMask = false: partners from LDS, padded
-// entries point at the sentinel atom, nothing needs masking (wrap-bit image
-// modes only).  kMask = true: entries past the list are masked; with
-// kFits = false the partners come from global memory.
-template <int kImage, bool kFits, bool kMask, typename Acc>
-__device__ __forceinline__ void chunk_pairs(const KParams& p, const Stage& s, uint64_t ch,
-                                            int mbase, int cnt, double xi, double yi, double zi,
-                                            Acc& a)
-{
-#pragma unroll
-    for (int k = 0; k < kChunk; ++k) {
-        const uint32_t v = (uint32_t)(ch >> (16 * k)) & 0xffffu;
-        const bool valid = !kMask || mbase + k < cnt;
-        int e = (int)(v & kEntryMask);
-        double xj, yj, zj;
-        if (kFits) {
-            if (kMask) e = valid ? e : 0;
-            xj = s.xs[e];
-            yj = s.ys[e];
-            zj = s.zs[e];
-        } else {
-            const int j = staged_slot(p, s, valid && e < s.total ? e : 0);
-            xj = p.x[j];
-            yj = p.y[j];
-            zj = p.z[j];
-        }
-        double dx = xi - xj, dy = yi - yj, dz = zi - zj;
-        image<kImage>(p, (int)(v >> kEntryBits), dx, dy, dz);
-        const double r2 = dist2(dx, dy, dz);
-        if (valid && r2 < p.rc2) pair_acc(p, dx, dy, dz, r2, a);
+// Pair operation of the force pass: the pair force, energy and virial of
+// partners inside the cutoff.
+template <typename Acc>
+struct ForceOp {
+    const KParams& p;
+    Acc& a;
+    __device__ __forceinline__ void operator()(double dx, double dy, double dz, double r2, int,
+                                               int)
+    {
+        if (r2 < p.rc2) pair_acc(p, dx, dy, dz, r2, a);
     }
-}
-
-// Chunks c = sub, sub+LANES, ... of one home atom's list, each loaded one
-// step ahead of its use.
-template <int LANES, int kImage, bool kFits, bool kMask, typename Acc>
-__device__ __forceinline__ void walk_list(const KParams& p, const Stage& s, int slot_i, int sub,
-                                          int cnt, double xi, double yi, double zi, Acc& a)
-{
-    const int nchunk = (cnt + kChunk - 1) / kChunk;
-    const uint64_t* col = p.nl64 + slot_i;
-    int c = sub;
-    uint64_t next = c < nchunk ? col[(int64_t)c * p.npad] : 0;
-    while (c < nchunk) {
-        const uint64_t ch = next;
-        const int cn = c + LANES;
-        if (cn < nchunk) next = col[(int64_t)cn * p.npad];
-        chunk_pairs<kImage, kFits, kMask>(p, s, ch, c * kChunk, cnt, xi, yi, zi, a);
-        c = cn;
-    }
-}
+};
 
 template <typename F, typename Acc, int LANES>
 __global__ void k_forces_tiles(KParams p)
@@ -152,29 +99,10 @@ __global__ void k_forces_tiles(KParams p)
         int slot_i = 0;
         if (h < nh) {
             slot_i = atom_at(p, slot0 + h);
-            const int cnt = p.nl_count[slot_i];
             double xi, yi, zi;
-            if (s.fits) {
-                xi = s.xs[h0 + h];
-                yi = s.ys[h0 + h];
-                zi = s.zs[h0 + h];
-            } else {
-                xi = p.x[slot_i];
-                yi = p.y[slot_i];
-                zi = p.z[slot_i];
-            }
-            if (!s.fits) {
-                if (mode == 2)
-                    walk_list<LANES, 2, false, true>(p, s, slot_i, sub, cnt, xi, yi, zi, a);
-                else
-                    walk_list<LANES, 1, false, true>(p, s, slot_i, sub, cnt, xi, yi, zi, a);
-            } else if (mode == 0) {
-                walk_list<LANES, 0, true, false>(p, s, slot_i, sub, cnt, xi, yi, zi, a);
-            } else if (mode == 1) {
-                walk_list<LANES, 1, true, false>(p, s, slot_i, sub, cnt, xi, yi, zi, a);
-            } else {
-                walk_list<LANES, 2, true, true>(p, s, slot_i, sub, cnt, xi, yi, zi, a);
-            }
+            home_position(p, s, h0, h, slot_i, xi, yi, zi);
+            ForceOp<Acc> op{p, a};
+            walk_home<LANES>(p, s, mode, slot_i, sub, p.nl_count[slot_i], xi, yi, zi, op);
         }
         if (LANES > 1) {
             a.fx = lane_group_sum<LANES>(a.fx);

@@ -38,6 +38,7 @@ struct KParams {
     int32_t n, npad, nc, ncell, cap, potential, precision, mode, reorder, newton3;
     // constants (all formed once on the host)
     double L, invL, inv_w, rc2, rl2, sig2, eps2, eps48, half_shift, hdt, dt, disp_thr2, mass;
+    double eps, sigma;
     double inner_lo, inner_hi;  // atoms with every coordinate in [lo, hi] need no minimum image
     // state (caller-owned)
     double *x, *y, *z, *vx, *vy, *vz;
@@ -67,6 +68,35 @@ struct KParams {
     int32_t scap;           // staged atoms a workgroup's LDS holds
 };
 
+// Arguments of one reverse-mode point (md_adjoint.hip).  lambda_x is the
+// adjoint of the positions, lambda_v that of the velocities; the point reads
+// vx/vy/vz (lambda_v of this point) and writes nx/ny/nz (lambda_v after the
+// drift of the step before it).
+struct AdjArgs {
+    double *lx, *ly, *lz;
+    const double *vx, *vy, *vz;
+    double *nx, *ny, *nz;
+    double* theta;         // [2] accumulated dL/deps, dL/dsigma
+    double* tpart;         // [workgroups][2] partials of this launch
+    const double* gobs;    // dL/d(observables); gobs[0] = dL/dubar
+    double coef;           // (dt/2m) times the number of half kicks that use F here
+    double loss_scale;     // 1/(S N) when the mean energy depends on this point, else 0
+    double drift;          // dt when a drift precedes this point, else 0
+    int32_t cap;           // staged atoms with positions and lambda_v
+};
+
+// Soft g(r) (md_adjoint.hip): n_bins bins on [0, rmax), Gaussian kernel of
+// standard deviation width lowered by its value at 3 widths and cut there.
+struct GrArgs {
+    unsigned long long* hist;  // [n_bins] fixed-point sums
+    double* out;               // [n_bins] g_b
+    const double* gobs;        // dL/d(observables); gobs[1 + b] = dL/dg_b (gradient only)
+    double* lx;                // gradient output (x); ly, lz follow
+    double *ly, *lz;
+    int32_t n_bins;
+    double rmax, width, scale;  // scale: fixed-point units per unit of kernel value
+};
+
 // Largest number of force-pass workgroups any tuning can ask for.
 inline int64_t max_force_blocks(int64_t n, int64_t ncell)
 {
@@ -75,6 +105,14 @@ inline int64_t max_force_blocks(int64_t n, int64_t ncell)
 }
 
 // Host-side launchers (one translation unit per stage).
+void launch_adj_reimage(const KParams& p, const double* px, const double* py, const double* pz,
+                        hipStream_t s);
+void launch_adj_point(const KParams& p, const AdjArgs& a, hipStream_t s);
+void launch_gr(const KParams& p, const GrArgs& g, hipStream_t s);
+void launch_gr_grad(const KParams& p, const GrArgs& g, hipStream_t s);
+void launch_traj_ubar(const KParams& p, int32_t n_steps, double* out, hipStream_t s);
+void launch_fill(double* a, size_t n, double v, hipStream_t s);
+int adj_stage_cap(const KParams& p, size_t lds_limit);
 void launch_clear(const KParams& p, hipStream_t s);
 void launch_cells(const KParams& p, int force, hipStream_t s);
 void launch_neighbors(const KParams& p, int force, hipStream_t s);

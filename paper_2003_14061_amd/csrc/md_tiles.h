@@ -60,15 +60,18 @@ __device__ __forceinline__ Tile tile_of(const KParams& p, int t)
 
 // LDS view of one staged tile.  Entry `total` of xs, ys, zs holds a sentinel
 // atom far outside the box; list chunks are padded with its index, so a
-// padded entry never falls inside the cutoff.
+// padded entry never falls inside the cutoff.  Kernels that also need a
+// per-atom vector of each partner (the adjoint's lambda) stage it in ax,
+// ay, az beside the positions.
 struct Stage {
-    MD_LDS double *xs, *ys, *zs;  // [scap]
+    MD_LDS double *xs, *ys, *zs;  // [cap]
+    MD_LDS double *ax, *ay, *az;  // [cap] when staged with an auxiliary vector
     MD_LDS int* off;              // [ntab + 1] LDS offset of each staged cell
     MD_LDS int* slot;             // [ntab] global slot of each staged cell's first atom
     MD_LDS int* flag;             // [ntab] wrap bits
     MD_LDS int* scan;             // [kWave] scratch
-    int ntab, stride, total;
-    bool fits;                    // total + 1 <= scap: positions (and sentinel) staged
+    int ntab, stride, total, cap;
+    bool fits;                    // total + 1 <= cap: positions (and sentinel) staged
 };
 
 constexpr double kSentinel = 1.0e30;
@@ -80,24 +83,35 @@ __host__ __device__ __forceinline__ int stage_table_ints(int kx_max)
     return (3 * ntab + 1 + kWave + 3) / 4 * 4;
 }
 
-// Dynamic LDS bytes of the staged tile.
-inline size_t stage_bytes(int scap, int kx_max)
+// Dynamic LDS bytes of the staged tile: positions (and with `aux` a second
+// 3-vector) of cap atoms, then the cell tables.
+inline size_t stage_bytes(int cap, int kx_max, bool aux = false)
 {
-    return sizeof(double) * 3 * (size_t)scap + sizeof(int) * (size_t)stage_table_ints(kx_max);
+    return sizeof(double) * (aux ? 6 : 3) * (size_t)cap +
+           sizeof(int) * (size_t)stage_table_ints(kx_max);
 }
 
-__device__ __forceinline__ Stage stage_layout(const KParams& p, char* smem)
+__device__ __forceinline__ Stage stage_layout(const KParams& p, char* smem, int cap, bool aux)
 {
     Stage s;
+    s.cap = cap;
     s.xs = (MD_LDS double*)smem;
-    s.ys = s.xs + p.scap;
-    s.zs = s.ys + p.scap;
+    s.ys = s.xs + cap;
+    s.zs = s.ys + cap;
+    s.ax = aux ? s.zs + cap : nullptr;
+    s.ay = aux ? s.ax + cap : nullptr;
+    s.az = aux ? s.ay + cap : nullptr;
     const int ntab_max = 9 * (p.kx_max + 2);
-    s.off = (MD_LDS int*)(s.zs + p.scap);
+    s.off = (MD_LDS int*)(s.zs + (aux ? 4 : 1) * cap);
     s.slot = s.off + ntab_max + 1;
     s.flag = s.slot + ntab_max;
     s.scan = s.flag + ntab_max;
     return s;
+}
+
+__device__ __forceinline__ Stage stage_layout(const KParams& p, char* smem)
+{
+    return stage_layout(p, smem, p.scap, false);
 }
 
 // Cell tables of tile g: slots, wrap bits and LDS offsets of the staged
@@ -144,7 +158,7 @@ __device__ __forceinline__ void stage_tables(const KParams& p, const Tile& g, St
     }
     if (threadIdx.x == 0) s.off[s.ntab] = carry;
     s.total = carry;
-    s.fits = carry < p.scap;
+    s.fits = carry < s.cap;
     __syncthreads();
 }
 
@@ -160,33 +174,47 @@ __device__ __forceinline__ int staged_cell(const Stage& s, int k)
     return lo;
 }
 
-// Positions of the staged atoms into LDS (when they fit), plus the sentinel.
-// Each thread takes entries tid, tid + blockDim, ... four at a time, so that
-// several loads are in flight per thread.  No barrier: the caller syncs.
-__device__ __forceinline__ void stage_positions(const KParams& p, const Stage& s)
+// Positions of the staged atoms into LDS (when they fit), plus the sentinel;
+// with kAux also the vector (vx, vy, vz) of each staged atom (zero for the
+// sentinel).  Each thread takes entries tid, tid + blockDim, ... four at a
+// time, so that several loads are in flight per thread.  No barrier: the
+// caller syncs.
+template <bool kAux>
+__device__ __forceinline__ void stage_atoms(const KParams& p, const Stage& s, const double* vx,
+                                            const double* vy, const double* vz)
 {
     if (!s.fits) return;
     constexpr int U = 4;
     for (int k0 = threadIdx.x; k0 < s.total; k0 += U * blockDim.x) {
-        double vx[U], vy[U], vz[U];
+        double px[U], py[U], pz[U], qx[U], qy[U], qz[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = k0 + u * blockDim.x;
             if (k < s.total) {
                 const int t = staged_cell(s, k);
                 const int j = atom_at(p, s.slot[t] + (k - s.off[t]));
-                vx[u] = p.x[j];
-                vy[u] = p.y[j];
-                vz[u] = p.z[j];
+                px[u] = p.x[j];
+                py[u] = p.y[j];
+                pz[u] = p.z[j];
+                if (kAux) {
+                    qx[u] = vx[j];
+                    qy[u] = vy[j];
+                    qz[u] = vz[j];
+                }
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = k0 + u * blockDim.x;
             if (k < s.total) {
-                s.xs[k] = vx[u];
-                s.ys[k] = vy[u];
-                s.zs[k] = vz[u];
+                s.xs[k] = px[u];
+                s.ys[k] = py[u];
+                s.zs[k] = pz[u];
+                if (kAux) {
+                    s.ax[k] = qx[u];
+                    s.ay[k] = qy[u];
+                    s.az[k] = qz[u];
+                }
             }
         }
     }
@@ -194,7 +222,17 @@ __device__ __forceinline__ void stage_positions(const KParams& p, const Stage& s
         s.xs[s.total] = kSentinel;
         s.ys[s.total] = kSentinel;
         s.zs[s.total] = kSentinel;
+        if (kAux) {
+            s.ax[s.total] = 0.0;
+            s.ay[s.total] = 0.0;
+            s.az[s.total] = 0.0;
+        }
     }
+}
+
+__device__ __forceinline__ void stage_positions(const KParams& p, const Stage& s)
+{
+    stage_atoms<false>(p, s, nullptr, nullptr, nullptr);
 }
 
 // Atom (storage slot) of staged entry e.
@@ -247,6 +285,110 @@ __device__ __forceinline__ bool tile_interior(const KParams& p, const Tile& g)
 {
     return p.nc >= 5 && g.cx0 >= 1 && g.cx0 + g.kx <= p.nc - 1 && g.cy >= 1 &&
            g.cy <= p.nc - 2 && g.cz >= 1 && g.cz <= p.nc - 2;
+}
+
+// ---- walking one home atom's list ----
+//
+// The pair operation `op(dx, dy, dz, r2, e, j)` gets the minimum-image
+// separation home - partner, its squared length, the partner's staged
+// index e and, when the tile's atoms did not fit in LDS, its storage slot j
+// (-1 otherwise).  It applies its own cutoff.
+
+// The 4 entries of one chunk.  kMask = false: partners from LDS, padded
+// entries point at the sentinel atom, nothing needs masking (wrap-bit image
+// modes only).  kMask = true: entries past the list are masked; with
+// kFits = false the partners come from global memory.
+template <int kImage, bool kFits, bool kMask, class Op>
+__device__ __forceinline__ void chunk_pairs(const KParams& p, const Stage& s, uint64_t ch,
+                                            int mbase, int cnt, double xi, double yi, double zi,
+                                            Op& op)
+{
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+        const uint32_t v = (uint32_t)(ch >> (16 * k)) & 0xffffu;
+        const bool valid = !kMask || mbase + k < cnt;
+        int e = (int)(v & kEntryMask);
+        double xj, yj, zj;
+        int j = -1;
+        if (kFits) {
+            if (kMask) e = valid ? e : 0;
+            xj = s.xs[e];
+            yj = s.ys[e];
+            zj = s.zs[e];
+        } else {
+            j = staged_slot(p, s, valid && e < s.total ? e : 0);
+            xj = p.x[j];
+            yj = p.y[j];
+            zj = p.z[j];
+        }
+        double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+        image<kImage>(p, (int)(v >> kEntryBits), dx, dy, dz);
+        const double r2 = dist2(dx, dy, dz);
+        if (valid) op(dx, dy, dz, r2, e, j);
+    }
+}
+
+// Chunks c = sub, sub+LANES, ... of one home atom's list, each loaded one
+// step ahead of its use.
+template <int LANES, int kImage, bool kFits, bool kMask, class Op>
+__device__ __forceinline__ void walk_list(const KParams& p, const Stage& s, int slot_i, int sub,
+                                          int cnt, double xi, double yi, double zi, Op& op)
+{
+    const int nchunk = (cnt + kChunk - 1) / kChunk;
+    const uint64_t* col = p.nl64 + slot_i;
+    int c = sub;
+    uint64_t next = c < nchunk ? col[(int64_t)c * p.npad] : 0;
+    while (c < nchunk) {
+        const uint64_t ch = next;
+        const int cn = c + LANES;
+        if (cn < nchunk) next = col[(int64_t)cn * p.npad];
+        chunk_pairs<kImage, kFits, kMask>(p, s, ch, c * kChunk, cnt, xi, yi, zi, op);
+        c = cn;
+    }
+}
+
+// The list of one home atom, with the image rule of its tile (mode, see
+// image_mode) and the LDS or global partner path.
+template <int LANES, class Op>
+__device__ __forceinline__ void walk_home(const KParams& p, const Stage& s, int mode, int slot_i,
+                                          int sub, int cnt, double xi, double yi, double zi,
+                                          Op& op)
+{
+    if (!s.fits) {
+        if (mode == 2)
+            walk_list<LANES, 2, false, true>(p, s, slot_i, sub, cnt, xi, yi, zi, op);
+        else
+            walk_list<LANES, 1, false, true>(p, s, slot_i, sub, cnt, xi, yi, zi, op);
+    } else if (mode == 0) {
+        walk_list<LANES, 0, true, false>(p, s, slot_i, sub, cnt, xi, yi, zi, op);
+    } else if (mode == 1) {
+        walk_list<LANES, 1, true, false>(p, s, slot_i, sub, cnt, xi, yi, zi, op);
+    } else {
+        walk_list<LANES, 2, true, true>(p, s, slot_i, sub, cnt, xi, yi, zi, op);
+    }
+}
+
+// Position of home atom h (LDS when staged).
+__device__ __forceinline__ void home_position(const KParams& p, const Stage& s, int h0, int h,
+                                              int slot_i, double& xi, double& yi, double& zi)
+{
+    if (s.fits) {
+        xi = s.xs[h0 + h];
+        yi = s.ys[h0 + h];
+        zi = s.zs[h0 + h];
+    } else {
+        xi = p.x[slot_i];
+        yi = p.y[slot_i];
+        zi = p.z[slot_i];
+    }
+}
+
+template <int LANES, typename T>
+__device__ __forceinline__ T lane_group_sum(T v)
+{
+#pragma unroll
+    for (int o = LANES / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
 }
 
 }  // namespace md

@@ -28,7 +28,8 @@ MD_ARR_CELL_OF, MD_ARR_CELL_START, MD_ARR_CELL_ATOMS, MD_ARR_NL, MD_ARR_NL_COUNT
 EXPORTS = ("md_init", "md_workspace_bytes", "md_geometry", "md_layout", "md_bind",
            "md_build_cells", "md_build_neighbors", "md_forces", "md_step", "md_reduce",
            "md_history", "md_set_tuning", "md_get_tuning", "md_set_timing", "md_get_timing",
-           "md_export_neighbors", "md_destroy", "md_status_str")
+           "md_export_neighbors", "md_traj_workspace_bytes", "md_traj_forward",
+           "md_traj_backward", "md_destroy", "md_status_str")
 
 
 class MDError(RuntimeError):
@@ -59,6 +60,11 @@ class Tuning(C.Structure):
     _fields_ = [("force_lanes", C.c_int32), ("force_block", C.c_int32),
                 ("nl_block", C.c_int32), ("tile_cells", C.c_int32), ("stage_cap", C.c_int32),
                 ("integrate_grid", C.c_int32)]
+
+
+class TrajParams(C.Structure):
+    _fields_ = [("n_steps", C.c_int32), ("checkpoint_every", C.c_int32), ("n_bins", C.c_int32),
+                ("pad", C.c_int32), ("gr_rmax", C.c_double), ("gr_width", C.c_double)]
 
 
 class Observables(C.Structure):
@@ -105,6 +111,9 @@ def lib():
         "md_get_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
         "md_set_timing": (C.c_int, [P, C.c_int32]),
         "md_get_timing": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "md_traj_workspace_bytes": (C.c_size_t, [P, C.POINTER(TrajParams)]),
+        "md_traj_forward": (C.c_int, [P, C.POINTER(TrajParams), P, P]),
+        "md_traj_backward": (C.c_int, [P, C.POINTER(TrajParams), P, P, P, P, P]),
         "md_destroy": (None, [P]),
         "md_status_str": (C.c_char_p, [C.c_int32]),
     }
@@ -188,6 +197,30 @@ def md_history(ctx, max_records: int = 4096):
     return list(buf[: n.value])
 
 
+def traj_params(n_steps, checkpoint_every=20, n_bins=0, gr_rmax=2.5, gr_width=None):
+    """Trajectory description for md_traj_*; gr_width defaults to the bin width."""
+    if gr_width is None:
+        gr_width = gr_rmax / n_bins if n_bins else 0.0
+    return TrajParams(int(n_steps), int(checkpoint_every), int(n_bins), 0, float(gr_rmax),
+                      float(gr_width))
+
+
+def md_traj_workspace_bytes(ctx, tp: TrajParams) -> int:
+    return int(lib().md_traj_workspace_bytes(ctx, C.byref(tp)))
+
+
+def md_traj_forward(ctx, tp: TrajParams, ws_ptr: int, obs_ptr: int):
+    _check(lib().md_traj_forward(ctx, C.byref(tp), C.c_void_p(ws_ptr), C.c_void_p(obs_ptr)),
+           "md_traj_forward")
+
+
+def md_traj_backward(ctx, tp: TrajParams, ws_ptr: int, gobs_ptr: int, gx_ptr: int, gv_ptr: int,
+                     gth_ptr: int):
+    _check(lib().md_traj_backward(ctx, C.byref(tp), C.c_void_p(ws_ptr), C.c_void_p(gobs_ptr),
+                                  C.c_void_p(gx_ptr), C.c_void_p(gv_ptr), C.c_void_p(gth_ptr)),
+           "md_traj_backward")
+
+
 def md_set_tuning(ctx, force_lanes=4, force_block=512, nl_block=0, tile_cells=0, stage_cap=0,
                   integrate_grid=0):
     t = Tuning(int(force_lanes), int(force_block), int(nl_block), int(tile_cells), int(stage_cap),
@@ -232,8 +265,10 @@ class Simulation:
         if not torch.cuda.is_available():
             raise RuntimeError("libmd needs a GPU; none is visible")
         lib()
-        pos = np.asarray(pos, dtype=np.float64)
-        vel = np.asarray(vel, dtype=np.float64)
+        if not isinstance(pos, torch.Tensor):
+            pos = np.asarray(pos, dtype=np.float64)
+        if not isinstance(vel, torch.Tensor):
+            vel = np.asarray(vel, dtype=np.float64)
         n = pos.shape[0]
         if reorder is None:
             reorder = bool(neighbor_list)
@@ -249,7 +284,10 @@ class Simulation:
         self.ctx = md_init(self.params)
         self._tuning = None
         self.grid = md_geometry(self.ctx)
-        t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=self.device)
+        def t(a):
+            if isinstance(a, torch.Tensor):
+                return a.detach().to(device=self.device, dtype=torch.float64).contiguous().clone()
+            return torch.as_tensor(np.ascontiguousarray(a), device=self.device)
         self.x, self.y, self.z = (t(pos[:, k]) for k in range(3))
         self.vx, self.vy, self.vz = (t(vel[:, k]) for k in range(3))
         fdt = torch.float64 if precision == "fp64" else torch.float32
@@ -295,6 +333,43 @@ class Simulation:
 
     def step(self, n_steps, record_every=0):
         md_step(self.ctx, n_steps, record_every)
+
+    # -- reverse mode
+    def traj_forward(self, n_steps, checkpoint_every=20, n_bins=0, gr_rmax=2.5, gr_width=None):
+        """Run n_steps keeping checkpoints; returns the observables (device
+        float64 tensor [1 + n_bins]: mean energy per atom over the steps, then
+        the soft g(r) of the last positions).  Needs reorder=False."""
+        import torch
+
+        tp = traj_params(n_steps, checkpoint_every, n_bins, gr_rmax, gr_width)
+        nbytes = md_traj_workspace_bytes(self.ctx, tp)
+        if nbytes == 0:
+            raise MDError(-1, "md_traj_workspace_bytes")
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        wp = ws.data_ptr() + (-ws.data_ptr()) % 256
+        obs = torch.empty(1 + tp.n_bins, dtype=torch.float64, device=self.device)
+        md_traj_forward(self.ctx, tp, wp, obs.data_ptr())
+        self._traj = (tp, ws, wp)
+        return obs
+
+    def traj_backward(self, grad_obs):
+        """dL/dx0 [n,3], dL/dv0 [n,3], dL/d(eps, sigma) [2] for dL/dobs =
+        grad_obs, after traj_forward (storage order; reorder=False keeps it
+        the input order)."""
+        import torch
+
+        if getattr(self, "_traj", None) is None:
+            raise RuntimeError("traj_backward needs a traj_forward first")
+        tp, ws, wp = self._traj
+        gobs = grad_obs.detach().to(device=self.device, dtype=torch.float64).contiguous()
+        if gobs.numel() != 1 + tp.n_bins:
+            raise ValueError("grad_obs must hold 1 + n_bins values")
+        gx = torch.empty(3, self.n, dtype=torch.float64, device=self.device)
+        gv = torch.empty(3, self.n, dtype=torch.float64, device=self.device)
+        gth = torch.empty(2, dtype=torch.float64, device=self.device)
+        md_traj_backward(self.ctx, tp, wp, gobs.data_ptr(), gx.data_ptr(), gv.data_ptr(),
+                         gth.data_ptr())
+        return gx.t().contiguous(), gv.t().contiguous(), gth
 
     def reduce(self, check=True) -> dict:
         o = md_reduce(self.ctx, check=check)

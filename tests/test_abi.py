@@ -110,3 +110,23 @@ def test_calls_before_bind_fail_cleanly():
         md.md_destroy(ctx)
     assert md.lib().md_build_cells(None) == -1
     md.lib().md_destroy(None)
+
+
+def test_trajectory_workspace_is_validated_on_the_host():
+    ctx = md.md_init(params(n=32000, rho=0.8, r_cut=2.5, reorder=0))
+    try:
+        ok = md.traj_params(200, 20, 50, 2.5)
+        b = md.md_traj_workspace_bytes(ctx, ok)
+        n = 32000
+        # 11 checkpoints of 6 arrays, 19 snapshots of 3, 9 adjoint arrays
+        assert b >= (11 * 6 + 19 * 3 + 9) * 8 * n
+        assert b < (11 * 6 + 19 * 3 + 9) * 8 * n + 4 * 1024 * 1024
+        # an interval beyond the run is one segment: 2 checkpoints, 199 snapshots
+        one = md.md_traj_workspace_bytes(ctx, md.traj_params(200, 1000))
+        assert one == md.md_traj_workspace_bytes(ctx, md.traj_params(200, 200)) > b
+        for bad in (md.traj_params(0, 20), md.traj_params(4097, 20), md.traj_params(10, 0),
+                    md.traj_params(10, 5, 1025, 2.5), md.traj_params(10, 5, 10, 2.5, 0.0),
+                    md.traj_params(10, 5, 10, -1.0, 0.1)):
+            assert md.md_traj_workspace_bytes(ctx, bad) == 0
+    finally:
+        md.md_destroy(ctx)
