@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-mixed measurement")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint/forward ratio of the differentiable run")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     return ap.parse_args()
@@ -141,6 +143,49 @@ def run_gpu(w, precision, steps, warmup):
     del sim
     torch.cuda.synchronize()
     return res
+
+
+def run_adjoint(precision, repeats=3):
+    """Adjoint/forward time ratio on the differentiable run: LJ r_c 2.5,
+    N = 32000 (20^3 FCC, rho 0.8, T 1), dt 0.004, 200 steps, checkpoints every
+    20, loss = mean potential energy per atom + sum_b (g_b - g*_b)^2 over 50
+    soft g(r) bins on [0, 2.5), g* from a seeded reference run at
+    (eps, sigma) = (1.05, 0.98) from the same initial state.  Forward = the
+    checkpointed run with its observables; backward = segment recompute plus
+    the reverse pass.  Median of `repeats` timings of each."""
+    import torch
+
+    from paper_2003_14061_amd import inputs, md
+
+    w = inputs.preset("lj_32k").materialize()
+    S, k, B = 200, 20, 50
+
+    def sim_at(eps, sigma):
+        return md.Simulation(w.pos, w.vel, w.L, r_cut=2.5 * sigma, skin=w.skin, dt=w.dt,
+                             eps=eps, sigma=sigma, precision=precision, reorder=False)
+
+    target = sim_at(1.05, 0.98).traj_forward(S, k, B, 2.5)[1:]
+    sim = sim_at(1.0, 1.0)
+    tf, tb = [], []
+    for _ in range(repeats + 1):  # the first pass is a warm-up
+        sim = sim_at(1.0, 1.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        obs = sim.traj_forward(S, k, B, 2.5)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gobs = torch.cat([torch.ones(1, dtype=torch.float64, device=obs.device),
+                          2.0 * (obs[1:] - target)])
+        gx, gv, gth = sim.traj_backward(gobs)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tf.append(t1 - t0)
+        tb.append(t2 - t1)
+    tf, tb = sorted(tf[1:]), sorted(tb[1:])
+    fwd, bwd = tf[len(tf) // 2], tb[len(tb) // 2]
+    return {"ratio": bwd / fwd, "forward_ms": 1e3 * fwd, "backward_ms": 1e3 * bwd,
+            "forward_atom_steps_per_s": w.n * S / fwd,
+            "grad_eps": float(gth[0]), "grad_sigma": float(gth[1])}
 
 
 def in_range_pairs(sim, w, sample=20000):
@@ -266,7 +311,21 @@ def main():
                              "energy_drift_per_atom": mixed["energy_drift_per_atom"],
                              "force_ms_avg": round(mixed["force_ms_avg"], 5),
                              "speedup_vs_fp64": round(mixed["value"] / fp64["value"], 3)}
-    out["adjoint_forward_ratio"] = None
+    if not args.no_adjoint:
+        adj = {}
+        for prec, key in (("fp64", "fp64"), ("fp32", "fp32_mixed")):
+            r = run_adjoint(prec)
+            adj[key] = {k: round(v, 6) for k, v in r.items()}
+            print(f"[bench] adjoint {key} done: ratio {r['ratio']:.3f}", file=sys.stderr,
+                  flush=True)
+        out["adjoint_forward_ratio"] = {
+            "fp64": adj["fp64"]["ratio"], "fp32_mixed": adj["fp32_mixed"]["ratio"],
+            "workload": "lj_32k: LJ r_c=2.5, N=32000 FCC, rho=0.8, T=1, dt=0.004, 200 steps, "
+                        "checkpoints every 20, loss = mean PE/N + soft g(r) (50 bins) "
+                        "mismatch against a run at eps=1.05, sigma=0.98",
+            "detail": adj}
+    else:
+        out["adjoint_forward_ratio"] = None
     print(json.dumps(out), flush=True)
 
 

@@ -303,6 +303,72 @@ md_status md_traj_backward(md_ctx* ctx, const md_traj_params* tp, void* traj_ws,
 
 void md_destroy(md_ctx* ctx);
 
+/* ---- Batched replicas ----
+ *
+ * Many independent systems advanced together: section 4.3 runs a set of
+ * mutually invisible realizations in one program so that systems too small
+ * for the GPU still fill it (the single-system kernels are those of section
+ * 2.3).  Every kernel of a step is one launch over all
+ * replicas: each workgroup finds its replica in a table and works on that
+ * replica's data, so replicas of very different sizes share the machine
+ * without one launch per replica.  md_batch_run captures a whole run in one
+ * HIP graph and launches it once (the graph is kept and relaunched while the
+ * step count, record interval and tuning stay the same).
+ *
+ * Every replica is an ordinary context (md_init parameters; its results are
+ * read with md_reduce, md_history and md_layout on md_batch_replica()), owned
+ * by the batch: do not md_destroy it or md_bind it yourself.  All replicas
+ * must share precision, mode, reorder and block; the launch shape (md_tuning)
+ * applies to all of them, with tile_cells = 0 resolved per replica from its
+ * density. */
+typedef struct md_batch md_batch;
+
+/* Validates params[0 .. n_replicas-1] (each as md_init would) and plans the
+ * shared workspace.  MD_ERR_ARG if the replicas disagree on precision, mode,
+ * reorder or block. */
+md_status md_batch_init(const md_params* params, int32_t n_replicas, md_batch** out);
+
+/* Bytes of the one workspace block of the whole batch (256-byte aligned). */
+size_t md_batch_workspace_bytes(const md_batch* b);
+
+/* The context of replica r (owned by the batch). */
+md_status md_batch_replica(md_batch* b, int32_t r, md_ctx** ctx);
+
+/* buffers[r]: the state arrays of replica r (its workspace field is
+ * ignored); workspace: md_batch_workspace_bytes() bytes, 256-byte aligned.
+ * The stream must be a created stream (not the legacy null stream), since
+ * md_batch_run captures graphs on it.  Clears every replica's device state;
+ * copies the launch tables to the device (synchronously). */
+md_status md_batch_bind(md_batch* b, const md_buffers* buffers, void* workspace, void* stream);
+
+/* Cells, lists and forces of every replica from scratch.  Enqueued. */
+md_status md_batch_prepare(md_batch* b);
+
+/* n_steps leapfrog steps of every replica (as md_step).  use_graph != 0:
+ * the run is captured once into a HIP graph and launched as one graph
+ * (relaunched on later calls with the same n_steps and record_every);
+ * 0: the kernels are launched one by one.  Needs md_batch_prepare after
+ * binding or retuning.  Enqueued. */
+md_status md_batch_run(md_batch* b, int32_t n_steps, int32_t record_every, int32_t use_graph);
+
+/* Launch shape of every replica (see md_tuning); lists and forces must be
+ * rebuilt afterwards (md_batch_prepare). */
+md_status md_batch_set_tuning(md_batch* b, const md_tuning* tuning);
+md_status md_batch_get_tuning(const md_batch* b, md_tuning* tuning);
+
+/* Autotuner (the best workgroup size depends on the GPU and the model,
+ * section 4.1 factor (2)): for each of the n candidate shapes, rebuild the replicas'
+ * cells and lists with it and time `reps` list builds and force passes (HIP
+ * events on the bound stream); the cost of a candidate is the mean force
+ * pass plus a tenth of the mean list build (a rebuild every ~10 steps).
+ * Writes the costs (ms) to ms_out[n] and the index of the cheapest to *best,
+ * and leaves the batch set to it and prepared.  Synchronizes the stream.
+ * Positions are only folded into the box and, with reorder, permuted. */
+md_status md_batch_autotune(md_batch* b, const md_tuning* candidates, int32_t n, int32_t reps,
+                            double* ms_out, int32_t* best);
+
+void md_batch_destroy(md_batch* b);
+
 /* Static string for a status code. */
 const char* md_status_str(int32_t status);
 

@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void k_adj_reimage(KParams p, const double* px
         for (int w = 0; w < (int)blockDim.x / kWave; ++w) t = red[w] > t ? red[w] : t;
         p.ipart[8 * blockIdx.x + 4] = t;
     }
-    if (!last_block(p.dev)) return;
+    if (!last_block(p.dev, gridDim.x)) return;
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int b = 0; b < (int)gridDim.x; ++b) {
@@ -213,7 +213,7 @@ __global__ void k_adj_point(KParams p, AdjArgs q)
         q.tpart[2 * blockIdx.x] = th[0];
         q.tpart[2 * blockIdx.x + 1] = th[1];
     }
-    if (!last_block(p.dev)) return;
+    if (!last_block(p.dev, gridDim.x)) return;
     double v[2] = {0.0, 0.0};
     for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
         v[0] += q.tpart[2 * b];

@@ -16,38 +16,10 @@
 
 using namespace md;
 
-namespace {
+#include "md_ctx.h"
 
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-enum Region {
-    R_DEV, R_CELL_COUNT, R_CELL_START, R_CELL_OF, R_SLOT, R_ORDER, R_TMP, R_NL, R_NL_COUNT,
-    R_XR, R_YR, R_ZR, R_SX, R_SY, R_SZ, R_SVX, R_SVY, R_SVZ, R_SFX, R_SFY, R_SFZ, R_SID,
-    R_SCELL, R_FPART, R_IPART, R_SCAN, R_HIST, R_COUNT
-};
-
-}  // namespace
-
-struct md_ctx {
-    md_params prm;
-    md_grid geo;
-    KParams kp;
-    size_t off[R_COUNT];
-    size_t bytes[R_COUNT];
-    size_t ws_bytes;
-    hipStream_t stream = nullptr;
-    bool bound = false, cells_ok = false, nl_ok = false, forces_ok = false;
-    int nl_block_req = 0;  // requested list-build workgroup size (0: one wave per tile cell)
-    bool timing = false;
-    std::vector<hipEvent_t> ev_free, ev_pending;  // pending holds start/stop pairs
-    double timed_ms = 0.0;
-    int64_t timed_launches = 0;
-    size_t lds_limit = 160 * 1024;  // per-workgroup LDS; refreshed from the device at bind
-    int tile_cells = 0;
-    int stage_cap = 0;              // requested staged-atom capacity (0: from density)
-};
+using md::align_up;
+using md::kAlign;
 
 extern "C" const char* md_status_str(int32_t st)
 {
@@ -406,11 +378,10 @@ extern "C" md_status md_step(md_ctx* c, int32_t n_steps, int32_t record_every)
     if (!c->bound) return MD_ERR_NOT_BOUND;
     if (!c->forces_ok) return MD_ERR_STATE;
     if (n_steps == 0) return MD_OK;
-    KParams k = c->kp;
+    const KParams& k = c->kp;
     const bool nl = c->prm.mode == MD_NEIGHBOR_LIST;
-    k.record_every = record_every;
     for (int32_t s = 0; s < n_steps; ++s) {
-        launch_integrate(k, s == 0 ? 0 : 1, c->stream);
+        launch_integrate(k, s == 0 ? 0 : 1, record_every, c->stream);
         launch_cells(k, 0, c->stream);
         if (nl) launch_neighbors(k, 0, c->stream);
         timed_forces(c);
@@ -419,7 +390,7 @@ extern "C" md_status md_step(md_ctx* c, int32_t n_steps, int32_t record_every)
             if (st != MD_OK) return st;
         }
     }
-    launch_integrate(k, 2, c->stream);
+    launch_integrate(k, 2, record_every, c->stream);
     return launched();
 }
 
@@ -668,7 +639,7 @@ extern "C" md_status md_traj_backward(md_ctx* c, const md_traj_params* tp, void*
         if ((st = checkpoint(c, ck, false)) != MD_OK) return st;
         rebuild_all(c);
         for (int j = 1; j < s1 - s0; ++j) {
-            launch_integrate(k, j == 1 ? 0 : 1, sm);
+            launch_integrate(k, j == 1 ? 0 : 1, 0, sm);
             launch_cells(k, 0, sm);
             launch_neighbors(k, 0, sm);
             launch_forces(k, sm);

@@ -13,23 +13,26 @@
 //   k_copyback
 //
 // Every kernel returns at once unless the rebuild flag is set (or the call
-// forces the build), so a step's launch sequence is fixed.
+// forces the build), so a step's launch sequence is fixed.  Each kernel is a
+// template over where its parameters come from (one system, or one replica
+// of a batch: md_internal.h).
 #include "md_device.h"
 
 namespace md {
-
-constexpr int kScanThreads = 256;
-constexpr int kScanPer = 4;
-constexpr int kScanTile = kScanThreads * kScanPer;
 
 __device__ __forceinline__ bool rebuild_on(const KParams& p, int force)
 {
     return force || p.dev->rebuild;
 }
 
-__global__ void k_clear(KParams p)
+template <class B>
+__global__ void k_clear(B b)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    Wg wg;
+    const KParams* pp = b.slot(G_CELLWAVES, wg);
+    if (!pp) return;
+    const KParams& p = *pp;
+    int i = wg.id * blockDim.x + threadIdx.x;
     if (i < p.ncell) p.cell_count[i] = 0;
     if (i == 0) {
         DevState* d = p.dev;
@@ -46,10 +49,15 @@ __global__ void k_clear(KParams p)
     }
 }
 
-__global__ void k_bin(KParams p, int force)
+template <class B>
+__global__ void k_bin(B b, int force)
 {
+    Wg wg;
+    const KParams* pp = b.slot(G_ATOMS, wg);
+    if (!pp) return;
+    const KParams& p = *pp;
     if (!rebuild_on(p, force)) return;
-    int i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    int i = xcd_tile(wg.id, wg.n) * blockDim.x + threadIdx.x;
     if (i >= p.n) return;
     // positions are folded into [0, L) here, at each cell build, and drift
     // freely in between (by less than skin/2), so the wrap bits of the
@@ -95,10 +103,15 @@ __device__ __forceinline__ int block_excl_scan(int v, int* total)
 }
 
 // Per tile: sum and max of the counts.
-__global__ __launch_bounds__(kScanThreads) void k_scan_partial(KParams p, int force)
+template <class B>
+__global__ __launch_bounds__(kScanThreads) void k_scan_partial(B b, int force)
 {
+    Wg wg;
+    const KParams* pp = b.slot(G_SCAN, wg);
+    if (!pp) return;
+    const KParams& p = *pp;
     if (!rebuild_on(p, force)) return;
-    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+    const int base = wg.id * kScanTile + threadIdx.x * kScanPer;
     int s = 0, m = 0;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
@@ -122,15 +135,21 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partial(KParams p, int fo
             ts += ss[w];
             tm = sm[w] > tm ? sm[w] : tm;
         }
-        p.scanpart[2 * blockIdx.x] = ts;
-        p.scanpart[2 * blockIdx.x + 1] = tm;
+        p.scanpart[2 * wg.id] = ts;
+        p.scanpart[2 * wg.id + 1] = tm;
     }
 }
 
 // One workgroup: exclusive scan of the tile sums (in place), largest occupancy.
-__global__ __launch_bounds__(kScanThreads) void k_scan_top(KParams p, int ntile, int force)
+template <class B>
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(B b, int force)
 {
+    Wg wg;
+    const KParams* pp = b.slot(G_ONE, wg);
+    if (!pp) return;
+    const KParams& p = *pp;
     if (!rebuild_on(p, force)) return;
+    const int ntile = grid_of(p, G_SCAN);
     __shared__ int carry;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
@@ -161,10 +180,15 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(KParams p, int ntile,
 }
 
 // Per tile: local exclusive scan plus the tile offset -> cell_start; clear counts.
-__global__ __launch_bounds__(kScanThreads) void k_scan_final(KParams p, int force)
+template <class B>
+__global__ __launch_bounds__(kScanThreads) void k_scan_final(B b, int force)
 {
+    Wg wg;
+    const KParams* pp = b.slot(G_SCAN, wg);
+    if (!pp) return;
+    const KParams& p = *pp;
     if (!rebuild_on(p, force)) return;
-    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+    const int base = wg.id * kScanTile + threadIdx.x * kScanPer;
     int v[kScanPer], s = 0;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
@@ -173,7 +197,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_final(KParams p, int forc
         s += v[k];
     }
     int total;
-    int ex = block_excl_scan(s, &total) + p.scanpart[2 * blockIdx.x];
+    int ex = block_excl_scan(s, &total) + p.scanpart[2 * wg.id];
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
         int c = base + k;
@@ -185,10 +209,15 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_final(KParams p, int forc
     }
 }
 
-__global__ void k_scatter(KParams p, int force)
+template <class B>
+__global__ void k_scatter(B b, int force)
 {
+    Wg wg;
+    const KParams* pp = b.slot(G_ATOMS, wg);
+    if (!pp) return;
+    const KParams& p = *pp;
     if (!rebuild_on(p, force)) return;
-    int i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    int i = xcd_tile(wg.id, wg.n) * blockDim.x + threadIdx.x;
     if (i >= p.n) return;
     p.tmp[p.cell_start[p.cell_of[i]] + p.slot[i]] = i;
 }
@@ -196,11 +225,16 @@ __global__ void k_scatter(KParams p, int force)
 // Canonical order inside each cell: ascending permanent id.  One wave per
 // cell; each member's position is its rank, the number of members with a
 // smaller id, counted with wave shuffles (ids are distinct).
-__global__ void k_cellsort(KParams p, int force)
+template <class B>
+__global__ void k_cellsort(B b, int force)
 {
+    Wg wg;
+    const KParams* pp = b.slot(G_CELLWAVES, wg);
+    if (!pp) return;
+    const KParams& p = *pp;
     if (!rebuild_on(p, force)) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const int c = xcd_tile(blockIdx.x, gridDim.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const int c = xcd_tile(wg.id, wg.n) * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (c >= p.ncell) return;
     const int a = p.cell_start[c], cnt = p.cell_start[c + 1] - a;
     for (int i0 = 0; i0 < cnt; i0 += kWave) {
@@ -218,11 +252,15 @@ __global__ void k_cellsort(KParams p, int force)
     }
 }
 
-template <typename F>
-__global__ void k_permute(KParams p, int force)
+template <typename F, class B>
+__global__ void k_permute(B b, int force)
 {
+    Wg wg;
+    const KParams* pp = b.slot(G_ATOMS, wg);
+    if (!pp) return;
+    const KParams& p = *pp;
     if (!rebuild_on(p, force)) return;
-    int q = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    int q = xcd_tile(wg.id, wg.n) * blockDim.x + threadIdx.x;
     if (q >= p.n) return;
     const int o = p.order[q];
     p.sx[q] = p.x[o];
@@ -238,11 +276,15 @@ __global__ void k_permute(KParams p, int force)
     p.scell[q] = p.cell_of[o];
 }
 
-template <typename F>
-__global__ void k_copyback(KParams p, int force)
+template <typename F, class B>
+__global__ void k_copyback(B b, int force)
 {
+    Wg wg;
+    const KParams* pp = b.slot(G_ATOMS, wg);
+    if (!pp) return;
+    const KParams& p = *pp;
     if (!rebuild_on(p, force)) return;
-    int q = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    int q = xcd_tile(wg.id, wg.n) * blockDim.x + threadIdx.x;
     if (q >= p.n) return;
     p.x[q] = p.sx[q];
     p.y[q] = p.sy[q];
@@ -258,37 +300,47 @@ __global__ void k_copyback(KParams p, int force)
     p.order[q] = q;
 }
 
-static inline unsigned nblocks(int64_t n, int b)
+template <class B>
+static void clear_seq(const B& b, const LaunchShape& sh, hipStream_t s)
 {
-    return (unsigned)((n + b - 1) / b);
+    hipLaunchKernelGGL(k_clear<B>, dim3(sh.grid[G_CELLWAVES]), dim3(256), 0, s, b);
 }
 
-void launch_clear(const KParams& p, hipStream_t s)
+template <class B>
+static void cells_seq(const B& b, const LaunchShape& sh, int force, hipStream_t s)
 {
-    int n = p.ncell > 1 ? p.ncell : 1;
-    hipLaunchKernelGGL(k_clear, dim3(nblocks(n, 256)), dim3(256), 0, s, p);
+    const dim3 atoms(sh.grid[G_ATOMS]), blk(sh.block);
+    hipLaunchKernelGGL(k_bin<B>, atoms, blk, 0, s, b, force);
+    hipLaunchKernelGGL(k_scan_partial<B>, dim3(sh.grid[G_SCAN]), dim3(kScanThreads), 0, s, b,
+                       force);
+    hipLaunchKernelGGL(k_scan_top<B>, dim3(sh.grid[G_ONE]), dim3(kScanThreads), 0, s, b, force);
+    hipLaunchKernelGGL(k_scan_final<B>, dim3(sh.grid[G_SCAN]), dim3(kScanThreads), 0, s, b,
+                       force);
+    hipLaunchKernelGGL(k_scatter<B>, atoms, blk, 0, s, b, force);
+    hipLaunchKernelGGL(k_cellsort<B>, dim3(sh.grid[G_CELLWAVES]), dim3(256), 0, s, b, force);
+    if (sh.reorder) {
+        if (sh.precision == MD_FP64) {
+            hipLaunchKernelGGL((k_permute<double, B>), atoms, blk, 0, s, b, force);
+            hipLaunchKernelGGL((k_copyback<double, B>), atoms, blk, 0, s, b, force);
+        } else {
+            hipLaunchKernelGGL((k_permute<float, B>), atoms, blk, 0, s, b, force);
+            hipLaunchKernelGGL((k_copyback<float, B>), atoms, blk, 0, s, b, force);
+        }
+    }
 }
+
+void launch_clear(const KParams& p, hipStream_t s) { clear_seq(Single{p}, shape_of(p), s); }
 
 void launch_cells(const KParams& p, int force, hipStream_t s)
 {
-    const int b = p.block;
-    const int ntile = (int)nblocks(p.ncell, kScanTile);
-    hipLaunchKernelGGL(k_bin, dim3(nblocks(p.n, b)), dim3(b), 0, s, p, force);
-    hipLaunchKernelGGL(k_scan_partial, dim3(ntile), dim3(kScanThreads), 0, s, p, force);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, p, ntile, force);
-    hipLaunchKernelGGL(k_scan_final, dim3(ntile), dim3(kScanThreads), 0, s, p, force);
-    hipLaunchKernelGGL(k_scatter, dim3(nblocks(p.n, b)), dim3(b), 0, s, p, force);
-    hipLaunchKernelGGL(k_cellsort, dim3(nblocks((int64_t)p.ncell * kWave, 256)), dim3(256), 0, s,
-                       p, force);
-    if (p.reorder) {
-        if (p.precision == MD_FP64) {
-            hipLaunchKernelGGL(k_permute<double>, dim3(nblocks(p.n, b)), dim3(b), 0, s, p, force);
-            hipLaunchKernelGGL(k_copyback<double>, dim3(nblocks(p.n, b)), dim3(b), 0, s, p, force);
-        } else {
-            hipLaunchKernelGGL(k_permute<float>, dim3(nblocks(p.n, b)), dim3(b), 0, s, p, force);
-            hipLaunchKernelGGL(k_copyback<float>, dim3(nblocks(p.n, b)), dim3(b), 0, s, p, force);
-        }
-    }
+    cells_seq(Single{p}, shape_of(p), force, s);
+}
+
+void launch_clear(const Batch& b, const LaunchShape& sh, hipStream_t s) { clear_seq(b, sh, s); }
+
+void launch_cells(const Batch& b, const LaunchShape& sh, int force, hipStream_t s)
+{
+    cells_seq(b, sh, force, s);
 }
 
 }  // namespace md

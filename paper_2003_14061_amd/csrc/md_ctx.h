@@ -1,0 +1,42 @@
+// md_ctx.h -- the host-side context of one system (private to libmd).
+#pragma once
+
+#include <stddef.h>
+
+#include <vector>
+
+#include "md_internal.h"
+
+namespace md {
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Regions of the workspace block, in order.
+enum Region {
+    R_DEV, R_CELL_COUNT, R_CELL_START, R_CELL_OF, R_SLOT, R_ORDER, R_TMP, R_NL, R_NL_COUNT,
+    R_XR, R_YR, R_ZR, R_SX, R_SY, R_SZ, R_SVX, R_SVY, R_SVZ, R_SFX, R_SFY, R_SFZ, R_SID,
+    R_SCELL, R_FPART, R_IPART, R_SCAN, R_HIST, R_COUNT
+};
+
+}  // namespace md
+
+struct md_ctx {
+    md_params prm;
+    md_grid geo;
+    md::KParams kp;
+    size_t off[md::R_COUNT];
+    size_t bytes[md::R_COUNT];
+    size_t ws_bytes;
+    hipStream_t stream = nullptr;
+    bool bound = false, cells_ok = false, nl_ok = false, forces_ok = false;
+    int nl_block_req = 0;  // requested list-build workgroup size (0: one wave per tile cell)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_free, ev_pending;  // pending holds start/stop pairs
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+    size_t lds_limit = 160 * 1024;  // per-workgroup LDS; refreshed from the device at bind
+    int tile_cells = 0;
+    int stage_cap = 0;              // requested staged-atom capacity (0: from density)
+};

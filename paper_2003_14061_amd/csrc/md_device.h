@@ -162,8 +162,9 @@ __device__ __forceinline__ int load_coherent(const int* p)
 
 // Last-workgroup-done (the paper's completion scheme, section 2.3): every
 // workgroup publishes its partial, bumps a counter, and the one that sees
-// the final count finishes the reduction.  Returns true in every thread of
-// that last workgroup.
+// the final count finishes the reduction.  n_wg is the number of
+// workgroups of this system's share of the launch.  Returns true in every
+// thread of that last workgroup.
 //
 // The partial must have been stored by thread 0: its counter increment is a
 // release at agent scope, which orders thread 0's own earlier stores before
@@ -171,14 +172,14 @@ __device__ __forceinline__ int load_coherent(const int* p)
 // agent-scope release writes back the XCD's L2 and an acquire invalidates
 // it, so a fence in every thread of every workgroup would cost far more than
 // the reduction itself.)
-__device__ __forceinline__ bool last_block(DevState* dev)
+__device__ __forceinline__ bool last_block(DevState* dev, int n_wg)
 {
     __shared__ int is_last;
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned t = __hip_atomic_fetch_add(&dev->blocks_done, 1u, __ATOMIC_RELEASE,
                                                   __HIP_MEMORY_SCOPE_AGENT);
-        is_last = (t == gridDim.x - 1);
+        is_last = (t == (unsigned)n_wg - 1);
     }
     __syncthreads();
     const bool last = is_last != 0;

@@ -78,12 +78,16 @@ struct ForceOp {
     }
 };
 
-template <typename F, typename Acc, int LANES>
-__global__ void k_forces_tiles(KParams p)
+template <typename F, typename Acc, int LANES, class B>
+__global__ void k_forces_tiles(B b)
 {
+    Wg wg;
+    const KParams* pp = b.slot(G_TILES, wg);
+    if (!pp) return;
+    const KParams& p = *pp;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ double red[(1024 / kWave) * 2];
-    const Tile g = tile_of(p, xcd_tile(blockIdx.x, gridDim.x));
+    const Tile g = tile_of(p, xcd_tile(wg.id, wg.n));
     Stage s = stage_layout(p, smem);
     stage_tables(p, g, s);
     const int nh = home_count(s), h0 = home_first_lds(s), slot0 = home_first_slot(s);
@@ -126,8 +130,8 @@ __global__ void k_forces_tiles(KParams p)
     }
     block_sum<2>(e, red);
     if (threadIdx.x == 0) {
-        p.fpart[2 * blockIdx.x] = e[0];
-        p.fpart[2 * blockIdx.x + 1] = e[1];
+        p.fpart[2 * wg.id] = e[0];
+        p.fpart[2 * wg.id + 1] = e[1];
     }
 }
 
@@ -168,11 +172,15 @@ __device__ __forceinline__ void walk_cells(const KParams& p, int i, Acc& a)
     }
 }
 
-template <typename F, typename Acc>
-__global__ void k_forces_cells(KParams p)
+template <typename F, typename Acc, class B>
+__global__ void k_forces_cells(B b)
 {
+    Wg wg;
+    const KParams* pp = b.slot(G_TILES, wg);
+    if (!pp) return;
+    const KParams& p = *pp;
     __shared__ double red[(1024 / kWave) * 2];
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int i = xcd_tile(wg.id, wg.n) * blockDim.x + threadIdx.x;
     Acc a;
     if (i < p.n) {
         const int c = p.cell_of[i], nc = p.nc;
@@ -194,44 +202,66 @@ __global__ void k_forces_cells(KParams p)
         atomicOr(&p.dev->flags, (int)MD_FLAG_NONFINITE);
     block_sum<2>(e, red);
     if (threadIdx.x == 0) {
-        p.fpart[2 * blockIdx.x] = e[0];
-        p.fpart[2 * blockIdx.x + 1] = e[1];
+        p.fpart[2 * wg.id] = e[0];
+        p.fpart[2 * wg.id + 1] = e[1];
     }
 }
 
-template <typename F, typename Acc>
-static void launch_tiles(const KParams& p, hipStream_t s)
+template <typename F, typename Acc, class B>
+static void tiles_seq(const B& b, const LaunchShape& sh, hipStream_t s)
 {
-    const dim3 g(p.n_tiles), t(p.force_block);
-    const size_t lds = stage_bytes(p.scap, p.kx_max);
-    switch (p.force_lanes) {
-        case 8: hipLaunchKernelGGL((k_forces_tiles<F, Acc, 8>), g, t, lds, s, p); break;
-        case 2: hipLaunchKernelGGL((k_forces_tiles<F, Acc, 2>), g, t, lds, s, p); break;
-        case 4: hipLaunchKernelGGL((k_forces_tiles<F, Acc, 4>), g, t, lds, s, p); break;
-        default: hipLaunchKernelGGL((k_forces_tiles<F, Acc, 1>), g, t, lds, s, p); break;
+    const dim3 g(sh.grid[G_TILES]), t(sh.force_block);
+    const size_t lds = sh.force_lds;
+    switch (sh.force_lanes) {
+        case 8: hipLaunchKernelGGL((k_forces_tiles<F, Acc, 8, B>), g, t, lds, s, b); break;
+        case 2: hipLaunchKernelGGL((k_forces_tiles<F, Acc, 2, B>), g, t, lds, s, b); break;
+        case 4: hipLaunchKernelGGL((k_forces_tiles<F, Acc, 4, B>), g, t, lds, s, b); break;
+        default: hipLaunchKernelGGL((k_forces_tiles<F, Acc, 1, B>), g, t, lds, s, b); break;
     }
 }
 
-int force_blocks(const KParams& p)
+template <class B>
+static void forces_seq(const B& b, const LaunchShape& sh, hipStream_t s)
 {
-    if (p.mode == MD_CELLS_ONLY) return (p.n + p.block - 1) / p.block;
-    return p.n_tiles;
-}
-
-void launch_forces(const KParams& p, hipStream_t s)
-{
-    if (p.mode == MD_CELLS_ONLY) {
-        const dim3 g(p.nblk_force), t(p.block);
-        if (p.precision == MD_FP64)
-            hipLaunchKernelGGL((k_forces_cells<double, AccD>), g, t, 0, s, p);
+    if (sh.mode == MD_CELLS_ONLY) {
+        const dim3 g(sh.grid[G_TILES]), t(sh.block);
+        if (sh.precision == MD_FP64)
+            hipLaunchKernelGGL((k_forces_cells<double, AccD, B>), g, t, 0, s, b);
         else
-            hipLaunchKernelGGL((k_forces_cells<float, AccF>), g, t, 0, s, p);
+            hipLaunchKernelGGL((k_forces_cells<float, AccF, B>), g, t, 0, s, b);
         return;
     }
-    if (p.precision == MD_FP64)
-        launch_tiles<double, AccD>(p, s);
+    if (sh.precision == MD_FP64)
+        tiles_seq<double, AccD>(b, sh, s);
     else
-        launch_tiles<float, AccF>(p, s);
+        tiles_seq<float, AccF>(b, sh, s);
 }
+
+int force_blocks(const KParams& p) { return grid_of(p, G_TILES); }
+
+size_t force_lds_bytes(const KParams& p)
+{
+    return p.mode == MD_NEIGHBOR_LIST ? stage_bytes(p.scap, p.kx_max) : 0;
+}
+
+LaunchShape shape_of(const KParams& p)
+{
+    LaunchShape sh;
+    for (int k = 0; k < G_KINDS; ++k) sh.grid[k] = grid_of(p, (GridKind)k);
+    sh.block = p.block;
+    sh.force_block = p.force_block;
+    sh.force_lanes = p.force_lanes;
+    sh.nl_block = p.nl_block;
+    sh.nl_lds = p.mode == MD_NEIGHBOR_LIST ? nl_lds_bytes(p) : 0;
+    sh.force_lds = force_lds_bytes(p);
+    sh.precision = p.precision;
+    sh.reorder = p.reorder;
+    sh.mode = p.mode;
+    return sh;
+}
+
+void launch_forces(const KParams& p, hipStream_t s) { forces_seq(Single{p}, shape_of(p), s); }
+
+void launch_forces(const Batch& b, const LaunchShape& sh, hipStream_t s) { forces_seq(b, sh, s); }
 
 }  // namespace md

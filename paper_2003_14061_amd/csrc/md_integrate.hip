@@ -54,20 +54,21 @@ __device__ double finish_max(const double* part, int nb, int stride, int k, doub
 }
 
 // Finish a completed step: count it, and on steps the history asks for, sum
-// U, W (last force pass) and K, P (this kernel's partials) and append them.
-__device__ void record_step(const KParams& p, double* red)
+// U, W (last force pass) and K, P (this kernel's n_wg partials) and append
+// them.
+__device__ void record_step(const KParams& p, int n_wg, int record_every, double* red)
 {
     DevState* dd = p.dev;
     const int64_t step = dd->step + 1;
     __syncthreads();
     if (threadIdx.x == 0) dd->step = step;
-    if (!(p.record_every > 0 && step % p.record_every == 0)) return;
+    if (!(record_every > 0 && step % record_every == 0)) return;
     const double U = finish_sum(p.fpart, p.nblk_force, 2, 0, red);
     const double W = finish_sum(p.fpart, p.nblk_force, 2, 1, red);
-    const double K = finish_sum(p.ipart, gridDim.x, 8, 0, red);
-    const double Px = finish_sum(p.ipart, gridDim.x, 8, 1, red);
-    const double Py = finish_sum(p.ipart, gridDim.x, 8, 2, red);
-    const double Pz = finish_sum(p.ipart, gridDim.x, 8, 3, red);
+    const double K = finish_sum(p.ipart, n_wg, 8, 0, red);
+    const double Px = finish_sum(p.ipart, n_wg, 8, 1, red);
+    const double Py = finish_sum(p.ipart, n_wg, 8, 2, red);
+    const double Pz = finish_sum(p.ipart, n_wg, 8, 3, red);
     if (threadIdx.x == 0) {
         md_record* r = p.hist + (dd->hist_count % kHistCap);
         r->step = step;
@@ -84,17 +85,21 @@ __device__ void record_step(const KParams& p, double* red)
     }
 }
 
-template <typename F>
-__global__ __launch_bounds__(kIntThreads) void k_integrate(KParams p, int phase)
+template <typename F, class B>
+__global__ __launch_bounds__(kIntThreads) void k_integrate(B b, int phase, int record_every)
 {
+    Wg wg;
+    const KParams* pp = b.slot(G_INTEGRATE, wg);
+    if (!pp) return;
+    const KParams& p = *pp;
     __shared__ double red[(kIntThreads / kWave) * 5];
     const F* fx = static_cast<const F*>(p.fx);
     const F* fy = static_cast<const F*>(p.fy);
     const F* fz = static_cast<const F*>(p.fz);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // v^2, Px, Py, Pz, (unused)
     double dmax2 = 0.0;
-    const int stride = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += stride) {
+    const int stride = wg.n * blockDim.x;
+    for (int i = wg.id * blockDim.x + threadIdx.x; i < p.n; i += stride) {
         const double gx = (double)fx[i], gy = (double)fy[i], gz = (double)fz[i];
         double vx = p.vx[i], vy = p.vy[i], vz = p.vz[i];
         if (phase >= 1) {  // second half kick of the finished step
@@ -141,17 +146,17 @@ __global__ __launch_bounds__(kIntThreads) void k_integrate(KParams p, int phase)
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        double* o = p.ipart + 8 * blockIdx.x;
+        double* o = p.ipart + 8 * wg.id;
         o[0] = acc[0];
         o[1] = acc[1];
         o[2] = acc[2];
         o[3] = acc[3];
         o[4] = dmax2;
     }
-    if (!last_block(p.dev)) return;
-    if (phase >= 1) record_step(p, red);
+    if (!last_block(p.dev, wg.n)) return;
+    if (phase >= 1) record_step(p, wg.n, record_every, red);
     if (phase <= 1) {
-        const double m = finish_max(p.ipart, gridDim.x, 8, 4, red);
+        const double m = finish_max(p.ipart, wg.n, 8, 4, red);
         if (threadIdx.x == 0) {
             DevState* d = p.dev;
             d->dmax2 = m;
@@ -182,7 +187,7 @@ __global__ __launch_bounds__(kIntThreads) void k_observe(KParams p)
         double* o = p.ipart + 8 * blockIdx.x;
         for (int k = 0; k < 4; ++k) o[k] = acc[k];
     }
-    if (!last_block(p.dev)) return;
+    if (!last_block(p.dev, gridDim.x)) return;
     const double U = finish_sum(p.fpart, p.nblk_force, 2, 0, red);
     const double W = finish_sum(p.fpart, p.nblk_force, 2, 1, red);
     double s[4];
@@ -200,24 +205,31 @@ __global__ __launch_bounds__(kIntThreads) void k_observe(KParams p)
     }
 }
 
-static unsigned grid_for(const KParams& p)
+template <class B>
+static void integrate_seq(const B& b, const LaunchShape& sh, int phase, int record_every,
+                          hipStream_t s)
 {
-    const int g = (p.n + kIntThreads - 1) / kIntThreads;
-    return (unsigned)(g < p.int_grid ? (g > 0 ? g : 1) : p.int_grid);
+    const dim3 g(sh.grid[G_INTEGRATE]), t(kIntThreads);
+    if (sh.precision == MD_FP64)
+        hipLaunchKernelGGL((k_integrate<double, B>), g, t, 0, s, b, phase, record_every);
+    else
+        hipLaunchKernelGGL((k_integrate<float, B>), g, t, 0, s, b, phase, record_every);
 }
 
-void launch_integrate(const KParams& p, int phase, hipStream_t s)
+void launch_integrate(const KParams& p, int phase, int record_every, hipStream_t s)
 {
-    const dim3 g(grid_for(p)), t(kIntThreads);
-    if (p.precision == MD_FP64)
-        hipLaunchKernelGGL(k_integrate<double>, g, t, 0, s, p, phase);
-    else
-        hipLaunchKernelGGL(k_integrate<float>, g, t, 0, s, p, phase);
+    integrate_seq(Single{p}, shape_of(p), phase, record_every, s);
+}
+
+void launch_integrate(const Batch& b, const LaunchShape& sh, int phase, int record_every,
+                      hipStream_t s)
+{
+    integrate_seq(b, sh, phase, record_every, s);
 }
 
 void launch_observe(const KParams& p, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_observe, dim3(grid_for(p)), dim3(kIntThreads), 0, s, p);
+    hipLaunchKernelGGL(k_observe, dim3(grid_of(p, G_INTEGRATE)), dim3(kIntThreads), 0, s, p);
 }
 
 }  // namespace md

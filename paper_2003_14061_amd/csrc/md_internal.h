@@ -58,7 +58,6 @@ struct KParams {
     md_record* hist;
     int32_t nblk_force;     // workgroups of the last-configured force pass
     int32_t block;
-    int32_t record_every;   // history interval of the running md_step (0 = none)
     int32_t force_lanes;    // lanes per home atom in the tiled force pass (1, 2, 4, 8)
     int32_t force_block;    // threads per workgroup of the tiled force pass
     int32_t nl_block;       // threads per workgroup of the list build
@@ -97,6 +96,85 @@ struct GrArgs {
     double rmax, width, scale;  // scale: fixed-point units per unit of kernel value
 };
 
+// ---- where a workgroup's parameters come from ----
+
+struct Wg {
+    int id, n;  // workgroup index and count within its system's share of the launch
+};
+
+// The grid rules of the launches; a batched launch concatenates, per rule,
+// the workgroups of every replica.
+enum GridKind { G_ATOMS, G_SCAN, G_ONE, G_CELLWAVES, G_INTEGRATE, G_TILES, G_KINDS };
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 4;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+__host__ __device__ inline int grid_of(const KParams& p, GridKind k)
+{
+    auto up = [](int64_t n, int64_t b) { return (int)((n + b - 1) / b); };
+    switch (k) {
+        case G_ATOMS: return up(p.n, p.block);
+        case G_SCAN: return up(p.ncell, kScanTile);
+        case G_ONE: return 1;
+        case G_CELLWAVES: return up((int64_t)p.ncell * kWave, 256);
+        case G_INTEGRATE: {
+            const int g = up(p.n, 256);
+            return g < p.int_grid ? (g > 0 ? g : 1) : p.int_grid;
+        }
+        case G_TILES: return p.mode == MD_NEIGHBOR_LIST ? p.n_tiles : up(p.n, p.block);
+        default: return 1;
+    }
+}
+
+// A single system: the parameters are the kernel argument.
+struct Single {
+    KParams p;
+    __device__ __forceinline__ const KParams* slot(GridKind, Wg& w) const
+    {
+        w.id = (int)blockIdx.x;
+        w.n = (int)gridDim.x;
+        return &p;
+    }
+};
+
+// Independent replicas in one launch.  For grid rule k, replica r owns
+// workgroups [first[k][r], first[k][r] + count[k][r]); first is rounded up
+// to a multiple of 8 so that the XCD-aware tile order (workgroup b runs on
+// XCD b mod 8) holds inside every replica.  Workgroups in the gaps return.
+struct Batch {
+    const KParams* __restrict__ kp;     // [R] per-replica parameters (device)
+    const int32_t* __restrict__ first;  // [G_KINDS][R + 1]
+    const int32_t* __restrict__ count;  // [G_KINDS][R]
+    int32_t R;
+    __device__ __forceinline__ const KParams* slot(GridKind k, Wg& w) const
+    {
+        const int32_t* f = first + (int)k * (R + 1);
+        const int blk = (int)blockIdx.x;
+        int lo = 0, hi = R - 1;  // last replica whose first workgroup is <= blk
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (f[mid] <= blk)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        w.id = blk - f[lo];
+        w.n = count[(int)k * R + lo];
+        return w.id < w.n ? kp + lo : nullptr;
+    }
+};
+
+// Uniform launch shape: workgroups per grid rule, block sizes, dynamic LDS.
+struct LaunchShape {
+    int grid[G_KINDS];
+    int block, force_block, force_lanes, nl_block;
+    size_t nl_lds, force_lds;
+    int precision, reorder, mode;
+};
+
+LaunchShape shape_of(const KParams& p);
+
 // Largest number of force-pass workgroups any tuning can ask for.
 inline int64_t max_force_blocks(int64_t n, int64_t ncell)
 {
@@ -118,9 +196,18 @@ void launch_cells(const KParams& p, int force, hipStream_t s);
 void launch_neighbors(const KParams& p, int force, hipStream_t s);
 void launch_nl_export(const KParams& p, int32_t* out, hipStream_t s);
 void launch_forces(const KParams& p, hipStream_t s);
+// the same over a batch of replicas
+void launch_clear(const Batch& b, const LaunchShape& sh, hipStream_t s);
+void launch_cells(const Batch& b, const LaunchShape& sh, int force, hipStream_t s);
+void launch_neighbors(const Batch& b, const LaunchShape& sh, int force, hipStream_t s);
+void launch_forces(const Batch& b, const LaunchShape& sh, hipStream_t s);
+void launch_integrate(const Batch& b, const LaunchShape& sh, int phase, int record_every,
+                      hipStream_t s);
+size_t nl_lds_bytes(const KParams& p);
+size_t force_lds_bytes(const KParams& p);
 int force_blocks(const KParams& p);  // workgroups of the force pass for the current tuning
 // phase 0: kick + drift; 1: kick, record, kick + drift; 2: kick, record
-void launch_integrate(const KParams& p, int phase, hipStream_t s);
+void launch_integrate(const KParams& p, int phase, int record_every, hipStream_t s);
 void launch_observe(const KParams& p, hipStream_t s);
 
 }  // namespace md

@@ -22,7 +22,7 @@
 namespace md {
 
 // LDS bytes of the list build: the staged tile.
-inline size_t nl_lds_bytes(const KParams& p) { return stage_bytes(p.scap, p.kx_max); }
+size_t nl_lds_bytes(const KParams& p) { return stage_bytes(p.scap, p.kx_max); }
 
 __device__ __forceinline__ double readlane_f64(double v, int lane)
 {
@@ -144,11 +144,16 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
     }
 }
 
-__global__ void k_nl_tiles(KParams p, int force)
+template <class B>
+__global__ void k_nl_tiles(B b, int force)
 {
+    Wg wg;
+    const KParams* pp = b.slot(G_TILES, wg);
+    if (!pp) return;
+    const KParams& p = *pp;
     if (!force && !p.dev->rebuild) return;
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int t = xcd_tile(wg.id, wg.n);
     const Tile g = tile_of(p, t);
     Stage s = stage_layout(p, smem);
     stage_tables(p, g, s);
@@ -200,8 +205,14 @@ __global__ void k_nl_export(KParams p, int32_t* out)
 
 void launch_neighbors(const KParams& p, int force, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_nl_tiles, dim3(p.n_tiles), dim3(p.nl_block), nl_lds_bytes(p), s, p,
-                       force);
+    hipLaunchKernelGGL(k_nl_tiles<Single>, dim3(p.n_tiles), dim3(p.nl_block), nl_lds_bytes(p), s,
+                       Single{p}, force);
+}
+
+void launch_neighbors(const Batch& b, const LaunchShape& sh, int force, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_nl_tiles<Batch>, dim3(sh.grid[G_TILES]), dim3(sh.nl_block), sh.nl_lds, s,
+                       b, force);
 }
 
 void launch_nl_export(const KParams& p, int32_t* out, hipStream_t s)

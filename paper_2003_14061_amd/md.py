@@ -29,7 +29,10 @@ EXPORTS = ("md_init", "md_workspace_bytes", "md_geometry", "md_layout", "md_bind
            "md_build_cells", "md_build_neighbors", "md_forces", "md_step", "md_reduce",
            "md_history", "md_set_tuning", "md_get_tuning", "md_set_timing", "md_get_timing",
            "md_export_neighbors", "md_traj_workspace_bytes", "md_traj_forward",
-           "md_traj_backward", "md_destroy", "md_status_str")
+           "md_traj_backward", "md_batch_init", "md_batch_workspace_bytes", "md_batch_replica",
+           "md_batch_bind", "md_batch_prepare", "md_batch_run", "md_batch_set_tuning",
+           "md_batch_get_tuning", "md_batch_autotune", "md_batch_destroy", "md_destroy",
+           "md_status_str")
 
 
 class MDError(RuntimeError):
@@ -114,6 +117,17 @@ def lib():
         "md_traj_workspace_bytes": (C.c_size_t, [P, C.POINTER(TrajParams)]),
         "md_traj_forward": (C.c_int, [P, C.POINTER(TrajParams), P, P]),
         "md_traj_backward": (C.c_int, [P, C.POINTER(TrajParams), P, P, P, P, P]),
+        "md_batch_init": (C.c_int, [C.POINTER(Params), C.c_int32, C.POINTER(P)]),
+        "md_batch_workspace_bytes": (C.c_size_t, [P]),
+        "md_batch_replica": (C.c_int, [P, C.c_int32, C.POINTER(P)]),
+        "md_batch_bind": (C.c_int, [P, C.POINTER(Buffers), P, P]),
+        "md_batch_prepare": (C.c_int, [P]),
+        "md_batch_run": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32]),
+        "md_batch_set_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
+        "md_batch_get_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
+        "md_batch_autotune": (C.c_int, [P, C.POINTER(Tuning), C.c_int32, C.c_int32,
+                                        C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+        "md_batch_destroy": (None, [P]),
         "md_destroy": (None, [P]),
         "md_status_str": (C.c_char_p, [C.c_int32]),
     }
@@ -463,3 +477,160 @@ class Simulation:
         cnt = self.ws_array(MD_ARR_NL_COUNT, torch.int32)
         nl_h, cnt_h = self._host(out, cnt)
         return cnt_h, nl_h.reshape(self.grid.nl_capacity, self.grid.n_pad)
+
+
+# ---- batched replicas ------------------------------------------------------
+
+def md_batch_init(params, n):
+    arr = (Params * n)(*params)
+    b = C.c_void_p()
+    _check(lib().md_batch_init(arr, int(n), C.byref(b)), "md_batch_init")
+    return b
+
+
+def md_batch_replica(b, r):
+    c = C.c_void_p()
+    _check(lib().md_batch_replica(b, int(r), C.byref(c)), "md_batch_replica")
+    return c
+
+
+def _tuning_tuple(t: dict):
+    return Tuning(int(t.get("force_lanes", 4)), int(t.get("force_block", 512)),
+                  int(t.get("nl_block", 0)), int(t.get("tile_cells", 0)),
+                  int(t.get("stage_cap", 0)), int(t.get("integrate_grid", 0)))
+
+
+class Batch:
+    """Independent replicas advanced together (md_batch_*).
+
+    ``systems`` is a list of dicts with keys pos, vel, L, r_cut, dt and
+    optionally skin, eps, sigma, mass, shifted.  The state lives in one
+    concatenated float64 tensor per component (replica r owns the slice
+    [offsets[r], offsets[r+1])); the batch runs on its own stream so that a
+    run can be captured into a HIP graph."""
+
+    def __init__(self, systems, *, precision="fp32", neighbor_list=True, reorder=None,
+                 block=256, device="cuda"):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("libmd needs a GPU; none is visible")
+        lib()
+        if reorder is None:
+            reorder = bool(neighbor_list)
+        self.device = torch.device(device)
+        self.R = len(systems)
+        self.sizes = [len(sy["pos"]) for sy in systems]
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        params = []
+        for sy in systems:
+            params.append(Params(len(sy["pos"]), MD_LJ_SHIFTED if sy.get("shifted", True)
+                                 else MD_LJ_TRUNC, float(sy["L"]), float(sy.get("eps", 1.0)),
+                                 float(sy.get("sigma", 1.0)), float(sy.get("mass", 1.0)),
+                                 float(sy["r_cut"]), float(sy.get("skin", 0.3)), float(sy["dt"]),
+                                 MD_FP64 if precision == "fp64" else MD_FP32_MIXED,
+                                 MD_NEIGHBOR_LIST if neighbor_list else MD_CELLS_ONLY, 0,
+                                 int(sy.get("nl_capacity", 0)), int(bool(reorder)), int(block)))
+        self.params = params
+        self.ctx = md_batch_init(params, self.R)
+        self.replicas = [md_batch_replica(self.ctx, r) for r in range(self.R)]
+        pos = np.concatenate([np.asarray(sy["pos"], np.float64) for sy in systems])
+        vel = np.concatenate([np.asarray(sy["vel"], np.float64) for sy in systems])
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=self.device)
+        self.x, self.y, self.z = (t(pos[:, k]) for k in range(3))
+        self.vx, self.vy, self.vz = (t(vel[:, k]) for k in range(3))
+        fdt = torch.float64 if precision == "fp64" else torch.float32
+        ntot = int(self.offsets[-1])
+        self.fx, self.fy, self.fz = (torch.zeros(ntot, dtype=fdt, device=self.device)
+                                     for _ in range(3))
+        self.id = torch.cat([torch.arange(n, dtype=torch.int32) for n in self.sizes]).to(
+            self.device)
+        nbytes = int(lib().md_batch_workspace_bytes(self.ctx))
+        self.workspace = torch.zeros(nbytes + 256, dtype=torch.uint8, device=self.device)
+        wp = self.workspace.data_ptr() + (-self.workspace.data_ptr()) % 256
+        bufs = (Buffers * self.R)()
+        for r in range(self.R):
+            o = int(self.offsets[r])
+            ptr = lambda ten: ten.data_ptr() + o * ten.element_size()
+            bufs[r] = Buffers(*[ptr(v) for v in (self.x, self.y, self.z, self.vx, self.vy,
+                                                 self.vz, self.fx, self.fy, self.fz, self.id)],
+                              0)
+        self.stream = torch.cuda.Stream(self.device)
+        torch.cuda.synchronize(self.device)
+        _check(lib().md_batch_bind(self.ctx, bufs, C.c_void_p(wp),
+                                   C.c_void_p(self.stream.cuda_stream)), "md_batch_bind")
+        self._tuning = None
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            try:
+                self.stream.synchronize()
+                lib().md_batch_destroy(ctx)
+            except Exception:
+                pass
+            self.ctx = None
+
+    def prepare(self):
+        _check(lib().md_batch_prepare(self.ctx), "md_batch_prepare")
+
+    def run(self, n_steps, record_every=0, graph=True):
+        _check(lib().md_batch_run(self.ctx, int(n_steps), int(record_every), int(bool(graph))),
+               "md_batch_run")
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def set_tuning(self, **kw):
+        if self._tuning is None:
+            self._tuning = self.get_tuning()
+            self._tuning.update(nl_block=0, tile_cells=0, stage_cap=0, integrate_grid=0)
+        req = dict(self._tuning)
+        req.update(kw)
+        t = _tuning_tuple(req)
+        _check(lib().md_batch_set_tuning(self.ctx, C.byref(t)), "md_batch_set_tuning")
+        self._tuning = req
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(lib().md_batch_get_tuning(self.ctx, C.byref(t)), "md_batch_get_tuning")
+        return {f: getattr(t, f) for f, _ in Tuning._fields_}
+
+    def autotune(self, candidates, reps=3):
+        """Time each candidate shape (dicts of md_tuning fields) and keep the
+        cheapest; returns (index, costs in ms)."""
+        arr = (Tuning * len(candidates))(*[_tuning_tuple(c) for c in candidates])
+        ms = (C.c_double * len(candidates))()
+        best = C.c_int32()
+        _check(lib().md_batch_autotune(self.ctx, arr, len(candidates), int(reps), ms,
+                                       C.byref(best)), "md_batch_autotune")
+        self._tuning = dict(candidates[best.value])
+        return best.value, list(ms)
+
+    # -- per replica
+    def reduce(self, r, check=True) -> dict:
+        o = md_reduce(self.replicas[r], check=check)
+        return {"U": o.U, "K": o.K, "W": o.W, "P": np.array(o.P[:]), "T": o.T,
+                "pressure": o.pressure, "dmax": o.dmax, "step": o.step,
+                "n_rebuilds": o.n_rebuilds, "flags": o.flags}
+
+    def history(self, r):
+        recs = md_history(self.replicas[r])
+        dt = np.dtype([("step", "i8"), ("U", "f8"), ("K", "f8"), ("W", "f8"), ("P", "f8", 3),
+                       ("dmax", "f8"), ("rebuilt", "i4")])
+        out = np.zeros(len(recs), dt)
+        for k, rec in enumerate(recs):
+            out[k] = (rec.step, rec.U, rec.K, rec.W, tuple(rec.P), rec.dmax, rec.rebuilt)
+        return out
+
+    def state(self, r):
+        """Positions, velocities, forces of replica r (float64) in id order."""
+        self.stream.synchronize()
+        a, b = int(self.offsets[r]), int(self.offsets[r + 1])
+        x, y, z, vx, vy, vz, fx, fy, fz, ids = [t[a:b].cpu().numpy() for t in (
+            self.x, self.y, self.z, self.vx, self.vy, self.vz, self.fx, self.fy, self.fz,
+            self.id)]
+        inv = np.empty(b - a, np.int64)
+        inv[ids] = np.arange(b - a)
+        return {"pos": np.stack([x, y, z], 1)[inv], "vel": np.stack([vx, vy, vz], 1)[inv],
+                "f": np.stack([fx, fy, fz], 1).astype(np.float64)[inv]}
