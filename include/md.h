@@ -344,6 +344,15 @@ md_status md_batch_bind(md_batch* b, const md_buffers* buffers, void* workspace,
 /* Cells, lists and forces of every replica from scratch.  Enqueued. */
 md_status md_batch_prepare(md_batch* b);
 
+/* The force pass (F1, section 2.3) of every replica, one launch, on the
+ * current lists.  Enqueued. */
+md_status md_batch_forces(md_batch* b);
+
+/* md_layout of replica r, with the offset counted from the start of the
+ * batch workspace. */
+md_status md_batch_layout(const md_batch* b, int32_t r, int32_t which, size_t* offset,
+                          size_t* count);
+
 /* n_steps leapfrog steps of every replica (as md_step).  use_graph != 0:
  * the run is captured once into a HIP graph and launched as one graph
  * (relaunched on later calls with the same n_steps and record_every);

@@ -209,6 +209,24 @@ extern "C" md_status md_batch_prepare(md_batch* b)
     return prepare(b);
 }
 
+extern "C" md_status md_batch_forces(md_batch* b)
+{
+    if (!b) return MD_ERR_ARG;
+    if (!b->bound) return MD_ERR_NOT_BOUND;
+    if (!b->prepared) return MD_ERR_STATE;
+    launch_forces(b->dev, b->sh, b->stream);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_ERR_HIP;
+}
+
+extern "C" md_status md_batch_layout(const md_batch* b, int32_t r, int32_t which, size_t* offset,
+                                     size_t* count)
+{
+    if (!b || r < 0 || r >= (int32_t)b->rep.size()) return MD_ERR_ARG;
+    md_status st = md_layout(b->rep[r], which, offset, count);
+    if (st == MD_OK) *offset += b->rep_off[r];
+    return st;
+}
+
 extern "C" md_status md_batch_run(md_batch* b, int32_t n_steps, int32_t record_every,
                                   int32_t use_graph)
 {

@@ -57,18 +57,35 @@ __global__ void k_bin(B b, int force)
     if (!pp) return;
     const KParams& p = *pp;
     if (!rebuild_on(p, force)) return;
-    int i = xcd_tile(wg.id, wg.n) * blockDim.x + threadIdx.x;
-    if (i >= p.n) return;
-    // positions are folded into [0, L) here, at each cell build, and drift
-    // freely in between (by less than skin/2), so the wrap bits of the
-    // list stay valid until the next build
-    const double x = wrap(p.x[i], p.L), y = wrap(p.y[i], p.L), z = wrap(p.z[i], p.L);
-    p.x[i] = x;
-    p.y[i] = y;
-    p.z[i] = z;
-    int c = cell_of_pos(x, y, z, p);
-    p.cell_of[i] = c;
-    p.slot[i] = atomicAdd(&p.cell_count[c], 1);
+    const int i = xcd_tile(wg.id, wg.n) * blockDim.x + threadIdx.x;
+    const bool act = i < p.n;
+    int c = -1;
+    if (act) {
+        // positions are folded into [0, L) here, at each cell build, and drift
+        // freely in between (by less than skin/2), so the wrap bits of the
+        // list stay valid until the next build
+        const double x = wrap(p.x[i], p.L), y = wrap(p.y[i], p.L), z = wrap(p.z[i], p.L);
+        p.x[i] = x;
+        p.y[i] = y;
+        p.z[i] = z;
+        c = cell_of_pos(x, y, z, p);
+        p.cell_of[i] = c;
+    }
+    // Atoms stored in cell order put a wave's 64 atoms into a few cells: the
+    // lanes of one cell take one atomic together and rank themselves by
+    // their position in the wave (the in-cell order is fixed later anyway).
+    const int lane = threadIdx.x & (kWave - 1);
+    uint64_t todo = __ballot(act);
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int cl = __shfl(c, leader, kWave);
+        const uint64_t same = __ballot(act && c == cl);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&p.cell_count[cl], (int)__popcll(same));
+        base = __shfl(base, leader, kWave);
+        if (act && c == cl) p.slot[i] = base + (int)__popcll(same & ((1ull << lane) - 1ull));
+        todo &= ~same;
+    }
 }
 
 // Inclusive scan across a wave64.

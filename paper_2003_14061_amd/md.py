@@ -30,7 +30,8 @@ EXPORTS = ("md_init", "md_workspace_bytes", "md_geometry", "md_layout", "md_bind
            "md_history", "md_set_tuning", "md_get_tuning", "md_set_timing", "md_get_timing",
            "md_export_neighbors", "md_traj_workspace_bytes", "md_traj_forward",
            "md_traj_backward", "md_batch_init", "md_batch_workspace_bytes", "md_batch_replica",
-           "md_batch_bind", "md_batch_prepare", "md_batch_run", "md_batch_set_tuning",
+           "md_batch_bind", "md_batch_prepare", "md_batch_forces", "md_batch_layout",
+           "md_batch_run", "md_batch_set_tuning",
            "md_batch_get_tuning", "md_batch_autotune", "md_batch_destroy", "md_destroy",
            "md_status_str")
 
@@ -122,6 +123,9 @@ def lib():
         "md_batch_replica": (C.c_int, [P, C.c_int32, C.POINTER(P)]),
         "md_batch_bind": (C.c_int, [P, C.POINTER(Buffers), P, P]),
         "md_batch_prepare": (C.c_int, [P]),
+        "md_batch_forces": (C.c_int, [P]),
+        "md_batch_layout": (C.c_int, [P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t),
+                                      C.POINTER(C.c_size_t)]),
         "md_batch_run": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32]),
         "md_batch_set_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
         "md_batch_get_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
@@ -573,6 +577,21 @@ class Batch:
 
     def prepare(self):
         _check(lib().md_batch_prepare(self.ctx), "md_batch_prepare")
+
+    def forces(self):
+        _check(lib().md_batch_forces(self.ctx), "md_batch_forces")
+
+    def nl_counts(self, r):
+        """List length per slot of replica r (host copy)."""
+        import torch
+
+        off, cnt = C.c_size_t(), C.c_size_t()
+        _check(lib().md_batch_layout(self.ctx, int(r), MD_ARR_NL_COUNT, C.byref(off),
+                                     C.byref(cnt)), "md_batch_layout")
+        base = (-self.workspace.data_ptr()) % 256 + off.value
+        v = self.workspace[base: base + 4 * cnt.value].view(torch.int32)
+        self.stream.synchronize()
+        return v.cpu().numpy()
 
     def run(self, n_steps, record_every=0, graph=True):
         _check(lib().md_batch_run(self.ctx, int(n_steps), int(record_every), int(bool(graph))),
