@@ -56,6 +56,7 @@ typedef enum {
 enum { MD_LJ_SHIFTED = 0, MD_LJ_TRUNC = 1 };      /* potential */
 enum { MD_FP64 = 0, MD_FP32_MIXED = 1 };          /* precision */
 enum { MD_CELLS_ONLY = 0, MD_NEIGHBOR_LIST = 1 }; /* mode */
+enum { MD_NL_AUTO = 0, MD_NL_LANES = 1, MD_NL_CELL_WAVES = 2 }; /* md_tuning.nl_method */
 
 /* Device flag bits (md_observables.flags). */
 enum { MD_FLAG_NL_OVERFLOW = 1, MD_FLAG_NONFINITE = 2 };
@@ -223,13 +224,19 @@ typedef struct {
     int32_t force_lanes;    /* lanes sharing one atom's list in the force pass: 1, 2, 4, 8 */
     int32_t force_block;    /* threads per workgroup of the force pass: 64..1024, multiple of 64 */
     int32_t nl_block;       /* threads per workgroup of the list build: 64..1024, multiple of 64;
-                               0 = one wave per cell of the widest tile */
+                               0 = automatic (a lane per home atom of a mean tile, or a wave
+                               per home cell) */
     int32_t tile_cells;     /* cells per tile along x in neighbor-list mode; 0 = enough for
                                about 80% of the force workgroup's home-atom slots */
     int32_t stage_cap;      /* atoms a workgroup stages in LDS (0 = 1.5x the mean need); tiles
                                that hold more read positions from global memory instead */
-    int32_t integrate_grid; /* workgroups of the per-atom kernels (integration, observables):
-                               1..4096; 0 = 512 */
+    int32_t integrate_grid; /* 1024-thread workgroups of the per-atom kernels (integration,
+                               observables): 1..4096; 0 = 256 */
+    int32_t nl_method;      /* list build: MD_NL_LANES (one lane per home atom, for sparse
+                               cells), MD_NL_CELL_WAVES (one wave per home cell, for dense
+                               ones) or MD_NL_AUTO (lanes below 8 atoms per cell); the list
+                               is the same either way.  md_get_tuning reports the method
+                               in use */
 } md_tuning;
 
 /* md_set_tuning: change the launch shape (host only; takes effect at the

@@ -66,8 +66,20 @@ static void plan_tiles(md_ctx* c, int cells)
     k.scap = scap < 64 ? 64 : scap;
     c->tile_cells = cells;
     k.nblk_force = force_blocks(k);
-    // list build: one wave per home cell of the widest tile unless set
-    const int nlb = c->nl_block_req > 0 ? c->nl_block_req : kWave * k.kx_max;
+    // list build: a lane per home atom of a mean tile (25% spare), or a
+    // wave per home cell of the widest tile (fewer waves, each taking
+    // several cells, when a tile holds under ~24 atoms per cell)
+    k.nl_method = c->nl_method_req != MD_NL_AUTO ? c->nl_method_req
+                                                 : (occ < 8.0 ? MD_NL_LANES : MD_NL_CELL_WAVES);
+    int waves;
+    if (k.nl_method == MD_NL_LANES) {
+        waves = (int)ceil(1.25 * k.kx_max * occ / kWave);
+    } else {
+        waves = (int)ceil(k.kx_max * occ / 24.0);
+        waves = waves > k.kx_max ? k.kx_max : waves;
+    }
+    waves = waves < 1 ? 1 : waves;
+    const int nlb = c->nl_block_req > 0 ? c->nl_block_req : kWave * waves;
     k.nl_block = nlb < kWave ? kWave : (nlb > 1024 ? 1024 : nlb);
 }
 
@@ -200,6 +212,7 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
     k.force_block = 512;
     c->nl_block_req = 0;
     k.int_grid = kIntegrateGridDefault;
+    k.gate_grid = kGateGridDefault;
     plan_tiles(c, 0);
     *out = c;
     return MD_OK;
@@ -713,13 +726,15 @@ extern "C" md_status md_set_tuning(md_ctx* c, const md_tuning* t)
     if (!one_of(t->force_lanes, {1, 2, 4, 8}) || t->force_block % 64 != 0 ||
         t->force_block < 64 || t->force_block > 1024 || t->nl_block % 64 != 0 ||
         t->nl_block < 0 || t->nl_block > 1024 || t->tile_cells < 0 || t->stage_cap < 0 ||
-        t->integrate_grid < 0 || t->integrate_grid > kIntegrateGridMax)
+        t->integrate_grid < 0 || t->integrate_grid > kIntegrateGridMax ||
+        !one_of(t->nl_method, {MD_NL_AUTO, MD_NL_LANES, MD_NL_CELL_WAVES}))
         return MD_ERR_ARG;
     KParams& k = c->kp;
     const int old_tiles = k.n_tiles, old_cells = c->tile_cells;
     k.force_lanes = t->force_lanes;
     k.force_block = t->force_block;
     c->nl_block_req = t->nl_block;
+    c->nl_method_req = t->nl_method;
     k.int_grid = t->integrate_grid > 0 ? t->integrate_grid : kIntegrateGridDefault;
     c->stage_cap = t->stage_cap;
     plan_tiles(c, t->tile_cells);
@@ -737,6 +752,7 @@ extern "C" md_status md_get_tuning(const md_ctx* c, md_tuning* t)
     t->force_block = c->kp.force_block;
     t->nl_block = c->kp.nl_block;
     t->integrate_grid = c->kp.int_grid;
+    t->nl_method = c->kp.nl_method;
     t->tile_cells = c->tile_cells;
     t->stage_cap = c->kp.scap;
     return MD_OK;

@@ -33,11 +33,35 @@ struct md_batch {
 
 namespace {
 
-size_t table_bytes(int R)
+// Workgroups per replica of the rebuild-gated grid-stride kernels, and of
+// the integration (1024-thread workgroups), in a batch of R.
+int gate_share(int R)
 {
-    return align_up(sizeof(KParams) * (size_t)R) +
-           align_up(sizeof(int32_t) * (size_t)G_KINDS * (size_t)(R + 1)) +
-           align_up(sizeof(int32_t) * (size_t)G_KINDS * (size_t)R);
+    const int g = 4 * kGateGridDefault / R;
+    return g > 64 ? g : 64;
+}
+
+int integrate_share(int R)
+{
+    const int g = 2 * kIntegrateGridDefault / R;
+    return g > 8 ? g : 8;
+}
+
+// Most workgroups replica c can ask of any grid rule, for any tuning.
+int64_t max_workgroups(const md_ctx* c)
+{
+    const int64_t n = c->prm.n_atoms, ncell = c->geo.n_cells, b = c->kp.block;
+    return (n + b - 1) / b + (ncell + kScanTile - 1) / kScanTile + 1 + kIntegrateGridMax +
+           max_force_blocks(n, ncell) + 8 * G_KINDS;
+}
+
+size_t table_bytes(const md_batch* b)
+{
+    const size_t R = b->rep.size();
+    int64_t wg = 0;
+    for (const md_ctx* c : b->rep) wg += max_workgroups(c);
+    return align_up(sizeof(KParams) * R) + align_up(sizeof(int32_t) * G_KINDS * (R + 1)) +
+           align_up(sizeof(int32_t) * G_KINDS * R) + align_up(sizeof(uint16_t) * (size_t)wg);
 }
 
 void drop_graph(md_batch* b)
@@ -58,6 +82,8 @@ md_status upload(md_batch* b)
     const int R = (int)b->rep.size();
     std::vector<KParams> kp(R);
     std::vector<int32_t> first((size_t)G_KINDS * (R + 1)), count((size_t)G_KINDS * R);
+    std::vector<uint16_t> rep_of;
+    int32_t rep_base[G_KINDS];
     LaunchShape sh;
     memset(&sh, 0, sizeof(sh));
     for (int r = 0; r < R; ++r) kp[r] = b->rep[r]->kp;
@@ -73,11 +99,18 @@ md_status upload(md_batch* b)
         if (off > 0x7fffffff) return MD_ERR_ARG;
         first[(size_t)k * (R + 1) + R] = (int32_t)off;
         sh.grid[k] = (int)off;
+        rep_base[k] = (int32_t)rep_of.size();
+        for (int r = 0; r < R; ++r) {
+            const int32_t end = first[(size_t)k * (R + 1) + r + 1];
+            for (int32_t w = first[(size_t)k * (R + 1) + r]; w < end; ++w)
+                rep_of.push_back((uint16_t)r);
+        }
     }
     const KParams& p0 = kp[0];
     sh.block = p0.block;
     sh.force_block = p0.force_block;
     sh.force_lanes = p0.force_lanes;
+    sh.nl_method = p0.nl_method;
     sh.precision = p0.precision;
     sh.reorder = p0.reorder;
     sh.mode = p0.mode;
@@ -96,16 +129,23 @@ md_status upload(md_batch* b)
     int32_t* d_count = reinterpret_cast<int32_t*>(
         t + align_up(sizeof(KParams) * (size_t)R) +
         align_up(sizeof(int32_t) * (size_t)G_KINDS * (size_t)(R + 1)));
+    uint16_t* d_rep = reinterpret_cast<uint16_t*>(
+        reinterpret_cast<char*>(d_count) + align_up(sizeof(int32_t) * (size_t)G_KINDS * R));
+    if ((char*)(d_rep + rep_of.size()) > b->ws + b->ws_bytes) return MD_ERR_ARG;
     if (hipMemcpy(d_kp, kp.data(), sizeof(KParams) * (size_t)R, hipMemcpyHostToDevice) !=
             hipSuccess ||
         hipMemcpy(d_first, first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice) !=
             hipSuccess ||
         hipMemcpy(d_count, count.data(), sizeof(int32_t) * count.size(), hipMemcpyHostToDevice) !=
-            hipSuccess)
+            hipSuccess ||
+        hipMemcpy(d_rep, rep_of.data(), sizeof(uint16_t) * rep_of.size(),
+                  hipMemcpyHostToDevice) != hipSuccess)
         return MD_ERR_HIP;
     b->dev.kp = d_kp;
     b->dev.first = d_first;
     b->dev.count = d_count;
+    b->dev.rep_of = d_rep;
+    for (int k = 0; k < G_KINDS; ++k) b->dev.rep_base[k] = rep_base[k];
     b->dev.R = R;
     b->sh = sh;
     drop_graph(b);
@@ -163,12 +203,16 @@ extern "C" md_status md_batch_init(const md_params* params, int32_t n_replicas, 
             md_batch_destroy(b);
             return st;
         }
+        // the gated per-atom and per-cell kernels and the integration share
+        // the machine among the replicas
+        c->kp.gate_grid = gate_share(n_replicas);
+        c->kp.int_grid = integrate_share(n_replicas);
         b->rep.push_back(c);
         b->rep_off.push_back(off);
         off += align_up(c->ws_bytes);
     }
     b->tab_off = off;
-    b->ws_bytes = off + table_bytes(n_replicas);
+    b->ws_bytes = off + table_bytes(b);
     *out = b;
     return MD_OK;
 }
@@ -261,9 +305,11 @@ extern "C" md_status md_batch_run(md_batch* b, int32_t n_steps, int32_t record_e
 extern "C" md_status md_batch_set_tuning(md_batch* b, const md_tuning* t)
 {
     if (!b || !t) return MD_ERR_ARG;
+    const int R = (int)b->rep.size();
     for (md_ctx* c : b->rep) {
         md_status st = md_set_tuning(c, t);
         if (st != MD_OK) return st;
+        if (t->integrate_grid == 0) c->kp.int_grid = integrate_share(R);
     }
     b->prepared = false;
     set_flags(b, false);

@@ -8,7 +8,9 @@
 //                largest occupancy; clears the counts for the next build
 //   k_scatter    slots grouped by cell (in the order the atomics gave)
 //   k_cellsort   inside each cell, ascending permanent id (the paper leaves
-//                the order open; a fixed order makes the list reproducible)
+//                the order open; a fixed order makes the list reproducible):
+//                each atom's place is the number of its cell's members with
+//                a smaller id
 //   k_permute /  with reorder on: atom data permuted into cell order
 //   k_copyback
 //
@@ -29,12 +31,11 @@ template <class B>
 __global__ void k_clear(B b)
 {
     Wg wg;
-    const KParams* pp = b.slot(G_CELLWAVES, wg);
-    if (!pp) return;
-    const KParams& p = *pp;
-    int i = wg.id * blockDim.x + threadIdx.x;
-    if (i < p.ncell) p.cell_count[i] = 0;
-    if (i == 0) {
+    KParams p;
+    if (!b.fetch(G_ATOMS, wg, p)) return;
+    const int i0 = wg.id * blockDim.x + threadIdx.x;
+    for (int i = i0; i < p.ncell; i += wg.n * blockDim.x) p.cell_count[i] = 0;
+    if (i0 == 0) {
         DevState* d = p.dev;
         d->step = 0;
         d->n_rebuilds = 0;
@@ -53,38 +54,40 @@ template <class B>
 __global__ void k_bin(B b, int force)
 {
     Wg wg;
-    const KParams* pp = b.slot(G_ATOMS, wg);
-    if (!pp) return;
-    const KParams& p = *pp;
+    KParams p;
+    if (!b.fetch(G_ATOMS, wg, p)) return;
     if (!rebuild_on(p, force)) return;
-    const int i = xcd_tile(wg.id, wg.n) * blockDim.x + threadIdx.x;
-    const bool act = i < p.n;
-    int c = -1;
-    if (act) {
-        // positions are folded into [0, L) here, at each cell build, and drift
-        // freely in between (by less than skin/2), so the wrap bits of the
-        // list stay valid until the next build
-        const double x = wrap(p.x[i], p.L), y = wrap(p.y[i], p.L), z = wrap(p.z[i], p.L);
-        p.x[i] = x;
-        p.y[i] = y;
-        p.z[i] = z;
-        c = cell_of_pos(x, y, z, p);
-        p.cell_of[i] = c;
-    }
-    // Atoms stored in cell order put a wave's 64 atoms into a few cells: the
-    // lanes of one cell take one atomic together and rank themselves by
-    // their position in the wave (the in-cell order is fixed later anyway).
     const int lane = threadIdx.x & (kWave - 1);
-    uint64_t todo = __ballot(act);
-    while (todo) {
-        const int leader = __ffsll((unsigned long long)todo) - 1;
-        const int cl = __shfl(c, leader, kWave);
-        const uint64_t same = __ballot(act && c == cl);
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&p.cell_count[cl], (int)__popcll(same));
-        base = __shfl(base, leader, kWave);
-        if (act && c == cl) p.slot[i] = base + (int)__popcll(same & ((1ull << lane) - 1ull));
-        todo &= ~same;
+    for (int i0 = wg.id * blockDim.x; i0 < p.n; i0 += wg.n * blockDim.x) {
+        const int i = i0 + threadIdx.x;
+        const bool act = i < p.n;
+        int c = -1;
+        if (act) {
+            // positions are folded into [0, L) here, at each cell build, and
+            // drift freely in between (by less than skin/2), so the wrap bits
+            // of the list stay valid until the next build
+            const double x = wrap(p.x[i], p.L), y = wrap(p.y[i], p.L), z = wrap(p.z[i], p.L);
+            p.x[i] = x;
+            p.y[i] = y;
+            p.z[i] = z;
+            c = cell_of_pos(x, y, z, p);
+            p.cell_of[i] = c;
+        }
+        // Atoms stored in cell order put a wave's 64 atoms into a few cells:
+        // the lanes of one cell take one atomic together and rank themselves
+        // by their position in the wave (the in-cell order is fixed later).
+        uint64_t todo = __ballot(act);
+        while (todo) {
+            const int leader = __ffsll((unsigned long long)todo) - 1;
+            const int cl = __shfl(c, leader, kWave);
+            const uint64_t same = __ballot(act && c == cl);
+            int base = 0;
+            if (lane == leader) base = atomicAdd(&p.cell_count[cl], (int)__popcll(same));
+            base = __shfl(base, leader, kWave);
+            if (act && c == cl)
+                p.slot[i] = base + (int)__popcll(same & ((1ull << lane) - 1ull));
+            todo &= ~same;
+        }
     }
 }
 
@@ -124,9 +127,8 @@ template <class B>
 __global__ __launch_bounds__(kScanThreads) void k_scan_partial(B b, int force)
 {
     Wg wg;
-    const KParams* pp = b.slot(G_SCAN, wg);
-    if (!pp) return;
-    const KParams& p = *pp;
+    KParams p;
+    if (!b.fetch(G_SCAN, wg, p)) return;
     if (!rebuild_on(p, force)) return;
     const int base = wg.id * kScanTile + threadIdx.x * kScanPer;
     int s = 0, m = 0;
@@ -162,9 +164,8 @@ template <class B>
 __global__ __launch_bounds__(kScanThreads) void k_scan_top(B b, int force)
 {
     Wg wg;
-    const KParams* pp = b.slot(G_ONE, wg);
-    if (!pp) return;
-    const KParams& p = *pp;
+    KParams p;
+    if (!b.fetch(G_ONE, wg, p)) return;
     if (!rebuild_on(p, force)) return;
     const int ntile = grid_of(p, G_SCAN);
     __shared__ int carry;
@@ -201,9 +202,8 @@ template <class B>
 __global__ __launch_bounds__(kScanThreads) void k_scan_final(B b, int force)
 {
     Wg wg;
-    const KParams* pp = b.slot(G_SCAN, wg);
-    if (!pp) return;
-    const KParams& p = *pp;
+    KParams p;
+    if (!b.fetch(G_SCAN, wg, p)) return;
     if (!rebuild_on(p, force)) return;
     const int base = wg.id * kScanTile + threadIdx.x * kScanPer;
     int v[kScanPer], s = 0;
@@ -230,42 +230,31 @@ template <class B>
 __global__ void k_scatter(B b, int force)
 {
     Wg wg;
-    const KParams* pp = b.slot(G_ATOMS, wg);
-    if (!pp) return;
-    const KParams& p = *pp;
+    KParams p;
+    if (!b.fetch(G_ATOMS, wg, p)) return;
     if (!rebuild_on(p, force)) return;
-    int i = xcd_tile(wg.id, wg.n) * blockDim.x + threadIdx.x;
-    if (i >= p.n) return;
-    p.tmp[p.cell_start[p.cell_of[i]] + p.slot[i]] = i;
+    for (int i = wg.id * blockDim.x + threadIdx.x; i < p.n; i += wg.n * blockDim.x)
+        p.tmp[p.cell_start[p.cell_of[i]] + p.slot[i]] = i;
 }
 
-// Canonical order inside each cell: ascending permanent id.  One wave per
-// cell; each member's position is its rank, the number of members with a
-// smaller id, counted with wave shuffles (ids are distinct).
+// Canonical order inside each cell: ascending permanent id.  One lane per
+// atom counts the members of its cell with a smaller id (ids are distinct);
+// that count is its place.
 template <class B>
 __global__ void k_cellsort(B b, int force)
 {
     Wg wg;
-    const KParams* pp = b.slot(G_CELLWAVES, wg);
-    if (!pp) return;
-    const KParams& p = *pp;
+    KParams p;
+    if (!b.fetch(G_ATOMS, wg, p)) return;
     if (!rebuild_on(p, force)) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int c = xcd_tile(wg.id, wg.n) * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (c >= p.ncell) return;
-    const int a = p.cell_start[c], cnt = p.cell_start[c + 1] - a;
-    for (int i0 = 0; i0 < cnt; i0 += kWave) {
-        const int ii = i0 + lane;
-        const int s = ii < cnt ? p.tmp[a + ii] : 0;
-        const int key = ii < cnt ? p.id[s] : 0x7fffffff;
+    for (int q = wg.id * blockDim.x + threadIdx.x; q < p.n; q += wg.n * blockDim.x) {
+        const int s = p.tmp[q];
+        const int c = p.cell_of[s];
+        const int a = p.cell_start[c], cnt = p.cell_start[c + 1] - a;
+        const int key = p.id[s];
         int rank = 0;
-        for (int j0 = 0; j0 < cnt; j0 += kWave) {
-            const int jj = j0 + lane;
-            const int kj = jj < cnt ? p.id[p.tmp[a + jj]] : 0x7fffffff;
-            const int lim = cnt - j0 < kWave ? cnt - j0 : kWave;
-            for (int q = 0; q < lim; ++q) rank += __shfl(kj, q, kWave) < key ? 1 : 0;
-        }
-        if (ii < cnt) p.order[a + rank] = s;
+        for (int j = 0; j < cnt; ++j) rank += p.id[p.tmp[a + j]] < key ? 1 : 0;
+        p.order[a + rank] = s;
     }
 }
 
@@ -273,54 +262,52 @@ template <typename F, class B>
 __global__ void k_permute(B b, int force)
 {
     Wg wg;
-    const KParams* pp = b.slot(G_ATOMS, wg);
-    if (!pp) return;
-    const KParams& p = *pp;
+    KParams p;
+    if (!b.fetch(G_ATOMS, wg, p)) return;
     if (!rebuild_on(p, force)) return;
-    int q = xcd_tile(wg.id, wg.n) * blockDim.x + threadIdx.x;
-    if (q >= p.n) return;
-    const int o = p.order[q];
-    p.sx[q] = p.x[o];
-    p.sy[q] = p.y[o];
-    p.sz[q] = p.z[o];
-    p.svx[q] = p.vx[o];
-    p.svy[q] = p.vy[o];
-    p.svz[q] = p.vz[o];
-    reinterpret_cast<F*>(p.sfx)[q] = static_cast<const F*>(p.fx)[o];
-    reinterpret_cast<F*>(p.sfy)[q] = static_cast<const F*>(p.fy)[o];
-    reinterpret_cast<F*>(p.sfz)[q] = static_cast<const F*>(p.fz)[o];
-    p.sid[q] = p.id[o];
-    p.scell[q] = p.cell_of[o];
+    for (int q = wg.id * blockDim.x + threadIdx.x; q < p.n; q += wg.n * blockDim.x) {
+        const int o = p.order[q];
+        p.sx[q] = p.x[o];
+        p.sy[q] = p.y[o];
+        p.sz[q] = p.z[o];
+        p.svx[q] = p.vx[o];
+        p.svy[q] = p.vy[o];
+        p.svz[q] = p.vz[o];
+        reinterpret_cast<F*>(p.sfx)[q] = static_cast<const F*>(p.fx)[o];
+        reinterpret_cast<F*>(p.sfy)[q] = static_cast<const F*>(p.fy)[o];
+        reinterpret_cast<F*>(p.sfz)[q] = static_cast<const F*>(p.fz)[o];
+        p.sid[q] = p.id[o];
+        p.scell[q] = p.cell_of[o];
+    }
 }
 
 template <typename F, class B>
 __global__ void k_copyback(B b, int force)
 {
     Wg wg;
-    const KParams* pp = b.slot(G_ATOMS, wg);
-    if (!pp) return;
-    const KParams& p = *pp;
+    KParams p;
+    if (!b.fetch(G_ATOMS, wg, p)) return;
     if (!rebuild_on(p, force)) return;
-    int q = xcd_tile(wg.id, wg.n) * blockDim.x + threadIdx.x;
-    if (q >= p.n) return;
-    p.x[q] = p.sx[q];
-    p.y[q] = p.sy[q];
-    p.z[q] = p.sz[q];
-    p.vx[q] = p.svx[q];
-    p.vy[q] = p.svy[q];
-    p.vz[q] = p.svz[q];
-    static_cast<F*>(p.fx)[q] = reinterpret_cast<const F*>(p.sfx)[q];
-    static_cast<F*>(p.fy)[q] = reinterpret_cast<const F*>(p.sfy)[q];
-    static_cast<F*>(p.fz)[q] = reinterpret_cast<const F*>(p.sfz)[q];
-    p.id[q] = p.sid[q];
-    p.cell_of[q] = p.scell[q];
-    p.order[q] = q;
+    for (int q = wg.id * blockDim.x + threadIdx.x; q < p.n; q += wg.n * blockDim.x) {
+        p.x[q] = p.sx[q];
+        p.y[q] = p.sy[q];
+        p.z[q] = p.sz[q];
+        p.vx[q] = p.svx[q];
+        p.vy[q] = p.svy[q];
+        p.vz[q] = p.svz[q];
+        static_cast<F*>(p.fx)[q] = reinterpret_cast<const F*>(p.sfx)[q];
+        static_cast<F*>(p.fy)[q] = reinterpret_cast<const F*>(p.sfy)[q];
+        static_cast<F*>(p.fz)[q] = reinterpret_cast<const F*>(p.sfz)[q];
+        p.id[q] = p.sid[q];
+        p.cell_of[q] = p.scell[q];
+        p.order[q] = q;
+    }
 }
 
 template <class B>
 static void clear_seq(const B& b, const LaunchShape& sh, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_clear<B>, dim3(sh.grid[G_CELLWAVES]), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_clear<B>, dim3(sh.grid[G_ATOMS]), dim3(sh.block), 0, s, b);
 }
 
 template <class B>
@@ -334,7 +321,7 @@ static void cells_seq(const B& b, const LaunchShape& sh, int force, hipStream_t 
     hipLaunchKernelGGL(k_scan_final<B>, dim3(sh.grid[G_SCAN]), dim3(kScanThreads), 0, s, b,
                        force);
     hipLaunchKernelGGL(k_scatter<B>, atoms, blk, 0, s, b, force);
-    hipLaunchKernelGGL(k_cellsort<B>, dim3(sh.grid[G_CELLWAVES]), dim3(256), 0, s, b, force);
+    hipLaunchKernelGGL(k_cellsort<B>, atoms, blk, 0, s, b, force);
     if (sh.reorder) {
         if (sh.precision == MD_FP64) {
             hipLaunchKernelGGL((k_permute<double, B>), atoms, blk, 0, s, b, force);

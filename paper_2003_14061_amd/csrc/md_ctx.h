@@ -31,7 +31,8 @@ struct md_ctx {
     size_t ws_bytes;
     hipStream_t stream = nullptr;
     bool bound = false, cells_ok = false, nl_ok = false, forces_ok = false;
-    int nl_block_req = 0;  // requested list-build workgroup size (0: one wave per tile cell)
+    int nl_block_req = 0;   // requested list-build workgroup size (0: automatic)
+    int nl_method_req = 0;  // requested list-build method (MD_NL_AUTO: by density)
     bool timing = false;
     std::vector<hipEvent_t> ev_free, ev_pending;  // pending holds start/stop pairs
     double timed_ms = 0.0;

@@ -82,9 +82,8 @@ template <typename F, typename Acc, int LANES, class B>
 __global__ void k_forces_tiles(B b)
 {
     Wg wg;
-    const KParams* pp = b.slot(G_TILES, wg);
-    if (!pp) return;
-    const KParams& p = *pp;
+    KParams p;
+    if (!b.fetch(G_TILES, wg, p)) return;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ double red[(1024 / kWave) * 2];
     const Tile g = tile_of(p, xcd_tile(wg.id, wg.n));
@@ -176,9 +175,8 @@ template <typename F, typename Acc, class B>
 __global__ void k_forces_cells(B b)
 {
     Wg wg;
-    const KParams* pp = b.slot(G_TILES, wg);
-    if (!pp) return;
-    const KParams& p = *pp;
+    KParams p;
+    if (!b.fetch(G_TILES, wg, p)) return;
     __shared__ double red[(1024 / kWave) * 2];
     const int i = xcd_tile(wg.id, wg.n) * blockDim.x + threadIdx.x;
     Acc a;
@@ -252,6 +250,7 @@ LaunchShape shape_of(const KParams& p)
     sh.force_block = p.force_block;
     sh.force_lanes = p.force_lanes;
     sh.nl_block = p.nl_block;
+    sh.nl_method = p.nl_method;
     sh.nl_lds = p.mode == MD_NEIGHBOR_LIST ? nl_lds_bytes(p) : 0;
     sh.force_lds = force_lds_bytes(p);
     sh.precision = p.precision;

@@ -19,8 +19,6 @@
 
 namespace md {
 
-constexpr int kIntThreads = 256;
-
 // Sum partials [nb][stride] (component k) over workgroups in a fixed order.
 // Called only by the last workgroup, after the acquire fence of last_block,
 // so plain loads see every other workgroup's partial.
@@ -89,9 +87,8 @@ template <typename F, class B>
 __global__ __launch_bounds__(kIntThreads) void k_integrate(B b, int phase, int record_every)
 {
     Wg wg;
-    const KParams* pp = b.slot(G_INTEGRATE, wg);
-    if (!pp) return;
-    const KParams& p = *pp;
+    KParams p;
+    if (!b.fetch(G_INTEGRATE, wg, p)) return;
     __shared__ double red[(kIntThreads / kWave) * 5];
     const F* fx = static_cast<const F*>(p.fx);
     const F* fy = static_cast<const F*>(p.fy);
@@ -99,9 +96,22 @@ __global__ __launch_bounds__(kIntThreads) void k_integrate(B b, int phase, int r
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // v^2, Px, Py, Pz, (unused)
     double dmax2 = 0.0;
     const int stride = wg.n * blockDim.x;
+    const bool drift_now = phase <= 1, track = phase <= 1 && p.mode == MD_NEIGHBOR_LIST;
     for (int i = wg.id * blockDim.x + threadIdx.x; i < p.n; i += stride) {
+        // every input first, so that one round of loads serves the iteration
         const double gx = (double)fx[i], gy = (double)fy[i], gz = (double)fz[i];
         double vx = p.vx[i], vy = p.vy[i], vz = p.vz[i];
+        double x = 0.0, y = 0.0, z = 0.0, rx = 0.0, ry = 0.0, rz = 0.0;
+        if (drift_now) {
+            x = p.x[i];
+            y = p.y[i];
+            z = p.z[i];
+        }
+        if (track) {
+            rx = p.xr[i];
+            ry = p.yr[i];
+            rz = p.zr[i];
+        }
         if (phase >= 1) {  // second half kick of the finished step
             vx = kick(vx, p.hdt, gx);
             vy = kick(vy, p.hdt, gy);
@@ -111,20 +121,19 @@ __global__ __launch_bounds__(kIntThreads) void k_integrate(B b, int phase, int r
             acc[2] += vy;
             acc[3] += vz;
         }
-        if (phase <= 1) {  // first half kick and drift of the next step
+        if (drift_now) {  // first half kick and drift of the next step
             vx = kick(vx, p.hdt, gx);
             vy = kick(vy, p.hdt, gy);
             vz = kick(vz, p.hdt, gz);
-            const double x = drift(p.x[i], p.dt, vx);
-            const double y = drift(p.y[i], p.dt, vy);
-            const double z = drift(p.z[i], p.dt, vz);
+            x = drift(x, p.dt, vx);
+            y = drift(y, p.dt, vy);
+            z = drift(z, p.dt, vz);
             p.x[i] = x;
             p.y[i] = y;
             p.z[i] = z;
-            if (p.mode == MD_NEIGHBOR_LIST) {
-                const double d2 = dist2(minimg(x - p.xr[i], p.L, p.invL),
-                                        minimg(y - p.yr[i], p.L, p.invL),
-                                        minimg(z - p.zr[i], p.L, p.invL));
+            if (track) {
+                const double d2 = dist2(minimg(x - rx, p.L, p.invL), minimg(y - ry, p.L, p.invL),
+                                        minimg(z - rz, p.L, p.invL));
                 dmax2 = d2 > dmax2 ? d2 : dmax2;
             }
         }

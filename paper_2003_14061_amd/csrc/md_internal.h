@@ -15,7 +15,9 @@ namespace md {
 constexpr int kWave = 64;
 constexpr int kHistCap = 4096;     // history records kept on the device
 constexpr int kIntegrateGridMax = 4096;  // largest grid of the grid-stride per-atom kernels
-constexpr int kIntegrateGridDefault = 512;
+constexpr int kIntegrateGridDefault = 256;
+constexpr int kIntThreads = 1024;        // workgroup of the integration and observables
+constexpr int kGateGridDefault = 2048;   // per system; a batch divides it among its replicas
 
 // Device-resident control block (first bytes of the workspace).
 struct DevState {
@@ -62,6 +64,8 @@ struct KParams {
     int32_t force_block;    // threads per workgroup of the tiled force pass
     int32_t nl_block;       // threads per workgroup of the list build
     int32_t int_grid;       // workgroups of the grid-stride per-atom kernels
+    int32_t gate_grid;      // most workgroups of a rebuild-gated per-atom or per-cell kernel
+    int32_t nl_method;      // MD_NL_LANES or MD_NL_CELL_WAVES
     // tiling of the neighbor-list mode: rows of nc cells cut into tiles_per_row tiles
     int32_t tiles_per_row, kx_max, n_tiles;
     int32_t scap;           // staged atoms a workgroup's LDS holds
@@ -104,7 +108,7 @@ struct Wg {
 
 // The grid rules of the launches; a batched launch concatenates, per rule,
 // the workgroups of every replica.
-enum GridKind { G_ATOMS, G_SCAN, G_ONE, G_CELLWAVES, G_INTEGRATE, G_TILES, G_KINDS };
+enum GridKind { G_ATOMS, G_SCAN, G_ONE, G_INTEGRATE, G_TILES, G_KINDS };
 
 constexpr int kScanThreads = 256;
 constexpr int kScanPer = 4;
@@ -114,12 +118,14 @@ __host__ __device__ inline int grid_of(const KParams& p, GridKind k)
 {
     auto up = [](int64_t n, int64_t b) { return (int)((n + b - 1) / b); };
     switch (k) {
-        case G_ATOMS: return up(p.n, p.block);
+        case G_ATOMS: {
+            const int g = up(p.n, p.block);
+            return g < p.gate_grid ? (g > 0 ? g : 1) : p.gate_grid;
+        }
         case G_SCAN: return up(p.ncell, kScanTile);
         case G_ONE: return 1;
-        case G_CELLWAVES: return up((int64_t)p.ncell * kWave, 256);
         case G_INTEGRATE: {
-            const int g = up(p.n, 256);
+            const int g = up(p.n, kIntThreads);
             return g < p.int_grid ? (g > 0 ? g : 1) : p.int_grid;
         }
         case G_TILES: return p.mode == MD_NEIGHBOR_LIST ? p.n_tiles : up(p.n, p.block);
@@ -127,48 +133,80 @@ __host__ __device__ inline int grid_of(const KParams& p, GridKind k)
     }
 }
 
+// A pointer the caller knows to address global memory (so the compiler
+// emits global, not flat, accesses through it).
+template <class T>
+__device__ __forceinline__ T* as_global(T* q)
+{
+    return (T*)((__attribute__((address_space(1))) T*)q);
+}
+
+// A register copy of a parameter block read from device memory, with every
+// pointer marked global: stores through those pointers cannot alias the
+// copy, so nothing is reloaded inside loops.
+__device__ __forceinline__ KParams global_view(const KParams& q)
+{
+    KParams p = q;
+    p.x = as_global(q.x); p.y = as_global(q.y); p.z = as_global(q.z);
+    p.vx = as_global(q.vx); p.vy = as_global(q.vy); p.vz = as_global(q.vz);
+    p.fx = as_global(q.fx); p.fy = as_global(q.fy); p.fz = as_global(q.fz);
+    p.id = as_global(q.id);
+    p.dev = as_global(q.dev);
+    p.cell_count = as_global(q.cell_count); p.cell_start = as_global(q.cell_start);
+    p.cell_of = as_global(q.cell_of); p.slot = as_global(q.slot);
+    p.order = as_global(q.order); p.tmp = as_global(q.tmp);
+    p.nl64 = as_global(q.nl64); p.nl_count = as_global(q.nl_count);
+    p.xr = as_global(q.xr); p.yr = as_global(q.yr); p.zr = as_global(q.zr);
+    p.sx = as_global(q.sx); p.sy = as_global(q.sy); p.sz = as_global(q.sz);
+    p.svx = as_global(q.svx); p.svy = as_global(q.svy); p.svz = as_global(q.svz);
+    p.sfx = as_global(q.sfx); p.sfy = as_global(q.sfy); p.sfz = as_global(q.sfz);
+    p.sid = as_global(q.sid); p.scell = as_global(q.scell);
+    p.fpart = as_global(q.fpart); p.ipart = as_global(q.ipart);
+    p.scanpart = as_global(q.scanpart); p.hist = as_global(q.hist);
+    return p;
+}
+
 // A single system: the parameters are the kernel argument.
 struct Single {
     KParams p;
-    __device__ __forceinline__ const KParams* slot(GridKind, Wg& w) const
+    __device__ __forceinline__ bool fetch(GridKind, Wg& w, KParams& out) const
     {
         w.id = (int)blockIdx.x;
         w.n = (int)gridDim.x;
-        return &p;
+        out = p;
+        return true;
     }
 };
 
 // Independent replicas in one launch.  For grid rule k, replica r owns
 // workgroups [first[k][r], first[k][r] + count[k][r]); first is rounded up
 // to a multiple of 8 so that the XCD-aware tile order (workgroup b runs on
-// XCD b mod 8) holds inside every replica.  Workgroups in the gaps return.
+// XCD b mod 8) holds inside every replica.  rep_of maps every workgroup of a
+// launch of rule k (from rep_base[k]) to its replica in one load; workgroups
+// in the gaps map to the replica before them and return.
 struct Batch {
-    const KParams* __restrict__ kp;     // [R] per-replica parameters (device)
-    const int32_t* __restrict__ first;  // [G_KINDS][R + 1]
-    const int32_t* __restrict__ count;  // [G_KINDS][R]
+    const KParams* __restrict__ kp;      // [R] per-replica parameters (device)
+    const int32_t* __restrict__ first;   // [G_KINDS][R + 1]
+    const int32_t* __restrict__ count;   // [G_KINDS][R]
+    const uint16_t* __restrict__ rep_of; // workgroup -> replica, all rules back to back
+    int32_t rep_base[G_KINDS];
     int32_t R;
-    __device__ __forceinline__ const KParams* slot(GridKind k, Wg& w) const
+    __device__ __forceinline__ bool fetch(GridKind k, Wg& w, KParams& out) const
     {
-        const int32_t* f = first + (int)k * (R + 1);
         const int blk = (int)blockIdx.x;
-        int lo = 0, hi = R - 1;  // last replica whose first workgroup is <= blk
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (f[mid] <= blk)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        w.id = blk - f[lo];
-        w.n = count[(int)k * R + lo];
-        return w.id < w.n ? kp + lo : nullptr;
+        const int r = rep_of[rep_base[(int)k] + blk];
+        w.id = blk - first[(int)k * (R + 1) + r];
+        w.n = count[(int)k * R + r];
+        if (w.id >= w.n) return false;
+        out = global_view(kp[r]);
+        return true;
     }
 };
 
 // Uniform launch shape: workgroups per grid rule, block sizes, dynamic LDS.
 struct LaunchShape {
     int grid[G_KINDS];
-    int block, force_block, force_lanes, nl_block;
+    int block, force_block, force_lanes, nl_block, nl_method;
     size_t nl_lds, force_lds;
     int precision, reorder, mode;
 };

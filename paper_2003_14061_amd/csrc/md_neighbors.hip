@@ -1,16 +1,19 @@
 // md_neighbors.hip -- step N5 of section 2.3: the neighbor matrix.
 //
 // One workgroup per tile (md_tiles.h) stages the tile's 27-cell
-// neighborhoods in LDS.  Each wave then takes one home cell at a time and
-// spreads that cell's candidates -- the three cells dx = -1, 0, +1 of each
-// of the 9 staged rows (dz, dy each -1, 0, +1, dz slowest), every cell in
-// ascending permanent id -- across its 64 lanes, 64 candidates per round.
-// For each home atom of the cell in turn, every lane tests its candidate;
-// a wave ballot and a prefix count give each hit its position in the home
-// atom's list, so the list comes out in the canonical candidate order.  An
-// entry is kept when the minimum-image squared separation is below
-// (r_cut + skin)^2 (dx*dx, then two fused multiply-adds) and it is not the
-// atom itself.
+// neighborhoods in LDS.  A home atom's candidates are the three cells
+// dx = -1, 0, +1 of each of the 9 staged rows (dz, dy each -1, 0, +1, dz
+// slowest), every cell in ascending permanent id; its list keeps them in
+// that canonical order.  An entry is kept when the minimum-image squared
+// separation is below (r_cut + skin)^2 (dx*dx, then two fused
+// multiply-adds) and it is not the atom itself.  Two ways to walk them:
+//
+//   lanes (default)  one lane per home atom walks its 27 cells; entries are
+//                    packed four to a chunk in a register and stored a
+//                    chunk at a time
+//   cell waves       one wave per home cell spreads the cell's candidates
+//                    over its 64 lanes, 64 per round; for each home atom a
+//                    ballot and a prefix count place the hits
 //
 // Storage follows the paper's W (section 2.3): row m holds the m-th
 // neighbor of every atom, so a wave of the force pass reads consecutive
@@ -144,13 +147,111 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
     }
 }
 
-template <class B>
+// Home cell (column 1..kx of the middle row) holding staged entry e.
+__device__ __forceinline__ int home_column(const Stage& s, int kx, int e)
+{
+    int lo = 1, hi = kx;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s.off[4 * s.stride + mid] <= e)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// The list of home atom h (staged entry e_self, home column q), by one lane.
+// Returns the number of entries found (beyond the capacity: overflow).
+template <int kImage, bool kFits>
+__device__ __forceinline__ int nl_home_atom(const KParams& p, const Stage& s, int h, int q)
+{
+    const int e_self = home_first_lds(s) + h;
+    const int slot_i = atom_at(p, home_first_slot(s) + h);
+    double xi, yi, zi;
+    if (kFits) {
+        xi = s.xs[e_self];
+        yi = s.ys[e_self];
+        zi = s.zs[e_self];
+    } else {
+        xi = p.x[slot_i];
+        yi = p.y[slot_i];
+        zi = p.z[slot_i];
+    }
+    const uint32_t cap = (uint32_t)p.cap;  // a multiple of 4
+    uint64_t* col = p.nl64 + slot_i;
+    uint64_t chunk = 0;
+    uint32_t m = 0;
+    for (int sg = 0; sg < 9; ++sg) {
+#pragma unroll
+        for (int w = 0; w < 3; ++w) {
+            const int t = sg * s.stride + q - 1 + w;
+            const int eb = s.off[t], ee = s.off[t + 1];
+            const int fl = s.flag[t];
+            const int tslot = kFits ? 0 : s.slot[t];
+            const uint64_t tag = (uint64_t)fl << kEntryBits;
+            for (int e = eb; e < ee; ++e) {
+                double xj, yj, zj;
+                if (kFits) {
+                    xj = s.xs[e];
+                    yj = s.ys[e];
+                    zj = s.zs[e];
+                } else {
+                    const int j = atom_at(p, tslot + (e - eb));
+                    xj = p.x[j];
+                    yj = p.y[j];
+                    zj = p.z[j];
+                }
+                double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+                image<kImage>(p, fl, dx, dy, dz);
+                if (dist2(dx, dy, dz) < p.rl2 && e != e_self) {
+                    if (m < cap) {
+                        chunk |= ((uint64_t)e | tag) << (16 * (m % kChunk));
+                        if (m % kChunk == kChunk - 1) {
+                            col[(int64_t)(m / kChunk) * p.npad] = chunk;
+                            chunk = 0;
+                        }
+                    }
+                    ++m;
+                }
+            }
+        }
+    }
+    const uint32_t stored = m < cap ? m : cap;
+    if (stored % kChunk != 0) {  // pad the last chunk with the sentinel
+        for (uint32_t mm = stored % kChunk; mm < kChunk; ++mm)
+            chunk |= (uint64_t)s.total << (16 * mm);
+        col[(int64_t)(stored / kChunk) * p.npad] = chunk;
+    }
+    p.nl_count[slot_i] = (int)stored;
+    p.xr[slot_i] = xi;
+    p.yr[slot_i] = yi;
+    p.zr[slot_i] = zi;
+    return (int)m;
+}
+
+template <int kImage, bool kFits>
+__device__ __forceinline__ void nl_lanes(const KParams& p, const Stage& s, int kx)
+{
+    const int nh = home_count(s), h0 = home_first_lds(s);
+    int mmax = 0;
+    for (int h = threadIdx.x; h < nh; h += blockDim.x) {
+        const int m = nl_home_atom<kImage, kFits>(p, s, h, home_column(s, kx, h0 + h));
+        mmax = m > mmax ? m : mmax;
+    }
+    mmax = wave_max(mmax);
+    if ((threadIdx.x & (kWave - 1)) == 0 && mmax > 0) {
+        atomicMax(&p.dev->max_nl, mmax);
+        if (mmax > p.cap) atomicOr(&p.dev->flags, (int)MD_FLAG_NL_OVERFLOW);
+    }
+}
+
+template <class B, int kMethod>
 __global__ void k_nl_tiles(B b, int force)
 {
     Wg wg;
-    const KParams* pp = b.slot(G_TILES, wg);
-    if (!pp) return;
-    const KParams& p = *pp;
+    KParams p;
+    if (!b.fetch(G_TILES, wg, p)) return;
     if (!force && !p.dev->rebuild) return;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int t = xcd_tile(wg.id, wg.n);
@@ -168,8 +269,23 @@ __global__ void k_nl_tiles(B b, int force)
     }
     stage_positions(p, s);
     __syncthreads();
-    const int wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const int mode = image_mode(p, tile_interior(p, g));
+    if (kMethod == MD_NL_LANES) {
+        if (!s.fits) {
+            if (mode == 2)
+                nl_lanes<2, false>(p, s, g.kx);
+            else
+                nl_lanes<1, false>(p, s, g.kx);
+        } else if (mode == 0) {
+            nl_lanes<0, true>(p, s, g.kx);
+        } else if (mode == 1) {
+            nl_lanes<1, true>(p, s, g.kx);
+        } else {
+            nl_lanes<2, true>(p, s, g.kx);
+        }
+        return;
+    }
+    const int wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
     for (int q = 1 + wid; q <= g.kx; q += nw) {
         if (mode == 0)
             nl_home_cell<0>(p, s, q);
@@ -203,16 +319,24 @@ __global__ void k_nl_export(KParams p, int32_t* out)
     }
 }
 
+template <class B>
+static void neighbors_seq(const B& b, const LaunchShape& sh, int force, hipStream_t s)
+{
+    const dim3 g(sh.grid[G_TILES]), t(sh.nl_block);
+    if (sh.nl_method == MD_NL_CELL_WAVES)
+        hipLaunchKernelGGL((k_nl_tiles<B, MD_NL_CELL_WAVES>), g, t, sh.nl_lds, s, b, force);
+    else
+        hipLaunchKernelGGL((k_nl_tiles<B, MD_NL_LANES>), g, t, sh.nl_lds, s, b, force);
+}
+
 void launch_neighbors(const KParams& p, int force, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_nl_tiles<Single>, dim3(p.n_tiles), dim3(p.nl_block), nl_lds_bytes(p), s,
-                       Single{p}, force);
+    neighbors_seq(Single{p}, shape_of(p), force, s);
 }
 
 void launch_neighbors(const Batch& b, const LaunchShape& sh, int force, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_nl_tiles<Batch>, dim3(sh.grid[G_TILES]), dim3(sh.nl_block), sh.nl_lds, s,
-                       b, force);
+    neighbors_seq(b, sh, force, s);
 }
 
 void launch_nl_export(const KParams& p, int32_t* out, hipStream_t s)

@@ -23,6 +23,7 @@ MD_OK = 0
 MD_LJ_SHIFTED, MD_LJ_TRUNC = 0, 1
 MD_FP64, MD_FP32_MIXED = 0, 1
 MD_CELLS_ONLY, MD_NEIGHBOR_LIST = 0, 1
+MD_NL_AUTO, MD_NL_LANES, MD_NL_CELL_WAVES = 0, 1, 2
 MD_ARR_CELL_OF, MD_ARR_CELL_START, MD_ARR_CELL_ATOMS, MD_ARR_NL, MD_ARR_NL_COUNT, MD_ARR_XREF = range(6)
 
 EXPORTS = ("md_init", "md_workspace_bytes", "md_geometry", "md_layout", "md_bind",
@@ -63,7 +64,7 @@ class Grid(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("force_lanes", C.c_int32), ("force_block", C.c_int32),
                 ("nl_block", C.c_int32), ("tile_cells", C.c_int32), ("stage_cap", C.c_int32),
-                ("integrate_grid", C.c_int32)]
+                ("integrate_grid", C.c_int32), ("nl_method", C.c_int32)]
 
 
 class TrajParams(C.Structure):
@@ -240,9 +241,9 @@ def md_traj_backward(ctx, tp: TrajParams, ws_ptr: int, gobs_ptr: int, gx_ptr: in
 
 
 def md_set_tuning(ctx, force_lanes=4, force_block=512, nl_block=0, tile_cells=0, stage_cap=0,
-                  integrate_grid=0):
+                  integrate_grid=0, nl_method=MD_NL_AUTO):
     t = Tuning(int(force_lanes), int(force_block), int(nl_block), int(tile_cells), int(stage_cap),
-               int(integrate_grid))
+               int(integrate_grid), int(nl_method))
     _check(lib().md_set_tuning(ctx, C.byref(t)), "md_set_tuning")
 
 
@@ -411,7 +412,8 @@ class Simulation:
         start automatic, 0)."""
         if self._tuning is None:
             self._tuning = md_get_tuning(self.ctx)
-            self._tuning.update(nl_block=0, tile_cells=0, stage_cap=0, integrate_grid=0)
+            self._tuning.update(nl_block=0, tile_cells=0, stage_cap=0, integrate_grid=0,
+                                nl_method=MD_NL_AUTO)
         req = dict(self._tuning)
         req.update(kw)
         md_set_tuning(self.ctx, **req)
@@ -501,7 +503,8 @@ def md_batch_replica(b, r):
 def _tuning_tuple(t: dict):
     return Tuning(int(t.get("force_lanes", 4)), int(t.get("force_block", 512)),
                   int(t.get("nl_block", 0)), int(t.get("tile_cells", 0)),
-                  int(t.get("stage_cap", 0)), int(t.get("integrate_grid", 0)))
+                  int(t.get("stage_cap", 0)), int(t.get("integrate_grid", 0)),
+                  int(t.get("nl_method", MD_NL_AUTO)))
 
 
 class Batch:
@@ -603,7 +606,8 @@ class Batch:
     def set_tuning(self, **kw):
         if self._tuning is None:
             self._tuning = self.get_tuning()
-            self._tuning.update(nl_block=0, tile_cells=0, stage_cap=0, integrate_grid=0)
+            self._tuning.update(nl_block=0, tile_cells=0, stage_cap=0, integrate_grid=0,
+                                nl_method=MD_NL_AUTO)
         req = dict(self._tuning)
         req.update(kw)
         t = _tuning_tuple(req)

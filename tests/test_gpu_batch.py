@@ -23,9 +23,15 @@ def systems(n_replicas=6, n_lo=500, n_hi=6000, jitter=0.03, seed=4):
     return out
 
 
-def single(sy, precision):
-    return md.Simulation(sy["pos"], sy["vel"], sy["L"], r_cut=sy["r_cut"], dt=sy["dt"],
-                         skin=sy["skin"], precision=precision)
+def single(sy, precision, batch=None, r=0):
+    """The same system alone; with the batch's integration grid for replica r
+    (a batch gives each replica a smaller share), so that the kinetic-energy
+    and momentum sums add in the same order."""
+    s = md.Simulation(sy["pos"], sy["vel"], sy["L"], r_cut=sy["r_cut"], dt=sy["dt"],
+                      skin=sy["skin"], precision=precision)
+    if batch is not None:
+        s.set_tuning(integrate_grid=md.md_get_tuning(batch.replicas[r])["integrate_grid"])
+    return s
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -37,7 +43,7 @@ def test_every_replica_matches_its_single_system_run_bitwise(precision, graph):
     b.run(30, record_every=5, graph=graph)
     b.run(30, record_every=5, graph=graph)  # a second launch of the same graph
     for r, sy in enumerate(sys_):
-        s = single(sy, precision)
+        s = single(sy, precision, b, r)
         s.prepare()
         s.step(30, record_every=5)
         s.step(30, record_every=5)
@@ -78,7 +84,7 @@ def test_autotuner_keeps_its_best_candidate():
     assert t["force_block"] == cands[best]["force_block"]
     b.run(10)
     for r, sy in enumerate(sys_):
-        s = single(sy, "fp32")
+        s = single(sy, "fp32", b, r)
         s.set_tuning(**cands[best])
         s.prepare()
         s.step(10)

@@ -248,7 +248,11 @@ TUNINGS = ([dict(force_lanes=l, force_block=b) for l in (1, 2, 4, 8) for b in (2
             for c, blk, fb in ((1, 64, 64), (3, 128, 512), (1000, 256, 1024), (2, 512, 128),
                                (5, 1024, 512))] +
            [dict(stage_cap=64), dict(stage_cap=64, force_lanes=4, tile_cells=2),
-            dict(force_lanes=8, force_block=64, tile_cells=1)])
+            dict(force_lanes=8, force_block=64, tile_cells=1)] +
+           [dict(nl_method=md.MD_NL_CELL_WAVES, tile_cells=c, stage_cap=cap)
+            for c, cap in ((0, 0), (2, 0), (3, 64))] +
+           [dict(nl_method=md.MD_NL_LANES, nl_block=b, tile_cells=c)
+            for b, c in ((64, 1), (1024, 0), (128, 6))])
 
 
 @pytest.mark.parametrize("name", ["lj32000_nl", "wca13500_nl", "lj5000_random", "wca108_nc3",
@@ -277,7 +281,8 @@ def test_tuning_is_validated():
     sim, s, pos, vel = setup("wca108_nc3")
     for bad in (dict(force_lanes=3), dict(force_lanes=16), dict(force_block=96),
                 dict(force_block=2048), dict(nl_block=32), dict(tile_cells=-1),
-                dict(stage_cap=-5), dict(integrate_grid=-1), dict(integrate_grid=4097)):
+                dict(stage_cap=-5), dict(integrate_grid=-1), dict(integrate_grid=4097),
+                dict(nl_method=3)):
         with pytest.raises(md.MDError):
             sim.set_tuning(**bad)
     sim.prepare()
