@@ -66,9 +66,13 @@ def lib():
         L.or_build_cells.argtypes = [_SP, C.c_int32, _D, _D, _D, _I, _I, _I]
         L.or_build_nl.restype = C.c_int32
         L.or_build_nl.argtypes = [_SP, C.c_int32, _D, _D, _D, _I, _I, _I, _I, _I]
+        L.or_build_nl_half.restype = C.c_int32
+        L.or_build_nl_half.argtypes = [_SP, C.c_int32, _D, _D, _D, _I, _I, _I, _I, _I]
         fo = [_D, _D, _D, C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_forces_nl.restype = None
         L.or_forces_nl.argtypes = [_SP, _D, _D, _D, _I, _I] + fo
+        L.or_forces_half.restype = None
+        L.or_forces_half.argtypes = [_SP, _D, _D, _D, _I, _I] + fo
         L.or_forces_cells.restype = None
         L.or_forces_cells.argtypes = [_SP, C.c_int32, _D, _D, _D, _I, _I, _I] + fo
         L.or_forces_allpairs.restype = None
@@ -181,6 +185,19 @@ def build_nl(s, nc, pos, cells):
     return cnt, nl, int(longest)
 
 
+def build_nl_half(s, nc, pos, cells):
+    """The half list (partner later in (cell, id) order).  Returns
+    (nl_count[n], nl[n, cap], longest)."""
+    x, y, z = _xyz(pos)
+    cell_of, cell_start, cell_atoms = cells
+    n = s.n
+    cnt = np.empty(n, np.int32)
+    nl = np.full((n, s.nl_cap), -1, np.int32)
+    longest = lib().or_build_nl_half(C.byref(s), nc, x, y, z, cell_of, cell_start, cell_atoms,
+                                     cnt, nl)
+    return cnt, nl, int(longest)
+
+
 def _fout(n):
     return (np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n))
 
@@ -198,6 +215,14 @@ def forces_nl(s, pos, nl_count, nl):
     x, y, z = _xyz(pos)
     o = _fout(s.n)
     lib().or_forces_nl(C.byref(s), x, y, z, _c(nl_count, np.int32), _c(nl, np.int32), *_ptrs(o))
+    return _pack(o)
+
+
+def forces_half(s, pos, nl_count, nl):
+    x, y, z = _xyz(pos)
+    o = _fout(s.n)
+    lib().or_forces_half(C.byref(s), x, y, z, _c(nl_count, np.int32), _c(nl, np.int32),
+                         *_ptrs(o))
     return _pack(o)
 
 

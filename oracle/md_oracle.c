@@ -191,6 +191,50 @@ int32_t or_build_nl(const or_sys* s, int32_t nc,
     return longest;
 }
 
+/* The half list: the entries of the full list whose partner comes later in
+ * the cell order (cell index, then permanent id), in the same order; every
+ * pair appears once, in the list of its earlier atom. */
+int32_t or_build_nl_half(const or_sys* s, int32_t nc,
+                         const double* x, const double* y, const double* z,
+                         const int32_t* cell_of, const int32_t* cell_start,
+                         const int32_t* cell_atoms,
+                         int32_t* nl_count, int32_t* nl)
+{
+    int32_t n = s->n, cap = s->nl_cap;
+    double L = s->L, invL = 1.0 / s->L;
+    double r_list = s->r_cut + s->skin;
+    double rl2 = r_list * r_list;
+    int32_t longest = 0;
+
+#pragma omp parallel for schedule(static) reduction(max : longest)
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t c = cell_of[i];
+        int32_t cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
+        int32_t m = 0;
+        for (int32_t dz = -1; dz <= 1; ++dz)
+            for (int32_t dy = -1; dy <= 1; ++dy)
+                for (int32_t dx = -1; dx <= 1; ++dx) {
+                    int32_t c2 = (wrap_cell(cz + dz, nc) * nc + wrap_cell(cy + dy, nc)) * nc
+                                 + wrap_cell(cx + dx, nc);
+                    for (int32_t k = cell_start[c2]; k < cell_start[c2 + 1]; ++k) {
+                        int32_t j = cell_atoms[k];
+                        if (j == i) continue;
+                        if (cell_of[j] < c || (cell_of[j] == c && j < i)) continue;
+                        double ddx = or_minimg(x[i] - x[j], L, invL);
+                        double ddy = or_minimg(y[i] - y[j], L, invL);
+                        double ddz = or_minimg(z[i] - z[j], L, invL);
+                        if (or_dist2(ddx, ddy, ddz) < rl2) {
+                            if (m < cap) nl[(int64_t)i * cap + m] = j;
+                            ++m;
+                        }
+                    }
+                }
+        nl_count[i] = m < cap ? m : cap;
+        if (m > longest) longest = m;
+    }
+    return longest;
+}
+
 /* ------------------------------------------------------------------ */
 /* F1: forces.  Each pair (i, j) contributes to atom i only; it is met again
  * from atom j (full list, section 2.3). */
@@ -251,6 +295,56 @@ void or_forces_nl(const or_sys* s,
                       or_minimg(z[i] - z[j], L, invL), f3, &u, &w, &sm);
         }
         store_atom(i, f3, u, w, sm, fx, fy, fz, u_i, w_i, s_i);
+    }
+}
+
+/* Forces from a half list (Newton's third law): each listed pair adds F_ij
+ * to atom i and -F_ij to atom j, and half of its energy, virial and error
+ * scale to each.  Serial, in list order. */
+void or_forces_half(const or_sys* s,
+                    const double* x, const double* y, const double* z,
+                    const int32_t* nl_count, const int32_t* nl,
+                    double* fx, double* fy, double* fz,
+                    double* u_i, double* w_i, double* s_i)
+{
+    const int32_t n = s->n;
+    const double L = s->L, invL = 1.0 / s->L, rc2 = s->r_cut * s->r_cut;
+    for (int32_t i = 0; i < n; ++i) {
+        fx[i] = fy[i] = fz[i] = 0.0;
+        if (u_i) u_i[i] = 0.0;
+        if (w_i) w_i[i] = 0.0;
+        if (s_i) s_i[i] = 0.0;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t m = 0; m < nl_count[i]; ++m) {
+            const int32_t j = nl[(int64_t)i * s->nl_cap + m];
+            const double dx = or_minimg(x[i] - x[j], L, invL);
+            const double dy = or_minimg(y[i] - y[j], L, invL);
+            const double dz = or_minimg(z[i] - z[j], L, invL);
+            const double r2 = or_dist2(dx, dy, dz);
+            if (!(r2 < rc2)) continue;
+            double fr;
+            const double u = or_pair(s, r2, &fr);  /* shifted pair energy */
+            fx[i] += fr * dx;
+            fy[i] += fr * dy;
+            fz[i] += fr * dz;
+            fx[j] -= fr * dx;
+            fy[j] -= fr * dy;
+            fz[j] -= fr * dz;
+            if (u_i) {
+                u_i[i] += 0.5 * u;
+                u_i[j] += 0.5 * u;
+            }
+            if (w_i) {
+                w_i[i] += 0.5 * fr * r2;
+                w_i[j] += 0.5 * fr * r2;
+            }
+            if (s_i) {
+                const double sc = or_pair_scale(s, r2);
+                s_i[i] += sc;
+                s_i[j] += sc;
+            }
+        }
     }
 }
 

@@ -84,6 +84,15 @@ int32_t or_build_nl(const or_sys* s, int32_t nc,
                     const int32_t* cell_atoms,
                     int32_t* nl_count, int32_t* nl);
 
+/* The half list (for Newton's-third-law force passes): the entries of the
+ * full list whose partner comes later in the cell order (cell index, then
+ * permanent id), same order and layout as or_build_nl. */
+int32_t or_build_nl_half(const or_sys* s, int32_t nc,
+                         const double* x, const double* y, const double* z,
+                         const int32_t* cell_of, const int32_t* cell_start,
+                         const int32_t* cell_atoms,
+                         int32_t* nl_count, int32_t* nl);
+
 /* ---- F1: forces.  u_i gets half of each pair energy, w_i half of each
  *      pair virial, s_i the sum over pairs of or_pair_scale (the scale of
  *      the rounding error of the force sum, used for tolerances).  Any of
@@ -94,6 +103,13 @@ void or_forces_nl(const or_sys* s,
                   const int32_t* nl_count, const int32_t* nl,
                   double* fx, double* fy, double* fz,
                   double* u_i, double* w_i, double* s_i);
+/* Forces from a half list: each pair adds F_ij to i and -F_ij to j (and
+ * half its energy, virial and scale to each); serial, in list order. */
+void or_forces_half(const or_sys* s,
+                    const double* x, const double* y, const double* z,
+                    const int32_t* nl_count, const int32_t* nl,
+                    double* fx, double* fy, double* fz,
+                    double* u_i, double* w_i, double* s_i);
 void or_forces_cells(const or_sys* s, int32_t nc,
                      const double* x, const double* y, const double* z,
                      const int32_t* cell_of, const int32_t* cell_start,

@@ -436,3 +436,32 @@ def test_kick_and_drift_pieces():
     p2 = oracle.drift(s, p, np.array([[1.0, -1.0, 0.0], [0, 0, 0], [0, 0, 0]]))
     assert p2[0, 0] == pytest.approx(0.009, abs=1e-15)
     assert p2[0, 1] == pytest.approx(4.99, abs=1e-15)
+
+
+def test_half_list_holds_every_pair_once_in_canonical_order():
+    # against the pinned full list: the half list of i is the full list of i
+    # filtered to partners later in (cell, id) order, and every listed pair of
+    # the full list appears in exactly one half list
+    rng = np.random.default_rng(71)
+    L = inputs.box_length(864, 0.8442)
+    pos = inputs.jitter(inputs.fcc_sites(6, L), L, 0.05, rng)
+    s = oracle.make_sys(len(pos), L, r_cut=2.5, skin=0.3)
+    nc = oracle.cells_per_side(L, 2.8)
+    cells = oracle.build_cells(s, nc, pos)
+    cell_of = cells[0]
+    fc, fl, _ = oracle.build_nl(s, nc, pos, cells)
+    hc, hl, _ = oracle.build_nl_half(s, nc, pos, cells)
+    later = lambda i, j: (cell_of[j], j) > (cell_of[i], i)
+    pairs = set()
+    for i in range(s.n):
+        want = [j for j in fl[i, : fc[i]] if later(i, j)]
+        assert list(hl[i, : hc[i]]) == want
+        pairs.update((i, j) for j in want)
+    full = {(min(i, j), max(i, j)) for i in range(s.n) for j in fl[i, : fc[i]]}
+    assert {(min(p), max(p)) for p in pairs} == full and len(pairs) == len(full)
+    # the third-law force pass gives the full-list forces and energy
+    f = oracle.forces_nl(s, pos, fc, fl)
+    h = oracle.forces_half(s, pos, hc, hl)
+    assert np.abs(h["f"] - f["f"]).max() <= 1e-12 * f["s"].max()
+    assert abs(h["u"].sum() - f["u"].sum()) <= 1e-12 * np.abs(f["u"]).sum()
+    assert abs(h["w"].sum() - f["w"].sum()) <= 1e-12 * np.abs(f["w"]).sum()
