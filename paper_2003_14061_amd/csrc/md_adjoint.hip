@@ -384,17 +384,6 @@ __global__ void k_fill(double* a, size_t n, double v)
 
 // ---- launchers ----
 
-// Staged atoms per workgroup when lambda_v is staged beside the positions.
-int adj_stage_cap(const KParams& p, size_t lds_limit)
-{
-    const size_t tables = stage_bytes(0, p.kx_max) + 2048;
-    const size_t room = lds_limit > tables ? lds_limit - tables : 0;
-    int cap = (int)(room / (6 * sizeof(double)));
-    cap = cap < p.scap ? cap : p.scap;
-    cap = cap / 64 * 64;
-    return cap < 64 ? 64 : cap;
-}
-
 static int gr_stage_cap(const KParams& p)
 {
     // the static LDS of the g(r) kernels (kMaxBins 8-byte words) comes out of

@@ -64,6 +64,10 @@ static void plan_tiles(md_ctx* c, int cells)
     if (scap > scap_max) scap = scap_max;
     scap = scap / 64 * 64;
     k.scap = scap < 64 ? 64 : scap;
+    // with a second 3-vector per staged atom (adjoint, third-law forces)
+    int aux = (int)(room / (6 * sizeof(double)));
+    aux = (aux < k.scap ? aux : k.scap) / 64 * 64;
+    k.scap_aux = aux < 64 ? 64 : aux;
     c->tile_cells = cells;
     k.nblk_force = force_blocks(k);
     // list build: a lane per home atom of a mean tile (25% spare), or a
@@ -101,7 +105,8 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
         return MD_ERR_ARG;
     if ((p.potential != MD_LJ_SHIFTED && p.potential != MD_LJ_TRUNC) ||
         (p.precision != MD_FP64 && p.precision != MD_FP32_MIXED) ||
-        (p.mode != MD_CELLS_ONLY && p.mode != MD_NEIGHBOR_LIST) || p.newton3 != 0 ||
+        (p.mode != MD_CELLS_ONLY && p.mode != MD_NEIGHBOR_LIST) ||
+        (p.newton3 != 0 && p.newton3 != 1) || (p.newton3 && p.mode != MD_NEIGHBOR_LIST) ||
         p.nl_capacity < 0 || (p.reorder != 0 && p.reorder != 1) || p.block % 64 != 0 ||
         p.block < 64 || p.block > 1024)
         return MD_ERR_ARG;
@@ -496,7 +501,8 @@ static md_status traj_check(md_ctx* c, const md_traj_params* tp, void* ws, TrajL
 {
     if (!c || !tp || !ws || !traj_layout(c, tp, L)) return MD_ERR_ARG;
     if (!c->bound) return MD_ERR_NOT_BOUND;
-    if (c->prm.mode != MD_NEIGHBOR_LIST || c->prm.reorder != 0) return MD_ERR_ARG;
+    if (c->prm.mode != MD_NEIGHBOR_LIST || c->prm.reorder != 0 || c->prm.newton3 != 0)
+        return MD_ERR_ARG;
     if (((uintptr_t)ws) % kAlign != 0) return MD_ERR_ARG;
     if (tp->n_bins > 0 && tp->gr_rmax + 3.0 * tp->gr_width > c->prm.r_cut + c->prm.skin)
         return MD_ERR_ARG;
@@ -605,7 +611,7 @@ extern "C" md_status md_traj_backward(md_ctx* c, const md_traj_params* tp, void*
     a.theta = theta;
     a.tpart = reinterpret_cast<double*>(static_cast<char*>(ws) + L.tpart);
     a.gobs = grad_obs;
-    a.cap = adj_stage_cap(k, c->lds_limit);
+    a.cap = k.scap_aux;
     int cur = 0;
     // one point: lambda_v of buffer cur in, of the other buffer out
     auto point = [&](double coef, double loss_scale, double drift) {

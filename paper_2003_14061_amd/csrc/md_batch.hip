@@ -114,6 +114,7 @@ md_status upload(md_batch* b)
     sh.precision = p0.precision;
     sh.reorder = p0.reorder;
     sh.mode = p0.mode;
+    sh.newton3 = p0.newton3;
     for (int r = 0; r < R; ++r) {
         const int nlb = kp[r].nl_block;
         sh.nl_block = nlb > sh.nl_block ? nlb : sh.nl_block;
@@ -193,7 +194,7 @@ extern "C" md_status md_batch_init(const md_params* params, int32_t n_replicas, 
         const md_params& p = params[r];
         const md_params& p0 = params[0];
         if (p.precision != p0.precision || p.mode != p0.mode || p.reorder != p0.reorder ||
-            p.block != p0.block) {
+            p.newton3 != p0.newton3 || p.block != p0.block) {
             md_batch_destroy(b);
             return MD_ERR_ARG;
         }

@@ -12,6 +12,16 @@
 // from the wrap bits carried by each entry (section 4.1, factor (4)); tiles
 // with no periodic wrap skip even that.
 //
+// With a half list (Newton's third law, the optional atomic variant the
+// paper sets aside in section 2.3) every pair is met once, from the atom
+// earlier in cell order; the partner's reaction force is added with LDS
+// atomics into a per-staged-atom accumulator beside the staged positions,
+// the home atom's own total goes there too, and at the end of the tile every
+// accumulator that was touched is added into the force arrays with global
+// atomics (which were cleared before the pass).  Tiles whose atoms do not
+// fit in LDS add straight into the force arrays.  The order of the atomic
+// adds is not fixed, so the forces are reproducible to rounding only.
+//
 // Cells-only mode: one lane per atom walks the 27 surrounding cells.
 //
 // Precision: FP64 forms everything in double.  FP32-mixed forms the pair
@@ -34,35 +44,51 @@ struct AccF {
     int np = 0;
 };
 
+// Adds the pair's force on the home atom, energy and virial to a, and
+// returns the force in g (for the partner's reaction under the third law).
 __device__ __forceinline__ void pair_acc(const KParams& p, double dx, double dy, double dz,
-                                         double r2, AccD& a)
+                                         double r2, AccD& a, double g[3])
 {
     const double inv = recip(r2);
     const double sr2 = p.sig2 * inv;
     const double sr6 = sr2 * sr2 * sr2;
     const double fr = p.eps48 * sr6 * (sr6 - 0.5) * inv;
-    a.fx += fr * dx;
-    a.fy += fr * dy;
-    a.fz += fr * dz;
+    g[0] = fr * dx;
+    g[1] = fr * dy;
+    g[2] = fr * dz;
+    a.fx += g[0];
+    a.fy += g[1];
+    a.fz += g[2];
     a.u += sr6 * (sr6 - 1.0);
     a.w += fr * r2;
     a.np += 1;
 }
 
 __device__ __forceinline__ void pair_acc(const KParams& p, double dx, double dy, double dz,
-                                         double r2, AccF& a)
+                                         double r2, AccF& a, float g[3])
 {
     const float r2f = (float)r2;
     const float inv = recipf(r2f);
     const float sr2 = (float)p.sig2 * inv;
     const float sr6 = sr2 * sr2 * sr2;
     const float fr = (float)p.eps48 * sr6 * (sr6 - 0.5f) * inv;
-    a.fx += fr * (float)dx;
-    a.fy += fr * (float)dy;
-    a.fz += fr * (float)dz;
+    g[0] = fr * (float)dx;
+    g[1] = fr * (float)dy;
+    g[2] = fr * (float)dz;
+    a.fx += g[0];
+    a.fy += g[1];
+    a.fz += g[2];
     a.u += sr6 * (sr6 - 1.0f);
     a.w += fr * r2f;
     a.np += 1;
+}
+
+template <typename Acc>
+__device__ __forceinline__ void pair_acc(const KParams& p, double dx, double dy, double dz,
+                                         double r2, Acc& a)
+{
+    decltype(a.fx) g[3];
+    pair_acc(p, dx, dy, dz, r2, a, g);
 }
 
 // Pair operation of the force pass: the pair force, energy and virial of
@@ -77,6 +103,133 @@ struct ForceOp {
         if (r2 < p.rc2) pair_acc(p, dx, dy, dz, r2, a);
     }
 };
+
+// Pair operation of the third-law pass: as ForceOp, and the reaction
+// -F into the partner's LDS accumulator (staged index e), or straight into
+// the force arrays at slot j when the tile is not staged.
+template <typename F, typename Acc>
+struct HalfOp {
+    const KParams& p;
+    Acc& a;
+    MD_LDS F *rx, *ry, *rz;
+    __device__ __forceinline__ void operator()(double dx, double dy, double dz, double r2, int e,
+                                               int j)
+    {
+        if (r2 >= p.rc2) return;
+        F g[3];
+        pair_acc(p, dx, dy, dz, r2, a, g);
+        if (j < 0) {
+            lds_add(rx + e, -g[0]);
+            lds_add(ry + e, -g[1]);
+            lds_add(rz + e, -g[2]);
+        } else {
+            global_add(static_cast<F*>(p.fx) + j, -g[0]);
+            global_add(static_cast<F*>(p.fy) + j, -g[1]);
+            global_add(static_cast<F*>(p.fz) + j, -g[2]);
+        }
+    }
+};
+
+template <typename F, typename Acc, int LANES, class B>
+__global__ void k_forces_half(B b)
+{
+    Wg wg;
+    KParams p;
+    if (!b.fetch(G_TILES, wg, p)) return;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    __shared__ double red[(1024 / kWave) * 2];
+    const Tile g = tile_of(p, xcd_tile(wg.id, wg.n));
+    Stage s = stage_layout(p, smem, p.scap_aux, true);
+    stage_tables(p, g, s);
+    const int nh = home_count(s), h0 = home_first_lds(s), slot0 = home_first_slot(s);
+    const int mode = image_mode(p, tile_interior(p, g));
+    stage_positions(p, s);
+    // the accumulators, in the aux region (F-typed)
+    MD_LDS F* rx = reinterpret_cast<MD_LDS F*>(s.ax);
+    MD_LDS F* ry = reinterpret_cast<MD_LDS F*>(s.ay);
+    MD_LDS F* rz = reinterpret_cast<MD_LDS F*>(s.az);
+    if (s.fits) {
+        for (int k = threadIdx.x; k < s.total; k += blockDim.x) {
+            rx[k] = F(0);
+            ry[k] = F(0);
+            rz[k] = F(0);
+        }
+    }
+    __syncthreads();
+    const int per_pass = blockDim.x / LANES;
+    const int sub = threadIdx.x % LANES;
+    double e[2] = {0.0, 0.0};
+    for (int hb = 0; hb < nh; hb += per_pass) {
+        const int h = hb + threadIdx.x / LANES;
+        Acc a;
+        int slot_i = 0;
+        if (h < nh) {
+            slot_i = atom_at(p, slot0 + h);
+            double xi, yi, zi;
+            home_position(p, s, h0, h, slot_i, xi, yi, zi);
+            HalfOp<F, Acc> op{p, a, rx, ry, rz};
+            walk_home<LANES>(p, s, mode, slot_i, sub, p.nl_count[slot_i], xi, yi, zi, op);
+        }
+        if (LANES > 1) {
+            a.fx = lane_group_sum<LANES>(a.fx);
+            a.fy = lane_group_sum<LANES>(a.fy);
+            a.fz = lane_group_sum<LANES>(a.fz);
+            a.u = lane_group_sum<LANES>(a.u);
+            a.w = lane_group_sum<LANES>(a.w);
+            a.np = lane_group_sum<LANES>(a.np);
+        }
+        if (h < nh && sub == 0) {
+            if (s.fits) {
+                lds_add(rx + h0 + h, a.fx);
+                lds_add(ry + h0 + h, a.fy);
+                lds_add(rz + h0 + h, a.fz);
+            } else {
+                global_add(static_cast<F*>(p.fx) + slot_i, a.fx);
+                global_add(static_cast<F*>(p.fy) + slot_i, a.fy);
+                global_add(static_cast<F*>(p.fz) + slot_i, a.fz);
+            }
+            // each pair once: its whole energy 4 eps (sr12 - sr6) - shift, and virial
+            const double ui = 2.0 * (p.eps2 * (double)a.u - p.half_shift * (double)a.np);
+            e[0] += ui;
+            e[1] += (double)a.w;
+            if (!isfinite(ui + (double)a.fx + (double)a.fy + (double)a.fz))
+                atomicOr(&p.dev->flags, (int)MD_FLAG_NONFINITE);
+        }
+    }
+    __syncthreads();
+    if (s.fits) {
+        // flush every touched accumulator (home atoms always; partners in
+        // the cells behind the home row in cell order never)
+        for (int k = threadIdx.x; k < s.total; k += blockDim.x) {
+            const F ax = rx[k], ay = ry[k], az = rz[k];
+            if (ax != F(0) || ay != F(0) || az != F(0)) {
+                const int j = staged_slot(p, s, k);
+                global_add(static_cast<F*>(p.fx) + j, ax);
+                global_add(static_cast<F*>(p.fy) + j, ay);
+                global_add(static_cast<F*>(p.fz) + j, az);
+            }
+        }
+    }
+    block_sum<2>(e, red);
+    if (threadIdx.x == 0) {
+        p.fpart[2 * wg.id] = e[0];
+        p.fpart[2 * wg.id + 1] = e[1];
+    }
+}
+
+// Clears the force arrays before a third-law pass.
+template <typename F, class B>
+__global__ void k_zero_forces(B b)
+{
+    Wg wg;
+    KParams p;
+    if (!b.fetch(G_ATOMS, wg, p)) return;
+    for (int i = wg.id * blockDim.x + threadIdx.x; i < p.n; i += wg.n * blockDim.x) {
+        static_cast<F*>(p.fx)[i] = F(0);
+        static_cast<F*>(p.fy)[i] = F(0);
+        static_cast<F*>(p.fz)[i] = F(0);
+    }
+}
 
 template <typename F, typename Acc, int LANES, class B>
 __global__ void k_forces_tiles(B b)
@@ -206,8 +359,26 @@ __global__ void k_forces_cells(B b)
 }
 
 template <typename F, typename Acc, class B>
+static void half_seq(const B& b, const LaunchShape& sh, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_zero_forces<F, B>), dim3(sh.grid[G_ATOMS]), dim3(sh.block), 0, s, b);
+    const dim3 g(sh.grid[G_TILES]), t(sh.force_block);
+    const size_t lds = sh.force_lds;
+    switch (sh.force_lanes) {
+        case 8: hipLaunchKernelGGL((k_forces_half<F, Acc, 8, B>), g, t, lds, s, b); break;
+        case 2: hipLaunchKernelGGL((k_forces_half<F, Acc, 2, B>), g, t, lds, s, b); break;
+        case 4: hipLaunchKernelGGL((k_forces_half<F, Acc, 4, B>), g, t, lds, s, b); break;
+        default: hipLaunchKernelGGL((k_forces_half<F, Acc, 1, B>), g, t, lds, s, b); break;
+    }
+}
+
+template <typename F, typename Acc, class B>
 static void tiles_seq(const B& b, const LaunchShape& sh, hipStream_t s)
 {
+    if (sh.newton3) {
+        half_seq<F, Acc>(b, sh, s);
+        return;
+    }
     const dim3 g(sh.grid[G_TILES]), t(sh.force_block);
     const size_t lds = sh.force_lds;
     switch (sh.force_lanes) {
@@ -239,7 +410,8 @@ int force_blocks(const KParams& p) { return grid_of(p, G_TILES); }
 
 size_t force_lds_bytes(const KParams& p)
 {
-    return p.mode == MD_NEIGHBOR_LIST ? stage_bytes(p.scap, p.kx_max) : 0;
+    if (p.mode != MD_NEIGHBOR_LIST) return 0;
+    return p.newton3 ? stage_bytes(p.scap_aux, p.kx_max, true) : stage_bytes(p.scap, p.kx_max);
 }
 
 LaunchShape shape_of(const KParams& p)
@@ -256,6 +428,7 @@ LaunchShape shape_of(const KParams& p)
     sh.precision = p.precision;
     sh.reorder = p.reorder;
     sh.mode = p.mode;
+    sh.newton3 = p.newton3;
     return sh;
 }
 

@@ -69,6 +69,7 @@ struct KParams {
     // tiling of the neighbor-list mode: rows of nc cells cut into tiles_per_row tiles
     int32_t tiles_per_row, kx_max, n_tiles;
     int32_t scap;           // staged atoms a workgroup's LDS holds
+    int32_t scap_aux;       // the same with a second 3-vector staged per atom
 };
 
 // Arguments of one reverse-mode point (md_adjoint.hip).  lambda_x is the
@@ -206,7 +207,7 @@ struct Batch {
 // Uniform launch shape: workgroups per grid rule, block sizes, dynamic LDS.
 struct LaunchShape {
     int grid[G_KINDS];
-    int block, force_block, force_lanes, nl_block, nl_method;
+    int block, force_block, force_lanes, nl_block, nl_method, newton3;
     size_t nl_lds, force_lds;
     int precision, reorder, mode;
 };
@@ -228,7 +229,7 @@ void launch_gr(const KParams& p, const GrArgs& g, hipStream_t s);
 void launch_gr_grad(const KParams& p, const GrArgs& g, hipStream_t s);
 void launch_traj_ubar(const KParams& p, int32_t n_steps, double* out, hipStream_t s);
 void launch_fill(double* a, size_t n, double v, hipStream_t s);
-int adj_stage_cap(const KParams& p, size_t lds_limit);
+
 void launch_clear(const KParams& p, hipStream_t s);
 void launch_cells(const KParams& p, int force, hipStream_t s);
 void launch_neighbors(const KParams& p, int force, hipStream_t s);

@@ -15,6 +15,13 @@
 //                    over its 64 lanes, 64 per round; for each home atom a
 //                    ballot and a prefix count place the hits
 //
+// The half list (for the Newton's-third-law force pass) keeps a candidate
+// only if it comes after the home atom in cell order (cell index, then
+// permanent id).  That order is the order of the cell-ordered slots:
+// candidate e of staged cell t sits at slot[t] + (e - off[t]), the home atom
+// h at home_first_slot + h, so the test is one integer comparison, and a
+// staged cell whose last slot is not past the home atom's is skipped whole.
+//
 // Storage follows the paper's W (section 2.3): row m holds the m-th
 // neighbor of every atom, so a wave of the force pass reads consecutive
 // atoms' entries at consecutive addresses.  Entries are 16 bits (staged
@@ -38,7 +45,7 @@ __device__ __forceinline__ double readlane_f64(double v, int lane)
 // time; lane L keeps home atom h0+L's position and list length in
 // registers, read by the whole wave with readlane while it tests 64
 // candidates at once.
-template <int kImage>
+template <int kImage, bool kHalf>
 __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, int q)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -89,6 +96,7 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
             const int t0 = sg * s.stride + q - 1;
             const int w = (e >= s.off[t0 + 1] ? 1 : 0) + (e >= s.off[t0 + 2] ? 1 : 0);
             const int fl = s.flag[t0 + w];
+            const int pos_j = s.slot[t0 + w] + (e - s.off[t0 + w]);
             double xj, yj, zj;
             if (s.fits) {
                 xj = s.xs[e];
@@ -108,7 +116,8 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
                              zi = readlane_f64(hz, hh);
                 double dx = xi - xj, dy = yi - yj, dz = zi - zj;
                 image<kImage>(p, fl, dx, dy, dz);
-                const bool hit = valid && dist2(dx, dy, dz) < p.rl2 && e != h0 + hh;
+                const bool later = !kHalf || pos_j > hslot0 + (h0 + hh - hb);
+                const bool hit = valid && later && dist2(dx, dy, dz) < p.rl2 && e != h0 + hh;
                 const uint64_t mask = __ballot(hit);
                 if (mask) {
                     const int base = __builtin_amdgcn_readlane(mcnt, hh);
@@ -163,11 +172,12 @@ __device__ __forceinline__ int home_column(const Stage& s, int kx, int e)
 
 // The list of home atom h (staged entry e_self, home column q), by one lane.
 // Returns the number of entries found (beyond the capacity: overflow).
-template <int kImage, bool kFits>
+template <int kImage, bool kFits, bool kHalf>
 __device__ __forceinline__ int nl_home_atom(const KParams& p, const Stage& s, int h, int q)
 {
     const int e_self = home_first_lds(s) + h;
-    const int slot_i = atom_at(p, home_first_slot(s) + h);
+    const int pos_i = home_first_slot(s) + h;
+    const int slot_i = atom_at(p, pos_i);
     double xi, yi, zi;
     if (kFits) {
         xi = s.xs[e_self];
@@ -188,8 +198,9 @@ __device__ __forceinline__ int nl_home_atom(const KParams& p, const Stage& s, in
             const int t = sg * s.stride + q - 1 + w;
             const int eb = s.off[t], ee = s.off[t + 1];
             const int fl = s.flag[t];
-            const int tslot = kFits ? 0 : s.slot[t];
+            const int tslot = kFits && !kHalf ? 0 : s.slot[t];
             const uint64_t tag = (uint64_t)fl << kEntryBits;
+            if (kHalf && tslot + (ee - eb) <= pos_i) continue;
             for (int e = eb; e < ee; ++e) {
                 double xj, yj, zj;
                 if (kFits) {
@@ -204,7 +215,8 @@ __device__ __forceinline__ int nl_home_atom(const KParams& p, const Stage& s, in
                 }
                 double dx = xi - xj, dy = yi - yj, dz = zi - zj;
                 image<kImage>(p, fl, dx, dy, dz);
-                if (dist2(dx, dy, dz) < p.rl2 && e != e_self) {
+                const bool later = !kHalf || tslot + (e - eb) > pos_i;
+                if (later && dist2(dx, dy, dz) < p.rl2 && e != e_self) {
                     if (m < cap) {
                         chunk |= ((uint64_t)e | tag) << (16 * (m % kChunk));
                         if (m % kChunk == kChunk - 1) {
@@ -230,13 +242,13 @@ __device__ __forceinline__ int nl_home_atom(const KParams& p, const Stage& s, in
     return (int)m;
 }
 
-template <int kImage, bool kFits>
+template <int kImage, bool kFits, bool kHalf>
 __device__ __forceinline__ void nl_lanes(const KParams& p, const Stage& s, int kx)
 {
     const int nh = home_count(s), h0 = home_first_lds(s);
     int mmax = 0;
     for (int h = threadIdx.x; h < nh; h += blockDim.x) {
-        const int m = nl_home_atom<kImage, kFits>(p, s, h, home_column(s, kx, h0 + h));
+        const int m = nl_home_atom<kImage, kFits, kHalf>(p, s, h, home_column(s, kx, h0 + h));
         mmax = m > mmax ? m : mmax;
     }
     mmax = wave_max(mmax);
@@ -246,7 +258,7 @@ __device__ __forceinline__ void nl_lanes(const KParams& p, const Stage& s, int k
     }
 }
 
-template <class B, int kMethod>
+template <class B, int kMethod, bool kHalf>
 __global__ void k_nl_tiles(B b, int force)
 {
     Wg wg;
@@ -273,26 +285,26 @@ __global__ void k_nl_tiles(B b, int force)
     if (kMethod == MD_NL_LANES) {
         if (!s.fits) {
             if (mode == 2)
-                nl_lanes<2, false>(p, s, g.kx);
+                nl_lanes<2, false, kHalf>(p, s, g.kx);
             else
-                nl_lanes<1, false>(p, s, g.kx);
+                nl_lanes<1, false, kHalf>(p, s, g.kx);
         } else if (mode == 0) {
-            nl_lanes<0, true>(p, s, g.kx);
+            nl_lanes<0, true, kHalf>(p, s, g.kx);
         } else if (mode == 1) {
-            nl_lanes<1, true>(p, s, g.kx);
+            nl_lanes<1, true, kHalf>(p, s, g.kx);
         } else {
-            nl_lanes<2, true>(p, s, g.kx);
+            nl_lanes<2, true, kHalf>(p, s, g.kx);
         }
         return;
     }
     const int wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
     for (int q = 1 + wid; q <= g.kx; q += nw) {
         if (mode == 0)
-            nl_home_cell<0>(p, s, q);
+            nl_home_cell<0, kHalf>(p, s, q);
         else if (mode == 1)
-            nl_home_cell<1>(p, s, q);
+            nl_home_cell<1, kHalf>(p, s, q);
         else
-            nl_home_cell<2>(p, s, q);
+            nl_home_cell<2, kHalf>(p, s, q);
     }
 }
 
@@ -319,14 +331,24 @@ __global__ void k_nl_export(KParams p, int32_t* out)
     }
 }
 
-template <class B>
+template <class B, bool kHalf>
 static void neighbors_seq(const B& b, const LaunchShape& sh, int force, hipStream_t s)
 {
     const dim3 g(sh.grid[G_TILES]), t(sh.nl_block);
     if (sh.nl_method == MD_NL_CELL_WAVES)
-        hipLaunchKernelGGL((k_nl_tiles<B, MD_NL_CELL_WAVES>), g, t, sh.nl_lds, s, b, force);
+        hipLaunchKernelGGL((k_nl_tiles<B, MD_NL_CELL_WAVES, kHalf>), g, t, sh.nl_lds, s, b,
+                           force);
     else
-        hipLaunchKernelGGL((k_nl_tiles<B, MD_NL_LANES>), g, t, sh.nl_lds, s, b, force);
+        hipLaunchKernelGGL((k_nl_tiles<B, MD_NL_LANES, kHalf>), g, t, sh.nl_lds, s, b, force);
+}
+
+template <class B>
+static void neighbors_seq(const B& b, const LaunchShape& sh, int force, hipStream_t s)
+{
+    if (sh.newton3)
+        neighbors_seq<B, true>(b, sh, force, s);
+    else
+        neighbors_seq<B, false>(b, sh, force, s);
 }
 
 void launch_neighbors(const KParams& p, int force, hipStream_t s)

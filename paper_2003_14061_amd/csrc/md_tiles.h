@@ -30,6 +30,21 @@ namespace md {
 
 #define MD_LDS __attribute__((address_space(3)))
 
+// Floating-point adds for the third-law force pass: workgroup-scope on LDS,
+// device-scope on global memory (the force arrays are ordinary device
+// allocations, where the hardware's float and double atomic adds apply).
+template <typename T>
+__device__ __forceinline__ void lds_add(MD_LDS T* a, T v)
+{
+    __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <typename T>
+__device__ __forceinline__ void global_add(T* a, T v)
+{
+    unsafeAtomicAdd(a, v);
+}
+
 constexpr int kEntryBits = 13;
 constexpr int kEntryMask = (1 << kEntryBits) - 1;
 constexpr int kMaxStaged = 1 << kEntryBits;  // virtual layout limit

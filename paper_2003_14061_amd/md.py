@@ -278,7 +278,7 @@ class Simulation:
 
     def __init__(self, pos, vel, L, *, r_cut, dt, skin=0.3, eps=1.0, sigma=1.0, mass=1.0,
                  shifted=True, precision="fp64", neighbor_list=True, reorder=None,
-                 nl_capacity=0, block=256, device="cuda", stream=None):
+                 newton3=False, nl_capacity=0, block=256, device="cuda", stream=None):
         import torch
 
         if not torch.cuda.is_available():
@@ -294,8 +294,9 @@ class Simulation:
         self.params = Params(int(n), MD_LJ_SHIFTED if shifted else MD_LJ_TRUNC, float(L),
                              float(eps), float(sigma), float(mass), float(r_cut), float(skin),
                              float(dt), MD_FP64 if precision == "fp64" else MD_FP32_MIXED,
-                             MD_NEIGHBOR_LIST if neighbor_list else MD_CELLS_ONLY, 0,
-                             int(nl_capacity), int(bool(reorder)), int(block))
+                             MD_NEIGHBOR_LIST if neighbor_list else MD_CELLS_ONLY,
+                             int(bool(newton3)), int(nl_capacity), int(bool(reorder)),
+                             int(block))
         self.n = n
         self.L = float(L)
         self.device = torch.device(device)
@@ -517,7 +518,7 @@ class Batch:
     run can be captured into a HIP graph."""
 
     def __init__(self, systems, *, precision="fp32", neighbor_list=True, reorder=None,
-                 block=256, device="cuda"):
+                 newton3=False, block=256, device="cuda"):
         import torch
 
         if not torch.cuda.is_available():
@@ -536,8 +537,9 @@ class Batch:
                                  float(sy.get("sigma", 1.0)), float(sy.get("mass", 1.0)),
                                  float(sy["r_cut"]), float(sy.get("skin", 0.3)), float(sy["dt"]),
                                  MD_FP64 if precision == "fp64" else MD_FP32_MIXED,
-                                 MD_NEIGHBOR_LIST if neighbor_list else MD_CELLS_ONLY, 0,
-                                 int(sy.get("nl_capacity", 0)), int(bool(reorder)), int(block)))
+                                 MD_NEIGHBOR_LIST if neighbor_list else MD_CELLS_ONLY,
+                                 int(bool(newton3)), int(sy.get("nl_capacity", 0)),
+                                 int(bool(reorder)), int(block)))
         self.params = params
         self.ctx = md_batch_init(params, self.R)
         self.replicas = [md_batch_replica(self.ctx, r) for r in range(self.R)]

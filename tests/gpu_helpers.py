@@ -26,12 +26,12 @@ def state(n, rho, seed, jitter=0.0, lattice=True):
 
 
 def pair(pos, vel, L, *, r_cut, dt=0.005, skin=0.3, nl=True, shifted=True,
-         precision="fp64", reorder=None, nl_capacity=0, block=256):
+         precision="fp64", reorder=None, nl_capacity=0, block=256, newton3=False):
     """A GPU Simulation and the oracle system description with the same
     parameters (same list capacity)."""
     sim = md.Simulation(pos, vel, L, r_cut=r_cut, dt=dt, skin=skin, shifted=shifted,
                         precision=precision, neighbor_list=nl, reorder=reorder,
-                        nl_capacity=nl_capacity, block=block)
+                        nl_capacity=nl_capacity, block=block, newton3=newton3)
     cap = sim.grid.nl_capacity if nl else 1
     s = oracle.make_sys(len(pos), L, r_cut=r_cut, skin=skin if nl else 0.0, dt=dt,
                         potential=oracle.LJ_SHIFTED if shifted else oracle.LJ_TRUNC,
@@ -59,9 +59,12 @@ def check_cells(sim, s, pos):
     return nc, (o_of, o_start, o_atoms)
 
 
-def check_nl(sim, s, pos, cells):
+def check_nl(sim, s, pos, cells, half=False):
+    """The GPU list against the oracle's (the half list with half=True),
+    entry by entry in atom-id space."""
     nc = sim.grid.nc
-    o_cnt, o_nl, longest = oracle.build_nl(s, nc, pos, cells)
+    build = oracle.build_nl_half if half else oracle.build_nl
+    o_cnt, o_nl, longest = build(s, nc, pos, cells)
     cnt, nl = sim.neighbor_list()
     ids = sim.ids()
     n = len(ids)

@@ -42,7 +42,8 @@ def params(**kw):
     L = inputs.box_length(base["n"], base["rho"])
     return md.Params(base["n"], md.MD_LJ_SHIFTED, L, 1.0, 1.0, 1.0, base["r_cut"], base["skin"],
                      base["dt"], base.get("precision", md.MD_FP64),
-                     base.get("mode", md.MD_NEIGHBOR_LIST), 0, base.get("cap", 0),
+                     base.get("mode", md.MD_NEIGHBOR_LIST), base.get("newton3", 0),
+                     base.get("cap", 0),
                      base.get("reorder", 1), base.get("block", 256))
 
 
@@ -83,11 +84,18 @@ def test_geometry_of_the_workloads():
 @pytest.mark.parametrize("bad", [
     dict(n=0), dict(r_cut=-1.0), dict(dt=0.0), dict(skin=-0.1), dict(block=100),
     dict(block=2048), dict(precision=7), dict(mode=3), dict(reorder=2), dict(cap=-1),
+    dict(newton3=2), dict(newton3=-1), dict(newton3=1, mode=md.MD_CELLS_ONLY),
 ])
 def test_invalid_parameters_are_rejected(bad):
     ctx = C.c_void_p()
     st = md.lib().md_init(C.byref(params(**bad)), C.byref(ctx))
     assert st == -1 and not ctx.value
+
+
+def test_third_law_variant_is_accepted_with_a_list():
+    for prec in (md.MD_FP64, md.MD_FP32_MIXED):
+        ctx = md.md_init(params(n=32000, rho=0.8, r_cut=2.5, newton3=1, precision=prec))
+        md.md_destroy(ctx)
 
 
 def test_box_too_small():
