@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-mixed measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
+    ap.add_argument("--no-newton3", action="store_true",
+                    help="skip the third-law (half list, atomic) variant")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward ratio of the differentiable run")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -91,13 +93,14 @@ def measured_traffic(n_atoms, precision):
         return None
 
 
-def run_gpu(w, precision, steps, warmup):
+def run_gpu(w, precision, steps, warmup, newton3=False):
     import torch
 
     from paper_2003_14061_amd import md
 
     sim = md.Simulation(w.pos, w.vel, w.L, r_cut=w.r_cut, skin=w.skin, dt=w.dt,
-                        shifted=w.shifted, precision=precision, neighbor_list=w.use_nl)
+                        shifted=w.shifted, precision=precision, neighbor_list=w.use_nl,
+                        newton3=newton3)
     sim.prepare()
     sim.step(warmup)
     o0 = sim.reduce()
@@ -323,6 +326,11 @@ def main():
         mixed = run_gpu(w, "fp32", args.steps, args.warmup)
         print(f"[bench] fp32-mixed done: {mixed['value']:.3e} atom-steps/s", file=sys.stderr,
               flush=True)
+    n3 = None
+    if not args.no_newton3:
+        n3 = run_gpu(w, "fp64", args.steps, args.warmup, newton3=True)
+        print(f"[bench] fp64 third-law variant done: {n3['value']:.3e} atom-steps/s",
+              file=sys.stderr, flush=True)
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
     cpu = None
@@ -363,6 +371,15 @@ def main():
                              "energy_drift_per_atom": mixed["energy_drift_per_atom"],
                              "force_ms_avg": round(mixed["force_ms_avg"], 5),
                              "speedup_vs_fp64": round(mixed["value"] / fp64["value"], 3)}
+    if n3 is not None:
+        out["newton3_fp64"] = {"value": round(n3["value"], 1),
+                               "ms_per_step": round(n3["ms_per_step"], 5),
+                               "force_ms_avg": round(n3["force_ms_avg"], 5),
+                               "mean_half_nl": round(n3["mean_nl"], 2),
+                               "rebuilds": n3["rebuilds"],
+                               "energy_drift_per_atom": n3["energy_drift_per_atom"],
+                               "speedup_vs_full_list": round(n3["value"] / fp64["value"], 3),
+                               "kernels": "k_zero_forces + k_forces_half"}
     if not args.no_batch:
         bt = run_batch()
         print(f"[bench] batch done: {bt['value']:.3e} atom-steps/s", file=sys.stderr, flush=True)
