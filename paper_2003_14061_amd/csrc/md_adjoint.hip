@@ -104,9 +104,7 @@ struct AdjOp {
         if (!(r2 < p.rc2)) return;
         double ljx, ljy, ljz;
         if (j < 0) {
-            ljx = s.ax[e];
-            ljy = s.ay[e];
-            ljz = s.az[e];
+            lds_xyz(s.a3, e, ljx, ljy, ljz);
         } else {
             ljx = q.vx[j];
             ljy = q.vy[j];
@@ -164,9 +162,7 @@ __global__ void k_adj_point(KParams p, AdjArgs q)
             double xi, yi, zi;
             home_position(p, s, h0, h, i, xi, yi, zi);
             if (s.fits) {
-                vix = s.ax[h0 + h];
-                viy = s.ay[h0 + h];
-                viz = s.az[h0 + h];
+                lds_xyz(s.a3, h0 + h, vix, viy, viz);
             } else {
                 vix = q.vx[i];
                 viy = q.vy[i];

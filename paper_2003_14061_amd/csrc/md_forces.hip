@@ -111,7 +111,7 @@ template <typename F, typename Acc>
 struct HalfOp {
     const KParams& p;
     Acc& a;
-    MD_LDS F *rx, *ry, *rz;
+    MD_LDS F* r;  // [cap][3] reaction accumulators
     __device__ __forceinline__ void operator()(double dx, double dy, double dz, double r2, int e,
                                                int j)
     {
@@ -119,9 +119,9 @@ struct HalfOp {
         F g[3];
         pair_acc(p, dx, dy, dz, r2, a, g);
         if (j < 0) {
-            lds_add(rx + e, -g[0]);
-            lds_add(ry + e, -g[1]);
-            lds_add(rz + e, -g[2]);
+            lds_add(r + 3 * e, -g[0]);
+            lds_add(r + 3 * e + 1, -g[1]);
+            lds_add(r + 3 * e + 2, -g[2]);
         } else {
             global_add(static_cast<F*>(p.fx) + j, -g[0]);
             global_add(static_cast<F*>(p.fy) + j, -g[1]);
@@ -144,16 +144,10 @@ __global__ void k_forces_half(B b)
     const int nh = home_count(s), h0 = home_first_lds(s), slot0 = home_first_slot(s);
     const int mode = image_mode(p, tile_interior(p, g));
     stage_positions(p, s);
-    // the accumulators, in the aux region (F-typed)
-    MD_LDS F* rx = reinterpret_cast<MD_LDS F*>(s.ax);
-    MD_LDS F* ry = reinterpret_cast<MD_LDS F*>(s.ay);
-    MD_LDS F* rz = reinterpret_cast<MD_LDS F*>(s.az);
+    // the accumulators, in the aux region (F-typed, interleaved)
+    MD_LDS F* r = reinterpret_cast<MD_LDS F*>(s.a3);
     if (s.fits) {
-        for (int k = threadIdx.x; k < s.total; k += blockDim.x) {
-            rx[k] = F(0);
-            ry[k] = F(0);
-            rz[k] = F(0);
-        }
+        for (int k = threadIdx.x; k < 3 * s.total; k += blockDim.x) r[k] = F(0);
     }
     __syncthreads();
     const int per_pass = blockDim.x / LANES;
@@ -167,7 +161,7 @@ __global__ void k_forces_half(B b)
             slot_i = atom_at(p, slot0 + h);
             double xi, yi, zi;
             home_position(p, s, h0, h, slot_i, xi, yi, zi);
-            HalfOp<F, Acc> op{p, a, rx, ry, rz};
+            HalfOp<F, Acc> op{p, a, r};
             walk_home<LANES>(p, s, mode, slot_i, sub, p.nl_count[slot_i], xi, yi, zi, op);
         }
         if (LANES > 1) {
@@ -180,9 +174,9 @@ __global__ void k_forces_half(B b)
         }
         if (h < nh && sub == 0) {
             if (s.fits) {
-                lds_add(rx + h0 + h, a.fx);
-                lds_add(ry + h0 + h, a.fy);
-                lds_add(rz + h0 + h, a.fz);
+                lds_add(r + 3 * (h0 + h), a.fx);
+                lds_add(r + 3 * (h0 + h) + 1, a.fy);
+                lds_add(r + 3 * (h0 + h) + 2, a.fz);
             } else {
                 global_add(static_cast<F*>(p.fx) + slot_i, a.fx);
                 global_add(static_cast<F*>(p.fy) + slot_i, a.fy);
@@ -201,7 +195,7 @@ __global__ void k_forces_half(B b)
         // flush every touched accumulator (home atoms always; partners in
         // the cells behind the home row in cell order never)
         for (int k = threadIdx.x; k < s.total; k += blockDim.x) {
-            const F ax = rx[k], ay = ry[k], az = rz[k];
+            const F ax = r[3 * k], ay = r[3 * k + 1], az = r[3 * k + 2];
             if (ax != F(0) || ay != F(0) || az != F(0)) {
                 const int j = staged_slot(p, s, k);
                 global_add(static_cast<F*>(p.fx) + j, ax);

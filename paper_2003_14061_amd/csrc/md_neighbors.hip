@@ -70,9 +70,7 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
         const int slot_l = atom_at(p, hslot0 + (hl - hb));
         double hx, hy, hz;
         if (s.fits) {
-            hx = s.xs[hl];
-            hy = s.ys[hl];
-            hz = s.zs[hl];
+            lds_xyz(s.p3, hl, hx, hy, hz);
         } else {
             hx = p.x[slot_l];
             hy = p.y[slot_l];
@@ -99,9 +97,7 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
             const int pos_j = s.slot[t0 + w] + (e - s.off[t0 + w]);
             double xj, yj, zj;
             if (s.fits) {
-                xj = s.xs[e];
-                yj = s.ys[e];
-                zj = s.zs[e];
+                lds_xyz(s.p3, e, xj, yj, zj);
             } else {
                 // lanes past the candidates read the home cell's first atom (e is
                 // not inside window cell t0 + w for them)
@@ -180,9 +176,7 @@ __device__ __forceinline__ int nl_home_atom(const KParams& p, const Stage& s, in
     const int slot_i = atom_at(p, pos_i);
     double xi, yi, zi;
     if (kFits) {
-        xi = s.xs[e_self];
-        yi = s.ys[e_self];
-        zi = s.zs[e_self];
+        lds_xyz(s.p3, e_self, xi, yi, zi);
     } else {
         xi = p.x[slot_i];
         yi = p.y[slot_i];
@@ -204,9 +198,7 @@ __device__ __forceinline__ int nl_home_atom(const KParams& p, const Stage& s, in
             for (int e = eb; e < ee; ++e) {
                 double xj, yj, zj;
                 if (kFits) {
-                    xj = s.xs[e];
-                    yj = s.ys[e];
-                    zj = s.zs[e];
+                    lds_xyz(s.p3, e, xj, yj, zj);
                 } else {
                     const int j = atom_at(p, tslot + (e - eb));
                     xj = p.x[j];

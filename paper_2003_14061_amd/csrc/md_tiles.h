@@ -73,14 +73,16 @@ __device__ __forceinline__ Tile tile_of(const KParams& p, int t)
     return g;
 }
 
-// LDS view of one staged tile.  Entry `total` of xs, ys, zs holds a sentinel
-// atom far outside the box; list chunks are padded with its index, so a
-// padded entry never falls inside the cutoff.  Kernels that also need a
-// per-atom vector of each partner (the adjoint's lambda) stage it in ax,
-// ay, az beside the positions.
+// LDS view of one staged tile.  Positions are interleaved, x y z of staged
+// atom e at p3[3e .. 3e+2], so that one address serves a paired 16-byte read
+// of (x, y) and an 8-byte read of z.  Entry `total` holds a sentinel atom
+// far outside the box; list chunks are padded with its index, so a padded
+// entry never falls inside the cutoff.  Kernels that also need a per-atom
+// vector of each partner (the adjoint's lambda, the third-law reactions)
+// keep it in a3, interleaved the same way.
 struct Stage {
-    MD_LDS double *xs, *ys, *zs;  // [cap]
-    MD_LDS double *ax, *ay, *az;  // [cap] when staged with an auxiliary vector
+    MD_LDS double* p3;            // [cap][3]
+    MD_LDS double* a3;            // [cap][3] when staged with an auxiliary vector
     MD_LDS int* off;              // [ntab + 1] LDS offset of each staged cell
     MD_LDS int* slot;             // [ntab] global slot of each staged cell's first atom
     MD_LDS int* flag;             // [ntab] wrap bits
@@ -90,6 +92,16 @@ struct Stage {
 };
 
 constexpr double kSentinel = 1.0e30;
+
+// The 3-vector of staged atom e from an interleaved [cap][3] LDS array.
+__device__ __forceinline__ void lds_xyz(const MD_LDS double* a, int e, double& x, double& y,
+                                        double& z)
+{
+    const MD_LDS double* q = a + 3 * e;
+    x = q[0];
+    y = q[1];
+    z = q[2];
+}
 
 // Ints of the table region, rounded up to 16 bytes.
 __host__ __device__ __forceinline__ int stage_table_ints(int kx_max)
@@ -110,14 +122,10 @@ __device__ __forceinline__ Stage stage_layout(const KParams& p, char* smem, int 
 {
     Stage s;
     s.cap = cap;
-    s.xs = (MD_LDS double*)smem;
-    s.ys = s.xs + cap;
-    s.zs = s.ys + cap;
-    s.ax = aux ? s.zs + cap : nullptr;
-    s.ay = aux ? s.ax + cap : nullptr;
-    s.az = aux ? s.ay + cap : nullptr;
+    s.p3 = (MD_LDS double*)smem;
+    s.a3 = aux ? s.p3 + 3 * cap : nullptr;
     const int ntab_max = 9 * (p.kx_max + 2);
-    s.off = (MD_LDS int*)(s.zs + (aux ? 4 : 1) * cap);
+    s.off = (MD_LDS int*)(s.p3 + (aux ? 6 : 3) * cap);
     s.slot = s.off + ntab_max + 1;
     s.flag = s.slot + ntab_max;
     s.scan = s.flag + ntab_max;
@@ -222,25 +230,25 @@ __device__ __forceinline__ void stage_atoms(const KParams& p, const Stage& s, co
         for (int u = 0; u < U; ++u) {
             const int k = k0 + u * blockDim.x;
             if (k < s.total) {
-                s.xs[k] = px[u];
-                s.ys[k] = py[u];
-                s.zs[k] = pz[u];
+                s.p3[3 * k] = px[u];
+                s.p3[3 * k + 1] = py[u];
+                s.p3[3 * k + 2] = pz[u];
                 if (kAux) {
-                    s.ax[k] = qx[u];
-                    s.ay[k] = qy[u];
-                    s.az[k] = qz[u];
+                    s.a3[3 * k] = qx[u];
+                    s.a3[3 * k + 1] = qy[u];
+                    s.a3[3 * k + 2] = qz[u];
                 }
             }
         }
     }
     if (threadIdx.x == 0) {
-        s.xs[s.total] = kSentinel;
-        s.ys[s.total] = kSentinel;
-        s.zs[s.total] = kSentinel;
+        s.p3[3 * s.total] = kSentinel;
+        s.p3[3 * s.total + 1] = kSentinel;
+        s.p3[3 * s.total + 2] = kSentinel;
         if (kAux) {
-            s.ax[s.total] = 0.0;
-            s.ay[s.total] = 0.0;
-            s.az[s.total] = 0.0;
+            s.a3[3 * s.total] = 0.0;
+            s.a3[3 * s.total + 1] = 0.0;
+            s.a3[3 * s.total + 2] = 0.0;
         }
     }
 }
@@ -327,9 +335,7 @@ __device__ __forceinline__ void chunk_pairs(const KParams& p, const Stage& s, ui
         int j = -1;
         if (kFits) {
             if (kMask) e = valid ? e : 0;
-            xj = s.xs[e];
-            yj = s.ys[e];
-            zj = s.zs[e];
+            lds_xyz(s.p3, e, xj, yj, zj);
         } else {
             j = staged_slot(p, s, valid && e < s.total ? e : 0);
             xj = p.x[j];
@@ -388,9 +394,7 @@ __device__ __forceinline__ void home_position(const KParams& p, const Stage& s, 
                                               int slot_i, double& xi, double& yi, double& zi)
 {
     if (s.fits) {
-        xi = s.xs[h0 + h];
-        yi = s.ys[h0 + h];
-        zi = s.zs[h0 + h];
+        lds_xyz(s.p3, h0 + h, xi, yi, zi);
     } else {
         xi = p.x[slot_i];
         yi = p.y[slot_i];
