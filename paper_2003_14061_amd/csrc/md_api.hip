@@ -56,7 +56,7 @@ static void plan_tiles(md_ctx* c, int cells)
     k.kx_max = (nc + k.tiles_per_row - 1) / k.tiles_per_row;
     k.n_tiles = nc * nc * k.tiles_per_row;
     const double s_mean = 9.0 * (k.kx_max + 2) * occ;
-    // tables, the list build's per-wave scratch and static LDS
+    // tables and static LDS
     const size_t tables = stage_bytes(0, k.kx_max) + 2048;
     const size_t room = c->lds_limit > tables ? c->lds_limit - tables : 0;
     int scap = c->stage_cap > 0 ? c->stage_cap : (int)(1.5 * s_mean + 128.0);

@@ -31,8 +31,7 @@
 
 namespace md {
 
-// LDS bytes of the list build: the staged tile.
-size_t nl_lds_bytes(const KParams& p) { return stage_bytes(p.scap, p.kx_max); }
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ double readlane_f64(double v, int lane)
 {
@@ -41,110 +40,135 @@ __device__ __forceinline__ double readlane_f64(double v, int lane)
     return __hiloint2double(hi, lo);
 }
 
-// One home cell q of the tile, by one wave.  Home atoms are taken 64 at a
-// time; lane L keeps home atom h0+L's position and list length in
-// registers, read by the whole wave with readlane while it tests 64
-// candidates at once.
-template <int kImage, bool kHalf>
+// LDS bytes of the list build: the staged tile.
+size_t nl_lds_bytes(const KParams& p, int) { return stage_bytes(p.scap, p.kx_max); }
+
+// One home cell q of the tile, by one wave.  The candidates (the 9 windows
+// of cells q-1..q+1 of every staged row, concatenated, in canonical order)
+// are taken kNlRounds x 64 at a time: lane l holds candidate k0 + 64 r + l
+// (position, wrap bits, encoded entry) in registers.  Each home atom hh in
+// turn is broadcast from lane hh (readlane) and tested against the block;
+// for round r the hit ballot places the hits: a hit lane's entry goes to
+// list position m_hh + (hits of lower lanes), m_hh being hh's running list
+// length, kept in a scalar register while hh is tested and in lane hh of a
+// vector register between blocks.  Lanes past the candidates read the home
+// cell's first atom (e = hb) and never hit.
+template <int kImage, bool kHalf, bool kFits>
 __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, int q)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int home_t = 4 * s.stride + q;
-    const int hb = s.off[home_t], he = s.off[home_t + 1];
-    const int hslot0 = s.slot[home_t];
-    // the 9 candidate windows (cells q-1..q+1 of every staged row), concatenated
+    // table values are the same in every lane: keep them in scalar registers
+    const int hb = uniform(s.off[home_t]), he = uniform(s.off[home_t + 1]);
+    const int hslot0 = uniform(s.slot[home_t]);
     int wa[9], wp[10];
     wp[0] = 0;
 #pragma unroll
     for (int sg = 0; sg < 9; ++sg) {
-        wa[sg] = s.off[sg * s.stride + q - 1];
-        wp[sg + 1] = wp[sg] + (s.off[sg * s.stride + q + 2] - wa[sg]);
+        wa[sg] = uniform(s.off[sg * s.stride + q - 1]);
+        wp[sg + 1] = wp[sg] + (uniform(s.off[sg * s.stride + q + 2]) - wa[sg]);
     }
     const int ncand = wp[9];
-    const uint32_t cap = (uint32_t)p.cap;
+    const int cap = p.cap;  // a multiple of 4
     uint16_t* nl16 = reinterpret_cast<uint16_t*>(p.nl64);
+    const uint32_t npad4 = 4u * (uint32_t)p.npad;  // 16-bit entries per chunk row
+    const bool small = npad4 < (1u << 24);         // row offsets by 24-bit multiply
     for (int h0 = hb; h0 < he; h0 += kWave) {
         const int nhs = he - h0 < kWave ? he - h0 : kWave;
-        // this lane's home atom
-        const int hl = h0 + (lane < nhs ? lane : 0);
+        const bool home_lane = lane < nhs;
+        const int hl = h0 + (home_lane ? lane : 0);
         const int slot_l = atom_at(p, hslot0 + (hl - hb));
         double hx, hy, hz;
-        if (s.fits) {
+        if (kFits) {
             lds_xyz(s.p3, hl, hx, hy, hz);
         } else {
             hx = p.x[slot_l];
             hy = p.y[slot_l];
             hz = p.z[slot_l];
         }
-        int mcnt = 0;
-        for (int k0 = 0; k0 < ncand; k0 += kWave) {
-            const int k = k0 + lane;
-            const bool valid = k < ncand;
-            int sg = 0;
+        int mreg = 0;  // lane hh: home atom hh's list length so far
+        for (int k0 = 0; k0 < ncand; k0 += kNlRounds * kWave) {
+            const int nr = (ncand - k0 + kWave - 1) / kWave;  // rounds with candidates
+            double cx[kNlRounds], cy[kNlRounds], cz[kNlRounds];
+            int ce[kNlRounds], cfl[kNlRounds], cpos[kNlRounds];
+            uint16_t cenc[kNlRounds];
+            bool cval[kNlRounds];
 #pragma unroll
-            for (int j = 1; j < 9; ++j) sg += k >= wp[j] ? 1 : 0;
-            int a = wa[0], pre = wp[0];
+            for (int r = 0; r < kNlRounds; ++r) {
+                const int k = k0 + r * kWave + lane;
+                cval[r] = k < ncand;
+                int sg = 0;
 #pragma unroll
-            for (int j = 1; j < 9; ++j) {
-                a = sg == j ? wa[j] : a;
-                pre = sg == j ? wp[j] : pre;
+                for (int j = 1; j < 9; ++j) sg += k >= wp[j] ? 1 : 0;
+                int a = wa[0], pre = wp[0];
+#pragma unroll
+                for (int j = 1; j < 9; ++j) {
+                    a = sg == j ? wa[j] : a;
+                    pre = sg == j ? wp[j] : pre;
+                }
+                const int e = cval[r] ? a + (k - pre) : hb;
+                const int t0 = sg * s.stride + q - 1;
+                const int w = (e >= s.off[t0 + 1] ? 1 : 0) + (e >= s.off[t0 + 2] ? 1 : 0);
+                const int t = cval[r] ? t0 + w : home_t;
+                ce[r] = e;
+                cfl[r] = s.flag[t];
+                cpos[r] = s.slot[t] + (e - s.off[t]);
+                cenc[r] = (uint16_t)((uint32_t)e | ((uint32_t)cfl[r] << kEntryBits));
+                if (kFits) {
+                    lds_xyz(s.p3, e, cx[r], cy[r], cz[r]);
+                } else {
+                    const int j = atom_at(p, cpos[r]);
+                    cx[r] = p.x[j];
+                    cy[r] = p.y[j];
+                    cz[r] = p.z[j];
+                }
             }
-            const int e = valid ? a + (k - pre) : hb;
-            // which of the window's three cells holds e, and its wrap bits
-            const int t0 = sg * s.stride + q - 1;
-            const int w = (e >= s.off[t0 + 1] ? 1 : 0) + (e >= s.off[t0 + 2] ? 1 : 0);
-            const int fl = s.flag[t0 + w];
-            const int pos_j = s.slot[t0 + w] + (e - s.off[t0 + w]);
-            double xj, yj, zj;
-            if (s.fits) {
-                lds_xyz(s.p3, e, xj, yj, zj);
-            } else {
-                // lanes past the candidates read the home cell's first atom (e is
-                // not inside window cell t0 + w for them)
-                const int j = atom_at(p, valid ? s.slot[t0 + w] + (e - s.off[t0 + w]) : hslot0);
-                xj = p.x[j];
-                yj = p.y[j];
-                zj = p.z[j];
-            }
-            const uint32_t enc = (uint32_t)e | ((uint32_t)fl << kEntryBits);
             for (int hh = 0; hh < nhs; ++hh) {
+                const int eh = h0 + hh;
+                const int pos_i = hslot0 + (eh - hb);
                 const double xi = readlane_f64(hx, hh), yi = readlane_f64(hy, hh),
                              zi = readlane_f64(hz, hh);
-                double dx = xi - xj, dy = yi - yj, dz = zi - zj;
-                image<kImage>(p, fl, dx, dy, dz);
-                const bool later = !kHalf || pos_j > hslot0 + (h0 + hh - hb);
-                const bool hit = valid && later && dist2(dx, dy, dz) < p.rl2 && e != h0 + hh;
-                const uint64_t mask = __ballot(hit);
-                if (mask) {
-                    const int base = __builtin_amdgcn_readlane(mcnt, hh);
-                    if (hit) {
-                        const uint32_t m = (uint32_t)base + __builtin_amdgcn_mbcnt_hi(
-                            (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                        if (m < cap) {
-                            const int slot_i =
-                                __builtin_amdgcn_readlane(slot_l, hh);
-                            nl16[((int64_t)(m / kChunk) * p.npad + slot_i) * kChunk + m % kChunk] =
-                                (uint16_t)enc;
+                const int slot_h = __builtin_amdgcn_readlane(slot_l, hh);
+                int m_h = __builtin_amdgcn_readlane(mreg, hh);
+                uint16_t* base = nl16 + (int64_t)slot_h * kChunk;
+#pragma unroll
+                for (int r = 0; r < kNlRounds; ++r) {
+                    if (r < nr) {
+                        double dx = xi - cx[r], dy = yi - cy[r], dz = zi - cz[r];
+                        image<kImage>(p, cfl[r], dx, dy, dz);
+                        const bool later = !kHalf || cpos[r] > pos_i;
+                        const bool hit = cval[r] & later & (dist2(dx, dy, dz) < p.rl2) &
+                                         (ce[r] != eh);
+                        const uint64_t mask = __builtin_amdgcn_ballot_w64(hit);
+                        if (hit) {
+                            const uint32_t m = (uint32_t)m_h + __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(mask >> 32),
+                                __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                            if (m < (uint32_t)cap) {
+                                const uint32_t row = m / kChunk;
+                                const uint32_t idx = (small ? __umul24(row, npad4)
+                                                            : row * npad4) + m % kChunk;
+                                base[idx] = cenc[r];
+                            }
                         }
+                        m_h += (int)__popcll(mask);
                     }
-                    if (lane == hh) mcnt = base + (int)__popcll(mask);
                 }
+                mreg = lane == hh ? m_h : mreg;
             }
         }
         // lengths, sentinel padding of the last chunk, displacement references
-        int m = 0;
-        if (lane < nhs) {
-            m = mcnt;
-            const int stored = m < p.cap ? m : p.cap;
+        if (home_lane) {
+            const int stored = mreg < cap ? mreg : cap;
             p.nl_count[slot_l] = stored;
+            uint16_t* base = nl16 + (int64_t)slot_l * kChunk;
             for (int mm = stored; mm % kChunk != 0; ++mm)
-                nl16[((int64_t)(mm / kChunk) * p.npad + slot_l) * kChunk + mm % kChunk] =
-                    (uint16_t)s.total;
+                base[(int64_t)(mm / kChunk) * npad4 + mm % kChunk] = (uint16_t)s.total;
             p.xr[slot_l] = hx;
             p.yr[slot_l] = hy;
             p.zr[slot_l] = hz;
         }
-        const int mmax = wave_max(m);
+        const int mmax = wave_max(home_lane ? mreg : 0);
         if (lane == 0 && mmax > 0) {
             atomicMax(&p.dev->max_nl, mmax);
             if (mmax > p.cap) atomicOr(&p.dev->flags, (int)MD_FLAG_NL_OVERFLOW);
@@ -291,12 +315,18 @@ __global__ void k_nl_tiles(B b, int force)
     }
     const int wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
     for (int q = 1 + wid; q <= g.kx; q += nw) {
-        if (mode == 0)
-            nl_home_cell<0, kHalf>(p, s, q);
-        else if (mode == 1)
-            nl_home_cell<1, kHalf>(p, s, q);
-        else
-            nl_home_cell<2, kHalf>(p, s, q);
+        if (!s.fits) {
+            if (mode == 2)
+                nl_home_cell<2, kHalf, false>(p, s, q);
+            else
+                nl_home_cell<1, kHalf, false>(p, s, q);
+        } else if (mode == 0) {
+            nl_home_cell<0, kHalf, true>(p, s, q);
+        } else if (mode == 1) {
+            nl_home_cell<1, kHalf, true>(p, s, q);
+        } else {
+            nl_home_cell<2, kHalf, true>(p, s, q);
+        }
     }
 }
 

@@ -118,6 +118,9 @@ inline size_t stage_bytes(int cap, int kx_max, bool aux = false)
            sizeof(int) * (size_t)stage_table_ints(kx_max);
 }
 
+// Candidate rounds (of 64) held in registers by the cell-wave list build.
+constexpr int kNlRounds = 4;
+
 __device__ __forceinline__ Stage stage_layout(const KParams& p, char* smem, int cap, bool aux)
 {
     Stage s;
