@@ -37,17 +37,20 @@ extern "C" const char* md_status_str(int32_t st)
 }
 
 // Tiling of the neighbor-list mode: each row of nc cells is cut into
-// tiles_per_row tiles of about `cells` cells (0: enough cells to fill about
-// 80% of the force workgroup's home-atom slots at the mean occupancy, so that
-// one pass of the workgroup covers the tile).  The LDS capacity allows 1.5x
-// the mean staged count, within the device's per-workgroup LDS.
+// tiles_per_row tiles of about `cells` cells (0: enough cells for about 1.25
+// home atoms per lane group of the force workgroup at the mean occupancy;
+// the staging of a tile's neighborhood is then shared by more home atoms
+// than one pass of the workgroup holds).  The LDS capacity allows 1.15x the
+// mean staged count plus 64, so that three force workgroups share a CU at
+// the dense LJ state; a tile that does not fit takes its partners from
+// global memory.
 static void plan_tiles(md_ctx* c, int cells)
 {
     KParams& k = c->kp;
     const int nc = k.nc;
     const double occ = (double)k.n / ((double)nc * nc * nc);
     if (cells <= 0) {
-        const double home = 0.8 * k.force_block / k.force_lanes;
+        const double home = 1.25 * k.force_block / k.force_lanes;
         cells = (int)floor(home / (occ > 1e-9 ? occ : 1e-9));
     }
     const int kx_cap = nc < 128 ? nc : 128;
@@ -59,7 +62,7 @@ static void plan_tiles(md_ctx* c, int cells)
     // tables and static LDS
     const size_t tables = stage_bytes(0, k.kx_max) + 2048;
     const size_t room = c->lds_limit > tables ? c->lds_limit - tables : 0;
-    int scap = c->stage_cap > 0 ? c->stage_cap : (int)(1.5 * s_mean + 128.0);
+    int scap = c->stage_cap > 0 ? c->stage_cap : (int)(1.15 * s_mean + 64.0);
     const int scap_max = (int)(room / (3 * sizeof(double)));
     if (scap > scap_max) scap = scap_max;
     scap = scap / 64 * 64;
