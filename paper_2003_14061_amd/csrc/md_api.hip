@@ -74,16 +74,15 @@ static void plan_tiles(md_ctx* c, int cells)
     c->tile_cells = cells;
     k.nblk_force = force_blocks(k);
     // list build: a lane per home atom of a mean tile (25% spare), or a
-    // wave per home cell of the widest tile (fewer waves, each taking
-    // several cells, when a tile holds under ~24 atoms per cell)
+    // wave per home cell of the widest tile (at most 16 waves, each then
+    // taking several cells)
     k.nl_method = c->nl_method_req != MD_NL_AUTO ? c->nl_method_req
                                                  : (occ < 8.0 ? MD_NL_LANES : MD_NL_CELL_WAVES);
     int waves;
     if (k.nl_method == MD_NL_LANES) {
         waves = (int)ceil(1.25 * k.kx_max * occ / kWave);
     } else {
-        waves = (int)ceil(k.kx_max * occ / 24.0);
-        waves = waves > k.kx_max ? k.kx_max : waves;
+        waves = k.kx_max < 16 ? k.kx_max : 16;
     }
     waves = waves < 1 ? 1 : waves;
     const int nlb = c->nl_block_req > 0 ? c->nl_block_req : kWave * waves;
