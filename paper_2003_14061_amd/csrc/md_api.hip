@@ -201,6 +201,7 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
         shift = 4.0 * p.eps * (sr6 * sr6 - sr6);
     }
     k.half_shift = 0.5 * shift;
+    k.ushift = k.half_shift / k.eps2;
     k.hdt = (0.5 * p.dt) / p.mass;
     k.dt = p.dt;
     k.disp_thr2 = (0.5 * p.skin) * (0.5 * p.skin);

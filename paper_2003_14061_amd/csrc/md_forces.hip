@@ -34,14 +34,14 @@
 
 namespace md {
 
+// Per-atom sums: force, u = sum over pairs of sr^12 - sr^6 - shift/(4 eps)
+// (the pair energy is 4 eps u_pair, half of it the atom's), virial.
 struct AccD {
     double fx = 0, fy = 0, fz = 0, u = 0, w = 0;
-    int np = 0;
 };
 
 struct AccF {
     float fx = 0, fy = 0, fz = 0, u = 0, w = 0;
-    int np = 0;
 };
 
 // Adds the pair's force on the home atom, energy and virial to a, and
@@ -59,9 +59,8 @@ __device__ __forceinline__ void pair_acc(const KParams& p, double dx, double dy,
     a.fx += g[0];
     a.fy += g[1];
     a.fz += g[2];
-    a.u += sr6 * (sr6 - 1.0);
+    a.u += sr6 * (sr6 - 1.0) - p.ushift;
     a.w += fr * r2;
-    a.np += 1;
 }
 
 __device__ __forceinline__ void pair_acc(const KParams& p, double dx, double dy, double dz,
@@ -78,9 +77,8 @@ __device__ __forceinline__ void pair_acc(const KParams& p, double dx, double dy,
     a.fx += g[0];
     a.fy += g[1];
     a.fz += g[2];
-    a.u += sr6 * (sr6 - 1.0f);
+    a.u += sr6 * (sr6 - 1.0f) - (float)p.ushift;
     a.w += fr * r2f;
-    a.np += 1;
 }
 
 template <typename Acc>
@@ -170,7 +168,6 @@ __global__ void k_forces_half(B b)
             a.fz = lane_group_sum<LANES>(a.fz);
             a.u = lane_group_sum<LANES>(a.u);
             a.w = lane_group_sum<LANES>(a.w);
-            a.np = lane_group_sum<LANES>(a.np);
         }
         if (h < nh && sub == 0) {
             if (s.fits) {
@@ -183,7 +180,7 @@ __global__ void k_forces_half(B b)
                 global_add(static_cast<F*>(p.fz) + slot_i, a.fz);
             }
             // each pair once: its whole energy 4 eps (sr12 - sr6) - shift, and virial
-            const double ui = 2.0 * (p.eps2 * (double)a.u - p.half_shift * (double)a.np);
+            const double ui = 2.0 * p.eps2 * (double)a.u;
             e[0] += ui;
             e[1] += (double)a.w;
             if (!isfinite(ui + (double)a.fx + (double)a.fy + (double)a.fz))
@@ -260,14 +257,13 @@ __global__ void k_forces_tiles(B b)
             a.fz = lane_group_sum<LANES>(a.fz);
             a.u = lane_group_sum<LANES>(a.u);
             a.w = lane_group_sum<LANES>(a.w);
-            a.np = lane_group_sum<LANES>(a.np);
         }
         if (h < nh && sub == 0) {
             static_cast<F*>(p.fx)[slot_i] = a.fx;
             static_cast<F*>(p.fy)[slot_i] = a.fy;
             static_cast<F*>(p.fz)[slot_i] = a.fz;
             // per-atom energy: half of each pair's 4 eps (sr12 - sr6) - shift
-            const double ui = p.eps2 * (double)a.u - p.half_shift * (double)a.np;
+            const double ui = p.eps2 * (double)a.u;
             e[0] += ui;
             e[1] += 0.5 * (double)a.w;
             if (!isfinite(ui + (double)a.fx + (double)a.fy + (double)a.fz))
@@ -341,7 +337,7 @@ __global__ void k_forces_cells(B b)
         static_cast<F*>(p.fz)[i] = a.fz;
     }
     double e[2];
-    e[0] = i < p.n ? p.eps2 * (double)a.u - p.half_shift * (double)a.np : 0.0;
+    e[0] = i < p.n ? p.eps2 * (double)a.u : 0.0;
     e[1] = i < p.n ? 0.5 * (double)a.w : 0.0;
     if (i < p.n && !isfinite(e[0] + (double)a.fx + (double)a.fy + (double)a.fz))
         atomicOr(&p.dev->flags, (int)MD_FLAG_NONFINITE);
