@@ -65,12 +65,18 @@ __global__ __launch_bounds__(256) void k_adj_reimage(KParams p, const double* px
         p.ipart[8 * blockIdx.x + 4] = t;
     }
     if (!last_block(p.dev, gridDim.x)) return;
+    // the last workgroup: maximum over the partials, spread over its threads
+    double t = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+        const double v = p.ipart[8 * b + 4];
+        t = v > t ? v : t;
+    }
+    t = wave_max(t);
+    __syncthreads();
+    if (lane == 0) red[wid] = t;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int b = 0; b < (int)gridDim.x; ++b) {
-            const double v = p.ipart[8 * b + 4];
-            t = v > t ? v : t;
-        }
+        for (int w = 0; w < (int)blockDim.x / kWave; ++w) t = red[w] > t ? red[w] : t;
         p.dev->dmax2 = t;
         p.dev->rebuild = t > p.disp_thr2 ? 1 : 0;
         p.dev->blocks_done = 0;

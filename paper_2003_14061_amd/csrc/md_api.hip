@@ -148,7 +148,6 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
 
     // workspace layout
     const int64_t ncell = (int64_t)nc * nc * nc;
-    const int ntile = (int)((ncell + 1023) / 1024);
     const size_t fsz = p.precision == MD_FP64 ? sizeof(double) : sizeof(float);
     size_t* b = c->bytes;
     b[R_DEV] = sizeof(DevState);
@@ -164,7 +163,6 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
     b[R_SID] = b[R_SCELL] = perm * sizeof(int32_t) * n;
     b[R_FPART] = sizeof(double) * 2 * (size_t)max_force_blocks(n, ncell);
     b[R_IPART] = sizeof(double) * 8 * kIntegrateGridMax;
-    b[R_SCAN] = sizeof(int32_t) * 2 * (size_t)ntile;
     b[R_HIST] = sizeof(md_record) * kHistCap;
     size_t o = 0;
     for (int r = 0; r < R_COUNT; ++r) {
@@ -297,7 +295,6 @@ extern "C" md_status md_bind(md_ctx* c, const md_buffers* bf, void* stream)
     k.scell = static_cast<int32_t*>(at(R_SCELL));
     k.fpart = static_cast<double*>(at(R_FPART));
     k.ipart = static_cast<double*>(at(R_IPART));
-    k.scanpart = static_cast<int32_t*>(at(R_SCAN));
     k.hist = static_cast<md_record*>(at(R_HIST));
     c->stream = static_cast<hipStream_t>(stream);
     int dev = 0, lds = 0;

@@ -103,126 +103,83 @@ __device__ __forceinline__ int wave_incl_scan(int v)
     return v;
 }
 
-// Exclusive scan of one value per thread across the workgroup (kScanThreads).
-__device__ __forceinline__ int block_excl_scan(int v, int* total)
-{
-    __shared__ int wsum[kScanThreads / kWave];
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    int inc = wave_incl_scan(v);
-    if (lane == kWave - 1) wsum[wid] = inc;
-    __syncthreads();
-    int off = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < kScanThreads / kWave; ++w) {
-        if (w < wid) off += wsum[w];
-        tot += wsum[w];
-    }
-    __syncthreads();
-    *total = tot;
-    return off + inc - v;
-}
-
-// Per tile: sum and max of the counts.
+// The cell offsets: one workgroup of kScanThreads threads scans the counts
+// kScanPer cells per thread at a time (one 16-byte load each), in chunks of
+// kScanThreads * kScanPer cells carried over in order; writes cell_start,
+// clears the counts for the next binning and records the largest
+// occupancy.  A single launch, so that a step with no rebuild pays for one
+// idle kernel here rather than three.
 template <class B>
-__global__ __launch_bounds__(kScanThreads) void k_scan_partial(B b, int force)
-{
-    Wg wg;
-    KParams p;
-    if (!b.fetch(G_SCAN, wg, p)) return;
-    if (!rebuild_on(p, force)) return;
-    const int base = wg.id * kScanTile + threadIdx.x * kScanPer;
-    int s = 0, m = 0;
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-        int c = base + k;
-        int v = c < p.ncell ? p.cell_count[c] : 0;
-        s += v;
-        m = v > m ? v : m;
-    }
-    s = wave_sum(s);
-    m = wave_max(m);
-    __shared__ int ss[kScanThreads / kWave], sm[kScanThreads / kWave];
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    if (lane == 0) {
-        ss[wid] = s;
-        sm[wid] = m;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int ts = 0, tm = 0;
-        for (int w = 0; w < kScanThreads / kWave; ++w) {
-            ts += ss[w];
-            tm = sm[w] > tm ? sm[w] : tm;
-        }
-        p.scanpart[2 * wg.id] = ts;
-        p.scanpart[2 * wg.id + 1] = tm;
-    }
-}
-
-// One workgroup: exclusive scan of the tile sums (in place), largest occupancy.
-template <class B>
-__global__ __launch_bounds__(kScanThreads) void k_scan_top(B b, int force)
+__global__ __launch_bounds__(kScanThreads) void k_scan(B b, int force)
 {
     Wg wg;
     KParams p;
     if (!b.fetch(G_ONE, wg, p)) return;
     if (!rebuild_on(p, force)) return;
-    const int ntile = grid_of(p, G_SCAN);
-    __shared__ int carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    int m = 0;
-    for (int base = 0; base < ntile; base += kScanThreads) {
-        int t = base + threadIdx.x;
-        int v = t < ntile ? p.scanpart[2 * t] : 0;
-        int mv = t < ntile ? p.scanpart[2 * t + 1] : 0;
-        m = mv > m ? mv : m;
-        int total;
-        int ex = block_excl_scan(v, &total);
-        if (t < ntile) p.scanpart[2 * t] = carry + ex;
+    __shared__ int wsum[kScanThreads / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    int carry = 0, m = 0;
+    for (int c0 = 0; c0 < p.ncell; c0 += kScanThreads * kScanPer) {
+        const int c = c0 + threadIdx.x * kScanPer;
+        int v[kScanPer];
+        if (c + kScanPer <= p.ncell) {
+            const int4 q = *reinterpret_cast<const int4*>(p.cell_count + c);
+            v[0] = q.x;
+            v[1] = q.y;
+            v[2] = q.z;
+            v[3] = q.w;
+        } else {
+#pragma unroll
+            for (int k = 0; k < kScanPer; ++k) v[k] = c + k < p.ncell ? p.cell_count[c + k] : 0;
+        }
+        int sum = 0;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            sum += v[k];
+            m = v[k] > m ? v[k] : m;
+        }
+        // exclusive scan of the thread sums: wave64 shuffles, then the wave totals
+        int inc = sum;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int t = __shfl_up(inc, o, kWave);
+            if (lane >= o) inc += t;
+        }
+        if (lane == kWave - 1) wsum[wid] = inc;
         __syncthreads();
-        if (threadIdx.x == 0) carry += total;
+        int before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kScanThreads / kWave; ++w) {
+            before += w < wid ? wsum[w] : 0;
+            total += wsum[w];
+        }
         __syncthreads();
+        int ex = carry + before + inc - sum;
+        if (c + kScanPer <= p.ncell) {
+            *reinterpret_cast<int4*>(p.cell_start + c) =
+                make_int4(ex, ex + v[0], ex + v[0] + v[1], ex + v[0] + v[1] + v[2]);
+            *reinterpret_cast<int4*>(p.cell_count + c) = make_int4(0, 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int k = 0; k < kScanPer; ++k) {
+                if (c + k < p.ncell) {
+                    p.cell_start[c + k] = ex;
+                    p.cell_count[c + k] = 0;
+                }
+                ex += v[k];
+            }
+        }
+        carry += total;
     }
     m = wave_max(m);
-    __shared__ int sm[kScanThreads / kWave];
-    if ((threadIdx.x & (kWave - 1)) == 0) sm[threadIdx.x / kWave] = m;
+    if (lane == 0) wsum[wid] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
         int tm = 0;
-        for (int w = 0; w < kScanThreads / kWave; ++w) tm = sm[w] > tm ? sm[w] : tm;
+        for (int w = 0; w < kScanThreads / kWave; ++w) tm = wsum[w] > tm ? wsum[w] : tm;
         p.dev->max_occ = tm;
         p.dev->max_nl = 0;
         p.cell_start[p.ncell] = carry;
-    }
-}
-
-// Per tile: local exclusive scan plus the tile offset -> cell_start; clear counts.
-template <class B>
-__global__ __launch_bounds__(kScanThreads) void k_scan_final(B b, int force)
-{
-    Wg wg;
-    KParams p;
-    if (!b.fetch(G_SCAN, wg, p)) return;
-    if (!rebuild_on(p, force)) return;
-    const int base = wg.id * kScanTile + threadIdx.x * kScanPer;
-    int v[kScanPer], s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-        int c = base + k;
-        v[k] = c < p.ncell ? p.cell_count[c] : 0;
-        s += v[k];
-    }
-    int total;
-    int ex = block_excl_scan(s, &total) + p.scanpart[2 * wg.id];
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-        int c = base + k;
-        if (c < p.ncell) {
-            p.cell_start[c] = ex;
-            p.cell_count[c] = 0;
-        }
-        ex += v[k];
     }
 }
 
@@ -315,11 +272,7 @@ static void cells_seq(const B& b, const LaunchShape& sh, int force, hipStream_t 
 {
     const dim3 atoms(sh.grid[G_ATOMS]), blk(sh.block);
     hipLaunchKernelGGL(k_bin<B>, atoms, blk, 0, s, b, force);
-    hipLaunchKernelGGL(k_scan_partial<B>, dim3(sh.grid[G_SCAN]), dim3(kScanThreads), 0, s, b,
-                       force);
-    hipLaunchKernelGGL(k_scan_top<B>, dim3(sh.grid[G_ONE]), dim3(kScanThreads), 0, s, b, force);
-    hipLaunchKernelGGL(k_scan_final<B>, dim3(sh.grid[G_SCAN]), dim3(kScanThreads), 0, s, b,
-                       force);
+    hipLaunchKernelGGL(k_scan<B>, dim3(sh.grid[G_ONE]), dim3(kScanThreads), 0, s, b, force);
     hipLaunchKernelGGL(k_scatter<B>, atoms, blk, 0, s, b, force);
     hipLaunchKernelGGL(k_cellsort<B>, atoms, blk, 0, s, b, force);
     if (sh.reorder) {

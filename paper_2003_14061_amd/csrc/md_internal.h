@@ -57,7 +57,6 @@ struct KParams {
     int32_t *sid, *scell;
     double *fpart;    // force-pass partials [nblk_force][2]: U, W
     double *ipart;    // per-atom kernel partials [int_grid][8]
-    int32_t *scanpart;  // scan partials [nscan][2]: sum, max
     md_record* hist;
     int32_t nblk_force;     // workgroups of the last-configured force pass
     int32_t block;
@@ -110,11 +109,10 @@ struct Wg {
 
 // The grid rules of the launches; a batched launch concatenates, per rule,
 // the workgroups of every replica.
-enum GridKind { G_ATOMS, G_SCAN, G_ONE, G_INTEGRATE, G_TILES, G_KINDS };
+enum GridKind { G_ATOMS, G_ONE, G_INTEGRATE, G_TILES, G_KINDS };
 
-constexpr int kScanThreads = 256;
+constexpr int kScanThreads = 1024;  // the one workgroup of the cell-offset scan
 constexpr int kScanPer = 4;
-constexpr int kScanTile = kScanThreads * kScanPer;
 
 __host__ __device__ inline int grid_of(const KParams& p, GridKind k)
 {
@@ -124,7 +122,6 @@ __host__ __device__ inline int grid_of(const KParams& p, GridKind k)
             const int g = up(p.n, p.block);
             return g < p.gate_grid ? (g > 0 ? g : 1) : p.gate_grid;
         }
-        case G_SCAN: return up(p.ncell, kScanTile);
         case G_ONE: return 1;
         case G_INTEGRATE: {
             const int g = up(p.n, kIntThreads);
@@ -164,7 +161,7 @@ __device__ __forceinline__ KParams global_view(const KParams& q)
     p.sfx = as_global(q.sfx); p.sfy = as_global(q.sfy); p.sfz = as_global(q.sfz);
     p.sid = as_global(q.sid); p.scell = as_global(q.scell);
     p.fpart = as_global(q.fpart); p.ipart = as_global(q.ipart);
-    p.scanpart = as_global(q.scanpart); p.hist = as_global(q.hist);
+    p.hist = as_global(q.hist);
     return p;
 }
 
