@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void k_adj_reimage(KParams p, const double* px
     // the last workgroup: maximum over the partials, spread over its threads
     double t = 0.0;
     for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
-        const double v = p.ipart[8 * b + 4];
+        const double v = load_coherent(p.ipart + 8 * b + 4);
         t = v > t ? v : t;
     }
     t = wave_max(t);
@@ -218,8 +218,8 @@ __global__ void k_adj_point(KParams p, AdjArgs q)
     if (!last_block(p.dev, gridDim.x)) return;
     double v[2] = {0.0, 0.0};
     for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
-        v[0] += q.tpart[2 * b];
-        v[1] += q.tpart[2 * b + 1];
+        v[0] += load_coherent(q.tpart + 2 * b);
+        v[1] += load_coherent(q.tpart + 2 * b + 1);
     }
     block_sum<2>(v, red);
     if (threadIdx.x == 0) {

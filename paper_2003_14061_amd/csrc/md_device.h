@@ -150,6 +150,9 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* red)
     __syncthreads();
 }
 
+// A value another workgroup of the running kernel published before its
+// release in last_block: an agent-scope atomic load, which reads the
+// coherence point past this XCD's L2 without invalidating it.
 __device__ __forceinline__ double load_coherent(const double* p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -168,10 +171,12 @@ __device__ __forceinline__ int load_coherent(const int* p)
 //
 // The partial must have been stored by thread 0: its counter increment is a
 // release at agent scope, which orders thread 0's own earlier stores before
-// it.  Only the last workgroup issues the matching acquire.  (On gfx950 an
-// agent-scope release writes back the XCD's L2 and an acquire invalidates
-// it, so a fence in every thread of every workgroup would cost far more than
-// the reduction itself.)
+// it (on gfx950 it writes back the XCD's L2).  The last workgroup reads the
+// partials with load_coherent, which sees them without the L2 invalidation
+// an agent-scope acquire fence would cost on every XCD that holds a last
+// workgroup (one per replica in a batch); its own ordering is a
+// workgroup-scope acquire after the counter.  Data of earlier kernels is
+// visible through the kernel boundary.
 __device__ __forceinline__ bool last_block(DevState* dev, int n_wg)
 {
     __shared__ int is_last;
@@ -183,7 +188,7 @@ __device__ __forceinline__ bool last_block(DevState* dev, int n_wg)
     }
     __syncthreads();
     const bool last = is_last != 0;
-    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     return last;
 }
 

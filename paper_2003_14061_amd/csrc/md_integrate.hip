@@ -20,12 +20,12 @@
 namespace md {
 
 // Sum partials [nb][stride] (component k) over workgroups in a fixed order.
-// Called only by the last workgroup, after the acquire fence of last_block,
-// so plain loads see every other workgroup's partial.
+// Called only by the last workgroup (see last_block), reading the partials
+// with coherent loads.
 __device__ double finish_sum(const double* part, int nb, int stride, int k, double* red)
 {
     double v[1] = {0.0};
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) v[0] += part[b * stride + k];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) v[0] += load_coherent(part + b * stride + k);
     block_sum<1>(v, red);
     return v[0];
 }
@@ -34,7 +34,7 @@ __device__ double finish_max(const double* part, int nb, int stride, int k, doub
 {
     double m = 0.0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        double t = part[b * stride + k];
+        double t = load_coherent(part + b * stride + k);
         m = t > m ? t : m;
     }
     m = wave_max(m);
