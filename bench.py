@@ -146,9 +146,33 @@ def run_gpu(w, precision, steps, warmup, newton3=False):
                                "flops_per_atom": round(force_flops_per_atom(mean_nl,
                                                                             mean_in_range), 1)}}
     res["mean_in_range"] = mean_in_range
+    res["final_pos"] = sim.state()["pos"]
     del sim
     torch.cuda.synchronize()
     return res
+
+
+def force_error_fp32(w, pos):
+    """Per-step force error of the FP32-mixed path: its forces against the FP64
+    path's on the same positions (the state the FP64 run ended in), per atom
+    relative to the largest FP64 force and normwise."""
+    import numpy as np
+    import torch
+
+    from paper_2003_14061_amd import md
+
+    f = {}
+    for prec in ("fp64", "fp32"):
+        sim = md.Simulation(pos, np.zeros_like(pos), w.L, r_cut=w.r_cut, skin=w.skin, dt=w.dt,
+                            shifted=w.shifted, precision=prec)
+        sim.prepare()
+        f[prec] = sim.state()["f"]
+        del sim
+        torch.cuda.synchronize()
+    d = np.linalg.norm(f["fp32"] - f["fp64"], axis=1)
+    scale = float(np.linalg.norm(f["fp64"], axis=1).max())
+    return {"max_per_atom_rel_to_max_force": float(d.max() / scale),
+            "normwise": float(np.linalg.norm(f["fp32"] - f["fp64"]) / np.linalg.norm(f["fp64"]))}
 
 
 def run_adjoint(precision, repeats=3):
@@ -374,7 +398,9 @@ def main():
         "force_ms_avg": round(fp64["force_ms_avg"], 5),
     }
     if mixed is not None:
+        ferr = force_error_fp32(w, fp64["final_pos"]) if "final_pos" in fp64 else None
         out["fp32_mixed"] = {"value": round(mixed["value"], 1),
+                             "force_error_vs_fp64": ferr,
                              "ms_per_step": round(mixed["ms_per_step"], 5),
                              "roofline": mixed["roofline"], "rebuilds": mixed["rebuilds"],
                              "energy_drift_per_atom": mixed["energy_drift_per_atom"],

@@ -1,0 +1,115 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times (default tuning, or the autotuner's pick for the ensemble):
+
+  * the 2.048M-atom LJ system and the 256 000-atom WCA system after a stretch
+    of steps: cells bit-exact over all atoms, list lengths of all atoms, list
+    entries and brute-force forces of a sample of atoms, total energy and
+    virial against the oracle's full-list sums, kinetic energy and momentum;
+  * the 64-replica ensemble, every replica against its own oracle run;
+  * the 4000-atom cells-only WCA system over its full 1000 steps: momentum
+    and energy conservation (the trajectory itself is chaotic at that length).
+
+Tolerances as in the small-size parity tests: 1e-12 (FP64) and 1e-5
+(FP32-mixed) on forces per atom against S_i, normwise and on energies.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2003_14061_amd import inputs
+from paper_2003_14061_amd import md
+
+from gpu_helpers import check_cells, force_errors, min_image
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+STEPS = {"lj_2048k": 30, "wca_256k": 60}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["lj_2048k", "wca_256k"])
+def test_full_size_state_matches_the_oracle_on_samples(name, precision):
+    w = inputs.preset(name).materialize()
+    sim = md.Simulation(w.pos, w.vel, w.L, r_cut=w.r_cut, skin=w.skin, dt=w.dt,
+                        precision=precision)
+    sim.prepare()
+    sim.step(STEPS[name])
+    # cells and list at the current positions (the build folds them into the box)
+    sim.build_cells()
+    sim.build_neighbors()
+    sim.forces()
+    obs = sim.reduce()
+    st = sim.state()
+    pos, vel, n = st["pos"], st["vel"], w.n
+    assert pos.min() >= 0.0 and pos.max() < w.L
+    s = oracle.make_sys(n, w.L, r_cut=w.r_cut, skin=w.skin, dt=w.dt,
+                        nl_cap=sim.grid.nl_capacity)
+    nc, cells = check_cells(sim, s, pos)
+    o_cnt, o_nl, longest = oracle.build_nl(s, nc, pos, cells)
+    assert longest <= sim.grid.nl_capacity
+    cnt, nl = sim.neighbor_list()
+    ids = sim.ids()
+    cnt_id = np.empty(n, np.int32)
+    cnt_id[ids] = cnt[:n]
+    assert np.array_equal(cnt_id, o_cnt), "list lengths differ"
+    assert obs["max_nl"] == int(o_cnt.max())
+    # entries of a sample, in list order
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(n, 2000, replace=False)).astype(np.int32)
+    slot_of = np.empty(n, np.int64)
+    slot_of[ids] = np.arange(n)
+    for i in idx:
+        k = slot_of[i]
+        got = ids[nl[: cnt[k], k]]
+        assert np.array_equal(got, o_nl[i, : o_cnt[i]]), i
+    # forces of the sample against brute force over all atoms
+    ref = oracle.forces_sample(s, pos, idx)
+    per_atom, normwise = force_errors(st["f"][idx], ref)
+    assert per_atom <= TOL[precision] and normwise <= TOL[precision], (per_atom, normwise)
+    # totals against the oracle's full-list pass
+    full = oracle.forces_nl(s, pos, o_cnt, o_nl)
+    assert abs(obs["U"] - full["u"].sum()) <= TOL[precision] * np.abs(full["u"]).sum()
+    assert obs["W"] == pytest.approx(full["w"].sum(), rel=TOL[precision] * 10, abs=1e-9)
+    assert obs["K"] == pytest.approx(oracle.kinetic(s, vel), rel=1e-13)
+    assert np.allclose(obs["P"], oracle.momentum(s, vel), atol=1e-9)
+    assert obs["flags"] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_ensemble_matches_the_oracle(precision):
+    reps = inputs.ensemble(64, seed=4)
+    systems = [dict(pos=r.pos, vel=r.vel, L=r.L, r_cut=r.r_cut, dt=r.dt, skin=r.skin)
+               for r in reps]
+    b = md.Batch(systems, precision=precision)
+    b.set_tuning(force_lanes=2, force_block=256)
+    b.prepare()
+    steps = 20
+    b.run(steps, record_every=1, graph=True)
+    b.synchronize()
+    tol = {"fp64": 1e-10, "fp32": 1e-5}[precision]
+    for r, w in enumerate(reps):
+        s = oracle.make_sys(w.n, w.L, r_cut=w.r_cut, skin=w.skin, dt=w.dt)
+        p_ref, v_ref, _, o_ref, _ = oracle.run(s, w.pos, w.vel, steps)
+        st, h = b.state(r), b.history(r)
+        e_scale = np.abs(o_ref["U"]).max() + np.abs(o_ref["K"]).max()
+        assert np.max(np.abs(h["U"] - o_ref["U"])) <= tol * e_scale, r
+        assert np.max(np.abs(h["K"] - o_ref["K"])) <= tol * e_scale, r
+        assert np.abs(min_image(st["pos"] - p_ref, w.L)).max() < tol, r
+        assert b.reduce(r)["flags"] == 0, r
+
+
+def test_cells_only_wca_4000_conserves_over_1000_steps():
+    w = inputs.preset("wca_4000").materialize()
+    sim = md.Simulation(w.pos, w.vel, w.L, r_cut=w.r_cut, dt=w.dt, neighbor_list=False)
+    sim.prepare()
+    sim.step(1000, record_every=10)
+    h = sim.history()
+    assert len(h) == 100
+    E = (h["U"] + h["K"]) / w.n
+    assert np.abs(h["P"]).max() < 1e-10
+    assert E.max() - E.min() < 3e-3
+    # the first steps follow the oracle (the short-run tests check this closely)
+    s = oracle.make_sys(w.n, w.L, r_cut=w.r_cut, dt=w.dt, use_nl=False)
+    _, _, _, o_ref, _ = oracle.run(s, w.pos, w.vel, 10)
+    assert h["U"][0] == pytest.approx(o_ref["U"][9], rel=1e-10, abs=1e-10)
