@@ -225,11 +225,12 @@ typedef struct {
     int32_t force_block;    /* threads per workgroup of the force pass: 64..1024, multiple of 64 */
     int32_t nl_block;       /* threads per workgroup of the list build: 64..1024, multiple of 64;
                                0 = automatic (a lane per home atom of a mean tile, or a wave
-                               per home cell) */
+                               per home cell of the widest tile, at most 16 waves) */
     int32_t tile_cells;     /* cells per tile along x in neighbor-list mode; 0 = enough for
-                               about 80% of the force workgroup's home-atom slots */
-    int32_t stage_cap;      /* atoms a workgroup stages in LDS (0 = 1.5x the mean need); tiles
-                               that hold more read positions from global memory instead */
+                               about 1.25 home atoms per lane group of the force workgroup */
+    int32_t stage_cap;      /* atoms a workgroup stages in LDS (0 = 1.15x the mean need plus
+                               64); tiles that hold more read positions from global memory
+                               instead */
     int32_t integrate_grid; /* 1024-thread workgroups of the per-atom kernels (integration,
                                observables): 1..4096; 0 = 256 */
     int32_t nl_method;      /* list build: MD_NL_LANES (one lane per home atom, for sparse

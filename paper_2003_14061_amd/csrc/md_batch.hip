@@ -117,13 +117,8 @@ md_status upload(md_batch* b)
     for (int r = 0; r < R; ++r) {
         const int nlb = kp[r].nl_block;
         sh.nl_block = nlb > sh.nl_block ? nlb : sh.nl_block;
-    }
-    for (int r = 0; r < R; ++r) {
         if (p0.mode == MD_NEIGHBOR_LIST) {
-            // every replica's list is built with the first replica's method
-            KParams q = kp[r];
-            q.nl_method = sh.nl_method;
-            const size_t a = nl_lds_bytes(q, sh.nl_block), f = force_lds_bytes(kp[r]);
+            const size_t a = nl_lds_bytes(kp[r]), f = force_lds_bytes(kp[r]);
             sh.nl_lds = a > sh.nl_lds ? a : sh.nl_lds;
             sh.force_lds = f > sh.force_lds ? f : sh.force_lds;
         }

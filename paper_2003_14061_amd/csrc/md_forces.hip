@@ -413,7 +413,7 @@ LaunchShape shape_of(const KParams& p)
     sh.force_lanes = p.force_lanes;
     sh.nl_block = p.nl_block;
     sh.nl_method = p.nl_method;
-    sh.nl_lds = p.mode == MD_NEIGHBOR_LIST ? nl_lds_bytes(p, p.nl_block) : 0;
+    sh.nl_lds = p.mode == MD_NEIGHBOR_LIST ? nl_lds_bytes(p) : 0;
     sh.force_lds = force_lds_bytes(p);
     sh.precision = p.precision;
     sh.reorder = p.reorder;

@@ -240,7 +240,7 @@ void launch_neighbors(const Batch& b, const LaunchShape& sh, int force, hipStrea
 void launch_forces(const Batch& b, const LaunchShape& sh, hipStream_t s);
 void launch_integrate(const Batch& b, const LaunchShape& sh, int phase, int record_every,
                       hipStream_t s);
-size_t nl_lds_bytes(const KParams& p, int block);
+size_t nl_lds_bytes(const KParams& p);
 size_t force_lds_bytes(const KParams& p);
 int force_blocks(const KParams& p);  // workgroups of the force pass for the current tuning
 // phase 0: kick + drift; 1: kick, record, kick + drift; 2: kick, record

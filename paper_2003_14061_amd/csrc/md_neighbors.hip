@@ -41,7 +41,7 @@ __device__ __forceinline__ double readlane_f64(double v, int lane)
 }
 
 // LDS bytes of the list build: the staged tile.
-size_t nl_lds_bytes(const KParams& p, int) { return stage_bytes(p.scap, p.kx_max); }
+size_t nl_lds_bytes(const KParams& p) { return stage_bytes(p.scap, p.kx_max); }
 
 // One home cell q of the tile, by one wave.  The candidates (the 9 windows
 // of cells q-1..q+1 of every staged row, concatenated, in canonical order)
