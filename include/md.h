@@ -50,16 +50,19 @@ typedef enum {
     MD_ERR_NONFINITE = -4,      /* a force or energy was not finite */
     MD_ERR_HIP = -5,            /* a HIP runtime call failed */
     MD_ERR_NOT_BOUND = -6,      /* md_bind has not been called */
-    MD_ERR_STATE = -7           /* call out of order (e.g. step before forces) */
+    MD_ERR_STATE = -7,          /* call out of order (e.g. step before forces) */
+    MD_ERR_LAYER_OVERFLOW = -8  /* a cell held more atoms than the layer matrix has layers
+                                   (MD_PIPE_LAYERS) */
 } md_status;
 
 enum { MD_LJ_SHIFTED = 0, MD_LJ_TRUNC = 1 };      /* potential */
 enum { MD_FP64 = 0, MD_FP32_MIXED = 1 };          /* precision */
 enum { MD_CELLS_ONLY = 0, MD_NEIGHBOR_LIST = 1 }; /* mode */
+enum { MD_PIPE_TILED = 0, MD_PIPE_LAYERS = 1 };   /* pipeline */
 enum { MD_NL_AUTO = 0, MD_NL_LANES = 1, MD_NL_CELL_WAVES = 2 }; /* md_tuning.nl_method */
 
 /* Device flag bits (md_observables.flags). */
-enum { MD_FLAG_NL_OVERFLOW = 1, MD_FLAG_NONFINITE = 2 };
+enum { MD_FLAG_NL_OVERFLOW = 1, MD_FLAG_NONFINITE = 2, MD_FLAG_LAYER_OVERFLOW = 4 };
 
 /* System and method parameters, copied by md_init.  Lengths in the units of
  * sigma's length, energies in eps's units. */
@@ -89,6 +92,16 @@ typedef struct {
                             (section 4.1, factor (1)); 0: never permute */
     int32_t block;       /* threads per workgroup for per-atom kernels, a multiple of 64
                             in [64, 1024]; 0 = 256 */
+    int32_t pipeline;    /* MD_PIPE_TILED (default): LDS-staged tiles, 16-bit list entries;
+                            MD_PIPE_LAYERS: the paper's own steps as it lays them out
+                            (section 2.3), one thread per atom throughout: an atomic layer
+                            index per atom (N2), the dense cell-by-layer matrix (N3-N4),
+                            the neighbor matrix W of 32-bit atom indices read in rows
+                            (N5) and the force pass gathering partners from memory (F1);
+                            within a cell the atoms follow the order of the atomics, so
+                            the list order is not reproducible, its content is.
+                            Requires MD_NEIGHBOR_LIST, newton3 = 0, reorder = 0; not in
+                            batches or trajectory mode */
 } md_params;
 
 /* Device buffers supplied by the caller (all device pointers). */
@@ -107,6 +120,8 @@ typedef struct {
     int32_t nl_capacity; /* list rows */
     int32_t n_pad;       /* row pitch of the list, n rounded up to 64 */
     double  cell_width;  /* L / nc */
+    int32_t n_layers;    /* layers per cell of the layer matrix (MD_PIPE_LAYERS; else 0) */
+    int32_t pad;
 } md_grid;
 
 /* Results of md_reduce.  Energies are totals over the system. */
@@ -143,10 +158,15 @@ enum {
     MD_ARR_NL = 3,         /* uint16[cap][n_pad] in 4-entry chunks: the m-th neighbor of slot k
                               is 16-bit word m%4 of 8-byte chunk (m/4)*n_pad + k; the word holds
                               the neighbor's index among its tile's staged atoms (13 bits) and
-                              its periodic wrap bits (3 bits); md_export_neighbors decodes it */
+                              its periodic wrap bits (3 bits); md_export_neighbors decodes it.
+                              MD_PIPE_LAYERS: int32[cap][n_pad], entry m*n_pad + k the m-th
+                              neighbor of atom k */
     MD_ARR_NL_COUNT = 4,   /* int32[n]     list length per slot */
     MD_ARR_XREF = 5,       /* double[3][n] positions at the last list build */
-    MD_ARR_COUNT_ = 6
+    MD_ARR_LAYERS = 6,     /* int32[nc^3][n_layers] layer matrix: the atom in each layer of
+                              each cell (MD_PIPE_LAYERS only) */
+    MD_ARR_LAYER_COUNT = 7,/* int32[nc^3] atoms per cell, i.e. layers in use (MD_PIPE_LAYERS) */
+    MD_ARR_COUNT_ = 8
 };
 
 /* md_init: validate parameters, derive the cell grid and list capacity.

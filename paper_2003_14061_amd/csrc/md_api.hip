@@ -32,6 +32,7 @@ extern "C" const char* md_status_str(int32_t st)
         case MD_ERR_HIP: return "HIP runtime error";
         case MD_ERR_NOT_BOUND: return "buffers not bound (call md_bind)";
         case MD_ERR_STATE: return "call out of order";
+        case MD_ERR_LAYER_OVERFLOW: return "layer matrix overflow: a cell held more atoms than layers";
         default: return "unknown status";
     }
 }
@@ -72,7 +73,7 @@ static void plan_tiles(md_ctx* c, int cells)
     aux = (aux < k.scap ? aux : k.scap) / 64 * 64;
     k.scap_aux = aux < 64 ? 64 : aux;
     c->tile_cells = cells;
-    k.nblk_force = force_blocks(k);
+    k.nblk_force = k.pipeline == MD_PIPE_LAYERS ? (k.n + k.block - 1) / k.block : force_blocks(k);
     // list build: a lane per home atom of a mean tile (25% spare), or a
     // wave per home cell of the widest tile (at most 16 waves, each then
     // taking several cells)
@@ -109,6 +110,9 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
         (p.precision != MD_FP64 && p.precision != MD_FP32_MIXED) ||
         (p.mode != MD_CELLS_ONLY && p.mode != MD_NEIGHBOR_LIST) ||
         (p.newton3 != 0 && p.newton3 != 1) || (p.newton3 && p.mode != MD_NEIGHBOR_LIST) ||
+        (p.pipeline != MD_PIPE_TILED && p.pipeline != MD_PIPE_LAYERS) ||
+        (p.pipeline == MD_PIPE_LAYERS &&
+         (p.mode != MD_NEIGHBOR_LIST || p.newton3 != 0 || p.reorder != 0)) ||
         p.nl_capacity < 0 || (p.reorder != 0 && p.reorder != 1) || p.block % 64 != 0 ||
         p.block < 64 || p.block > 1024)
         return MD_ERR_ARG;
@@ -145,6 +149,14 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
     c->geo.nl_capacity = cap;
     c->geo.n_pad = npad;
     c->geo.cell_width = p.L / nc;
+    // layers per cell of the layer matrix: the mean occupancy plus six of its
+    // Poisson standard deviations plus 8 (overflow is latched, not silent)
+    int n_layers = 0;
+    if (p.pipeline == MD_PIPE_LAYERS) {
+        const double occ = (double)p.n_atoms / ((double)nc * nc * nc);
+        n_layers = (int)ceil(occ + 6.0 * sqrt(occ) + 8.0);
+    }
+    c->geo.n_layers = n_layers;
 
     // workspace layout
     const int64_t ncell = (int64_t)nc * nc * nc;
@@ -154,7 +166,10 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
     b[R_CELL_COUNT] = sizeof(int32_t) * ncell;
     b[R_CELL_START] = sizeof(int32_t) * (ncell + 1);
     b[R_CELL_OF] = b[R_SLOT] = b[R_ORDER] = b[R_TMP] = sizeof(int32_t) * n;
-    b[R_NL] = sizeof(uint16_t) * (size_t)cap * npad;
+    const bool layers = p.pipeline == MD_PIPE_LAYERS;
+    b[R_NL] = layers ? 0 : sizeof(uint16_t) * (size_t)cap * npad;
+    b[R_LAYERS] = sizeof(int32_t) * (size_t)ncell * n_layers;
+    b[R_W32] = layers ? sizeof(int32_t) * (size_t)cap * npad : 0;
     b[R_NL_COUNT] = sizeof(int32_t) * npad;
     b[R_XR] = b[R_YR] = b[R_ZR] = nl ? sizeof(double) * n : 0;
     const size_t perm = p.reorder ? 1 : 0;
@@ -183,6 +198,8 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
     k.mode = p.mode;
     k.reorder = p.reorder;
     k.newton3 = p.newton3;
+    k.pipeline = p.pipeline;
+    k.n_layers = n_layers;
     k.L = p.L;
     k.invL = 1.0 / p.L;
     k.inv_w = (double)nc / p.L;
@@ -237,13 +254,32 @@ extern "C" md_status md_layout(const md_ctx* c, int32_t which, size_t* offset, s
 {
     if (!c || !offset || !count) return MD_ERR_ARG;
     const int64_t n = c->prm.n_atoms;
+    const bool layers = c->prm.pipeline == MD_PIPE_LAYERS;
     switch (which) {
         case MD_ARR_CELL_OF: *offset = c->off[R_CELL_OF]; *count = n; break;
-        case MD_ARR_CELL_START: *offset = c->off[R_CELL_START]; *count = c->geo.n_cells + 1; break;
-        case MD_ARR_CELL_ATOMS: *offset = c->off[R_ORDER]; *count = n; break;
+        case MD_ARR_CELL_START:
+            if (layers) return MD_ERR_ARG;
+            *offset = c->off[R_CELL_START];
+            *count = c->geo.n_cells + 1;
+            break;
+        case MD_ARR_CELL_ATOMS:
+            if (layers) return MD_ERR_ARG;
+            *offset = c->off[R_ORDER];
+            *count = n;
+            break;
         case MD_ARR_NL:
-            *offset = c->off[R_NL];
+            *offset = c->off[layers ? R_W32 : R_NL];
             *count = (size_t)c->geo.nl_capacity * c->geo.n_pad;
+            break;
+        case MD_ARR_LAYERS:
+            if (!layers) return MD_ERR_ARG;
+            *offset = c->off[R_LAYERS];
+            *count = (size_t)c->geo.n_cells * c->geo.n_layers;
+            break;
+        case MD_ARR_LAYER_COUNT:
+            if (!layers) return MD_ERR_ARG;
+            *offset = c->off[R_CELL_COUNT];
+            *count = c->geo.n_cells;
             break;
         case MD_ARR_NL_COUNT: *offset = c->off[R_NL_COUNT]; *count = n; break;
         case MD_ARR_XREF:
@@ -292,6 +328,8 @@ extern "C" md_status md_bind(md_ctx* c, const md_buffers* bf, void* stream)
     k.sfy = static_cast<double*>(at(R_SFY));
     k.sfz = static_cast<double*>(at(R_SFZ));
     k.sid = static_cast<int32_t*>(at(R_SID));
+    k.layers = static_cast<int32_t*>(at(R_LAYERS));
+    k.w32 = static_cast<int32_t*>(at(R_W32));
     k.scell = static_cast<int32_t*>(at(R_SCELL));
     k.fpart = static_cast<double*>(at(R_FPART));
     k.ipart = static_cast<double*>(at(R_IPART));
@@ -309,11 +347,36 @@ extern "C" md_status md_bind(md_ctx* c, const md_buffers* bf, void* stream)
     return launched();
 }
 
+// The stages of either pipeline.
+static void cells_any(const KParams& k, int force, hipStream_t s)
+{
+    if (k.pipeline == MD_PIPE_LAYERS)
+        launch_layer_cells(k, force, s);
+    else
+        launch_cells(k, force, s);
+}
+
+static void neighbors_any(const KParams& k, int force, hipStream_t s)
+{
+    if (k.pipeline == MD_PIPE_LAYERS)
+        launch_layer_nl(k, force, s);
+    else
+        launch_neighbors(k, force, s);
+}
+
+static void forces_any(const KParams& k, hipStream_t s)
+{
+    if (k.pipeline == MD_PIPE_LAYERS)
+        launch_layer_forces(k, s);
+    else
+        launch_forces(k, s);
+}
+
 extern "C" md_status md_build_cells(md_ctx* c)
 {
     if (!c) return MD_ERR_ARG;
     if (!c->bound) return MD_ERR_NOT_BOUND;
-    launch_cells(c->kp, 1, c->stream);
+    cells_any(c->kp, 1, c->stream);
     c->cells_ok = true;
     c->nl_ok = false;
     c->forces_ok = false;
@@ -326,7 +389,7 @@ extern "C" md_status md_build_neighbors(md_ctx* c)
     if (!c->bound) return MD_ERR_NOT_BOUND;
     if (c->prm.mode != MD_NEIGHBOR_LIST) return MD_ERR_ARG;
     if (!c->cells_ok) return MD_ERR_STATE;
-    launch_neighbors(c->kp, 1, c->stream);
+    neighbors_any(c->kp, 1, c->stream);
     c->nl_ok = true;
     return launched();
 }
@@ -334,7 +397,7 @@ extern "C" md_status md_build_neighbors(md_ctx* c)
 static void timed_forces(md_ctx* c)
 {
     if (!c->timing) {
-        launch_forces(c->kp, c->stream);
+        forces_any(c->kp, c->stream);
         return;
     }
     hipEvent_t ev[2];
@@ -347,7 +410,7 @@ static void timed_forces(md_ctx* c)
         }
     }
     (void)hipEventRecord(ev[0], c->stream);
-    launch_forces(c->kp, c->stream);
+    forces_any(c->kp, c->stream);
     (void)hipEventRecord(ev[1], c->stream);
     c->ev_pending.push_back(ev[0]);
     c->ev_pending.push_back(ev[1]);
@@ -376,7 +439,10 @@ extern "C" md_status md_export_neighbors(md_ctx* c, int32_t* dst)
     if (!c->bound) return MD_ERR_NOT_BOUND;
     if (c->prm.mode != MD_NEIGHBOR_LIST) return MD_ERR_ARG;
     if (!c->nl_ok) return MD_ERR_STATE;
-    launch_nl_export(c->kp, dst, c->stream);
+    if (c->kp.pipeline == MD_PIPE_LAYERS)
+        launch_layer_export(c->kp, dst, c->stream);
+    else
+        launch_nl_export(c->kp, dst, c->stream);
     return launched();
 }
 
@@ -400,8 +466,8 @@ extern "C" md_status md_step(md_ctx* c, int32_t n_steps, int32_t record_every)
     const bool nl = c->prm.mode == MD_NEIGHBOR_LIST;
     for (int32_t s = 0; s < n_steps; ++s) {
         launch_integrate(k, s == 0 ? 0 : 1, record_every, c->stream);
-        launch_cells(k, 0, c->stream);
-        if (nl) launch_neighbors(k, 0, c->stream);
+        cells_any(k, 0, c->stream);
+        if (nl) neighbors_any(k, 0, c->stream);
         timed_forces(c);
         if (c->timing && c->ev_pending.size() >= 8192) {
             md_status st = fold_timing(c);
@@ -440,6 +506,7 @@ extern "C" md_status md_reduce(md_ctx* c, md_observables* out)
     out->max_occupancy = d.max_occ;
     out->max_nl = d.max_nl;
     out->flags = d.flags;
+    if (d.flags & MD_FLAG_LAYER_OVERFLOW) return MD_ERR_LAYER_OVERFLOW;
     if (d.flags & MD_FLAG_NL_OVERFLOW) return MD_ERR_NL_OVERFLOW;
     if (d.flags & MD_FLAG_NONFINITE) return MD_ERR_NONFINITE;
     return MD_OK;
@@ -501,7 +568,8 @@ static md_status traj_check(md_ctx* c, const md_traj_params* tp, void* ws, TrajL
 {
     if (!c || !tp || !ws || !traj_layout(c, tp, L)) return MD_ERR_ARG;
     if (!c->bound) return MD_ERR_NOT_BOUND;
-    if (c->prm.mode != MD_NEIGHBOR_LIST || c->prm.reorder != 0 || c->prm.newton3 != 0)
+    if (c->prm.mode != MD_NEIGHBOR_LIST || c->prm.reorder != 0 || c->prm.newton3 != 0 ||
+        c->prm.pipeline != MD_PIPE_TILED)
         return MD_ERR_ARG;
     if (((uintptr_t)ws) % kAlign != 0) return MD_ERR_ARG;
     if (tp->n_bins > 0 && tp->gr_rmax + 3.0 * tp->gr_width > c->prm.r_cut + c->prm.skin)

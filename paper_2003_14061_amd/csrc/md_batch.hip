@@ -193,7 +193,7 @@ extern "C" md_status md_batch_init(const md_params* params, int32_t n_replicas, 
         const md_params& p = params[r];
         const md_params& p0 = params[0];
         if (p.precision != p0.precision || p.mode != p0.mode || p.reorder != p0.reorder ||
-            p.newton3 != p0.newton3 || p.block != p0.block) {
+            p.newton3 != p0.newton3 || p.block != p0.block || p.pipeline != MD_PIPE_TILED) {
             md_batch_destroy(b);
             return MD_ERR_ARG;
         }

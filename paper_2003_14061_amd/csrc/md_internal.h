@@ -38,6 +38,7 @@ struct DevState {
 struct KParams {
     // sizes
     int32_t n, npad, nc, ncell, cap, potential, precision, mode, reorder, newton3;
+    int32_t pipeline, n_layers;  // MD_PIPE_*; layers per cell of the layer matrix
     // constants (all formed once on the host)
     double L, invL, inv_w, rc2, rl2, sig2, eps2, eps48, half_shift, hdt, dt, disp_thr2, mass;
     double ushift;          // half_shift / eps2: the shift in the units of the u sums
@@ -55,6 +56,8 @@ struct KParams {
     double *xr, *yr, *zr;
     double *sx, *sy, *sz, *svx, *svy, *svz, *sfx, *sfy, *sfz;  // permutation scratch
     int32_t *sid, *scell;
+    int32_t *layers;  // layer matrix [ncell][n_layers] (MD_PIPE_LAYERS)
+    int32_t *w32;     // neighbor matrix, 32-bit atom indices [cap][npad] (MD_PIPE_LAYERS)
     double *fpart;    // force-pass partials [nblk_force][2]: U, W
     double *ipart;    // per-atom kernel partials [int_grid][8]
     md_record* hist;
@@ -162,6 +165,7 @@ __device__ __forceinline__ KParams global_view(const KParams& q)
     p.sid = as_global(q.sid); p.scell = as_global(q.scell);
     p.fpart = as_global(q.fpart); p.ipart = as_global(q.ipart);
     p.hist = as_global(q.hist);
+    p.layers = as_global(q.layers); p.w32 = as_global(q.w32);
     return p;
 }
 
@@ -227,6 +231,10 @@ void launch_gr(const KParams& p, const GrArgs& g, hipStream_t s);
 void launch_gr_grad(const KParams& p, const GrArgs& g, hipStream_t s);
 void launch_traj_ubar(const KParams& p, int32_t n_steps, double* out, hipStream_t s);
 void launch_fill(double* a, size_t n, double v, hipStream_t s);
+void launch_layer_cells(const KParams& p, int force, hipStream_t s);
+void launch_layer_nl(const KParams& p, int force, hipStream_t s);
+void launch_layer_forces(const KParams& p, hipStream_t s);
+void launch_layer_export(const KParams& p, int32_t* out, hipStream_t s);
 
 void launch_clear(const KParams& p, hipStream_t s);
 void launch_cells(const KParams& p, int force, hipStream_t s);

@@ -24,7 +24,9 @@ MD_LJ_SHIFTED, MD_LJ_TRUNC = 0, 1
 MD_FP64, MD_FP32_MIXED = 0, 1
 MD_CELLS_ONLY, MD_NEIGHBOR_LIST = 0, 1
 MD_NL_AUTO, MD_NL_LANES, MD_NL_CELL_WAVES = 0, 1, 2
-MD_ARR_CELL_OF, MD_ARR_CELL_START, MD_ARR_CELL_ATOMS, MD_ARR_NL, MD_ARR_NL_COUNT, MD_ARR_XREF = range(6)
+MD_PIPE_TILED, MD_PIPE_LAYERS = 0, 1
+(MD_ARR_CELL_OF, MD_ARR_CELL_START, MD_ARR_CELL_ATOMS, MD_ARR_NL, MD_ARR_NL_COUNT, MD_ARR_XREF,
+ MD_ARR_LAYERS, MD_ARR_LAYER_COUNT) = range(8)
 
 EXPORTS = ("md_init", "md_workspace_bytes", "md_geometry", "md_layout", "md_bind",
            "md_build_cells", "md_build_neighbors", "md_forces", "md_step", "md_reduce",
@@ -48,7 +50,8 @@ class Params(C.Structure):
                 ("eps", C.c_double), ("sigma", C.c_double), ("mass", C.c_double),
                 ("r_cut", C.c_double), ("skin", C.c_double), ("dt", C.c_double),
                 ("precision", C.c_int32), ("mode", C.c_int32), ("newton3", C.c_int32),
-                ("nl_capacity", C.c_int32), ("reorder", C.c_int32), ("block", C.c_int32)]
+                ("nl_capacity", C.c_int32), ("reorder", C.c_int32), ("block", C.c_int32),
+                ("pipeline", C.c_int32)]
 
 
 class Buffers(C.Structure):
@@ -58,7 +61,8 @@ class Buffers(C.Structure):
 
 class Grid(C.Structure):
     _fields_ = [("nc", C.c_int32), ("n_cells", C.c_int32), ("nl_capacity", C.c_int32),
-                ("n_pad", C.c_int32), ("cell_width", C.c_double)]
+                ("n_pad", C.c_int32), ("cell_width", C.c_double), ("n_layers", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class Tuning(C.Structure):
@@ -278,7 +282,8 @@ class Simulation:
 
     def __init__(self, pos, vel, L, *, r_cut, dt, skin=0.3, eps=1.0, sigma=1.0, mass=1.0,
                  shifted=True, precision="fp64", neighbor_list=True, reorder=None,
-                 newton3=False, nl_capacity=0, block=256, device="cuda", stream=None):
+                 newton3=False, nl_capacity=0, block=256, pipeline="tiled", device="cuda",
+                 stream=None):
         import torch
 
         if not torch.cuda.is_available():
@@ -289,14 +294,15 @@ class Simulation:
         if not isinstance(vel, torch.Tensor):
             vel = np.asarray(vel, dtype=np.float64)
         n = pos.shape[0]
+        pipe = {"tiled": MD_PIPE_TILED, "layers": MD_PIPE_LAYERS}[pipeline]
         if reorder is None:
-            reorder = bool(neighbor_list)
+            reorder = bool(neighbor_list) and pipe == MD_PIPE_TILED
         self.params = Params(int(n), MD_LJ_SHIFTED if shifted else MD_LJ_TRUNC, float(L),
                              float(eps), float(sigma), float(mass), float(r_cut), float(skin),
                              float(dt), MD_FP64 if precision == "fp64" else MD_FP32_MIXED,
                              MD_NEIGHBOR_LIST if neighbor_list else MD_CELLS_ONLY,
                              int(bool(newton3)), int(nl_capacity), int(bool(reorder)),
-                             int(block))
+                             int(block), pipe)
         self.n = n
         self.L = float(L)
         self.device = torch.device(device)
@@ -467,6 +473,16 @@ class Simulation:
         cell_of, cell_start, cell_atoms, ids = self._host(co, cs, ca, self.id)
         return {"cell_of": cell_of, "cell_start": cell_start, "cell_atoms": cell_atoms,
                 "id": ids}
+
+    def layers(self):
+        """The layer matrix [n_cells, n_layers] and the atoms per cell
+        (MD_PIPE_LAYERS), host copies."""
+        import torch
+
+        h = self.ws_array(MD_ARR_LAYERS, torch.int32)
+        c = self.ws_array(MD_ARR_LAYER_COUNT, torch.int32)
+        h_h, c_h = self._host(h, c)
+        return h_h.reshape(self.grid.n_cells, self.grid.n_layers), c_h
 
     def nl_counts(self):
         """List length per slot (host copy)."""

@@ -44,7 +44,7 @@ def params(**kw):
                      base["dt"], base.get("precision", md.MD_FP64),
                      base.get("mode", md.MD_NEIGHBOR_LIST), base.get("newton3", 0),
                      base.get("cap", 0),
-                     base.get("reorder", 1), base.get("block", 256))
+                     base.get("reorder", 1), base.get("block", 256), base.get("pipeline", 0))
 
 
 def test_geometry_of_the_workloads():
@@ -85,6 +85,8 @@ def test_geometry_of_the_workloads():
     dict(n=0), dict(r_cut=-1.0), dict(dt=0.0), dict(skin=-0.1), dict(block=100),
     dict(block=2048), dict(precision=7), dict(mode=3), dict(reorder=2), dict(cap=-1),
     dict(newton3=2), dict(newton3=-1), dict(newton3=1, mode=md.MD_CELLS_ONLY),
+    dict(pipeline=2), dict(pipeline=1, reorder=1), dict(pipeline=1, reorder=0, newton3=1),
+    dict(pipeline=1, reorder=0, mode=md.MD_CELLS_ONLY),
 ])
 def test_invalid_parameters_are_rejected(bad):
     ctx = C.c_void_p()
@@ -96,6 +98,40 @@ def test_third_law_variant_is_accepted_with_a_list():
     for prec in (md.MD_FP64, md.MD_FP32_MIXED):
         ctx = md.md_init(params(n=32000, rho=0.8, r_cut=2.5, newton3=1, precision=prec))
         md.md_destroy(ctx)
+
+
+def test_layer_pipeline_geometry_and_arrays():
+    """The paper's layer-matrix pipeline: layers per cell from the mean
+    occupancy, a 32-bit neighbor matrix in place of the 16-bit one, and the
+    layer arrays exposed through md_layout only in that pipeline."""
+    for n, rho, rc in ((2048000, 0.8442, 2.5), (256000, 0.8, 2 ** (1 / 6))):
+        p = params(n=n, rho=rho, r_cut=rc, reorder=0, pipeline=1)
+        ctx = md.md_init(p)
+        tiled = md.md_init(params(n=n, rho=rho, r_cut=rc, reorder=0))
+        try:
+            g = md.md_geometry(ctx)
+            occ = n / g.n_cells
+            assert g.n_layers == math.ceil(occ + 6 * math.sqrt(occ) + 8)
+            assert md.md_geometry(tiled).n_layers == 0
+            off, cnt = md.md_layout(ctx, md.MD_ARR_LAYERS)
+            assert cnt == g.n_cells * g.n_layers and off % 256 == 0
+            off, cnt = md.md_layout(ctx, md.MD_ARR_LAYER_COUNT)
+            assert cnt == g.n_cells
+            off, cnt = md.md_layout(ctx, md.MD_ARR_NL)
+            assert cnt == g.nl_capacity * g.n_pad
+            for which in (md.MD_ARR_CELL_START, md.MD_ARR_CELL_ATOMS):
+                with pytest.raises(md.MDError):
+                    md.md_layout(ctx, which)
+            for which in (md.MD_ARR_LAYERS, md.MD_ARR_LAYER_COUNT):
+                with pytest.raises(md.MDError):
+                    md.md_layout(tiled, which)
+            # the 32-bit matrix is twice the 16-bit one
+            wl = md.md_workspace_bytes(ctx) - md.md_workspace_bytes(tiled)
+            assert wl >= 2 * g.nl_capacity * g.n_pad + 4 * g.n_cells * g.n_layers
+        finally:
+            md.md_destroy(ctx)
+            md.md_destroy(tiled)
+    assert md.status_str(-8).startswith("layer matrix overflow")
 
 
 def test_box_too_small():
