@@ -26,6 +26,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6   # MI355X dense FP64 vector
 FP32_PEAK_TFS = 157.3  # MI355X FP32 vector
 FORCE_SOURCES = ("paper_2003_14061_amd/csrc/md_forces.hip", "paper_2003_14061_amd/csrc/md_tiles.h",
+                 "paper_2003_14061_amd/csrc/md_pair.h",
                  "paper_2003_14061_amd/csrc/md_device.h", "paper_2003_14061_amd/csrc/md_internal.h")
 TRAFFIC_FILE = "profiles/k_forces_tiles_lj_2048k_traffic.txt"
 
@@ -42,6 +43,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--no-newton3", action="store_true",
                     help="skip the third-law (half list, atomic) variant")
+    ap.add_argument("--no-layers", action="store_true",
+                    help="skip the paper's layer-matrix pipeline (thread-per-atom kernels)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward ratio of the differentiable run")
     ap.add_argument("--no-main", action="store_true",
@@ -95,14 +98,14 @@ def measured_traffic(n_atoms, precision):
         return None
 
 
-def run_gpu(w, precision, steps, warmup, newton3=False):
+def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled"):
     import torch
 
     from paper_2003_14061_amd import md
 
     sim = md.Simulation(w.pos, w.vel, w.L, r_cut=w.r_cut, skin=w.skin, dt=w.dt,
                         shifted=w.shifted, precision=precision, neighbor_list=w.use_nl,
-                        newton3=newton3)
+                        newton3=newton3, pipeline=pipeline)
     sim.prepare()
     sim.step(warmup)
     o0 = sim.reduce()
@@ -355,6 +358,11 @@ def main():
         mixed = run_gpu(w, "fp32", args.steps, args.warmup)
         print(f"[bench] fp32-mixed done: {mixed['value']:.3e} atom-steps/s", file=sys.stderr,
               flush=True)
+    lay = None
+    if not args.no_layers:
+        lay = run_gpu(w, "fp64", args.steps, args.warmup, pipeline="layers")
+        print(f"[bench] fp64 layer-matrix pipeline done: {lay['value']:.3e} atom-steps/s",
+              file=sys.stderr, flush=True)
     n3 = None
     if not args.no_newton3:
         n3 = run_gpu(w, "fp64", args.steps, args.warmup, newton3=True)
@@ -406,6 +414,14 @@ def main():
                              "energy_drift_per_atom": mixed["energy_drift_per_atom"],
                              "force_ms_avg": round(mixed["force_ms_avg"], 5),
                              "speedup_vs_fp64": round(mixed["value"] / fp64["value"], 3)}
+    if lay is not None:
+        out["paper_layers_fp64"] = {
+            "value": round(lay["value"], 1), "ms_per_step": round(lay["ms_per_step"], 5),
+            "force_ms_avg": round(lay["force_ms_avg"], 5), "rebuilds": lay["rebuilds"],
+            "energy_drift_per_atom": lay["energy_drift_per_atom"],
+            "tiled_speedup": round(fp64["value"] / lay["value"], 3),
+            "kernels": "k_layer_clear, k_layer_assign, k_layer_nl, k_layer_forces: one thread "
+                       "per atom, 32-bit neighbor matrix, partners gathered from HBM"}
     if n3 is not None:
         out["newton3_fp64"] = {"value": round(n3["value"], 1),
                                "ms_per_step": round(n3["ms_per_step"], 5),
