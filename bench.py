@@ -45,6 +45,8 @@ def parse():
                     help="skip the third-law (half list, atomic) variant")
     ap.add_argument("--no-layers", action="store_true",
                     help="skip the paper's layer-matrix pipeline (thread-per-atom kernels)")
+    ap.add_argument("--no-allpairs", action="store_true",
+                    help="skip the all-pairs comparison on the 4000-atom WCA system")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward ratio of the differentiable run")
     ap.add_argument("--no-main", action="store_true",
@@ -98,7 +100,7 @@ def measured_traffic(n_atoms, precision):
         return None
 
 
-def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled"):
+def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled", detail=True):
     import torch
 
     from paper_2003_14061_amd import md
@@ -120,6 +122,14 @@ def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled"):
     sim.set_timing(False)
     o1 = sim.reduce()
     e1 = (o1["U"] + o1["K"]) / w.n
+    if not detail:
+        wall = t1 - t0
+        res = {"value": w.n * steps / wall, "ms_per_step": 1e3 * wall / steps,
+               "force_ms_avg": f_ms / max(f_launches, 1), "energy_drift_per_atom": e1 - e0,
+               "rebuilds": int(o1["n_rebuilds"] - o0["n_rebuilds"])}
+        del sim
+        torch.cuda.synchronize()
+        return res
     cnt = sim.nl_counts()
     mean_nl = float(cnt[: w.n].mean())
     mean_in_range = in_range_pairs(sim, w)
@@ -176,6 +186,60 @@ def force_error_fp32(w, pos):
     scale = float(np.linalg.norm(f["fp64"], axis=1).max())
     return {"max_per_atom_rel_to_max_force": float(d.max() / scale),
             "normwise": float(np.linalg.norm(f["fp32"] - f["fp64"]) / np.linalg.norm(f["fp64"]))}
+
+
+# FP64 lane operations the all-pairs test needs per ordered pair: three
+# differences, the minimum image (multiply, round, multiply, subtract) per
+# coordinate, the squared length (a multiply and two fused multiply-adds) and
+# the cutoff compare; a fused multiply-add counts as one operation.
+ALLPAIRS_OPS_PER_PAIR = 3 + 3 * 4 + 3 + 1
+# FP64 lane-operation issue rate: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz
+FP64_LANE_OPS_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def run_allpairs():
+    """The paper's all-pairs comparison (section 4.2, alternative (2); it
+    quotes N=4096 soft spheres): WCA, rho 0.8, T 1, dt 0.005 on N = 4000
+    (10^3 FCC), 32 000 and 256 000.  The all-pairs pipeline against the tiled
+    list pipeline and the layer-matrix pipeline (skin 0.3) on the same
+    system, FP64.  The all-pairs force time per launch covers its two kernels
+    (the pair pass and, with several partner chunks, the combine)."""
+    from paper_2003_14061_amd import inputs
+
+    def leg(r):
+        return {"value": round(r["value"], 1), "ms_per_step": round(r["ms_per_step"], 6),
+                "force_ms_avg": round(r["force_ms_avg"], 6)}
+
+    out = []
+    for n, steps, warmup in ((4000, 2000, 100), (32000, 200, 20), (256000, 6, 2)):
+        w_ap = inputs.preset("wca_4000", n=n).materialize()
+        w_nl = inputs.preset("wca_4000", n=n, use_nl=True).materialize()
+        ap = run_gpu(w_ap, "fp64", steps, warmup, pipeline="allpairs", detail=False)
+        tl = run_gpu(w_nl, "fp64", steps, warmup, detail=False)
+        ly = run_gpu(w_nl, "fp64", steps, warmup, pipeline="layers", detail=False)
+        t = ap["force_ms_avg"] * 1e-3
+        ops = ALLPAIRS_OPS_PER_PAIR * n * (n - 1) / t / 1e12
+        out.append({
+            "n": n, "steps": steps,
+            "allpairs": dict(leg(ap), pairs_per_s=round(n * (n - 1) / t, 1),
+                             roofline={"bound": "alu",
+                                       "kernels": "k_forces_allpairs + k_ap_combine",
+                                       "achieved": round(ops, 3),
+                                       "peak": round(FP64_LANE_OPS_PEAK_TOPS, 2),
+                                       "unit": "TOP/s (FP64 lane operations)",
+                                       "frac": round(ops / FP64_LANE_OPS_PEAK_TOPS, 4),
+                                       "ops_per_pair": ALLPAIRS_OPS_PER_PAIR,
+                                       "units_per_launch": n * (n - 1)}),
+            "tiled_list": leg(tl),
+            "layer_matrix": leg(ly),
+            "allpairs_slowdown_vs_tiled": round(tl["value"] / ap["value"], 2),
+            "allpairs_slowdown_vs_layers": round(ly["value"] / ap["value"], 2),
+        })
+        print(f"[bench] all-pairs N={n}: {ap['value']:.3e} atom-steps/s, "
+              f"{tl['value'] / ap['value']:.2f}x slower than the tiled list",
+              file=sys.stderr, flush=True)
+    return {"workload": "WCA (LJ cut and shifted at r_c=2^(1/6) sigma), FCC, rho=0.8, T=1, "
+                        "dt=0.005; list pipelines with skin 0.3", "by_n": out}
 
 
 def run_adjoint(precision, repeats=3):
@@ -437,6 +501,8 @@ def main():
         out["batched_ensemble"] = dict(bt, workload="64 WCA replicas, N~U[500,32000], "
                                        "rho~U[0.6,0.9], T=1, dt=0.005, skin 0.3, FP32-mixed, "
                                        "one HIP graph launch per 500 steps")
+    if not args.no_allpairs:
+        out["paper_allpairs"] = run_allpairs()
     if not args.no_adjoint:
         adj = {}
         for prec, key in (("fp64", "fp64"), ("fp32", "fp32_mixed")):

@@ -58,7 +58,7 @@ typedef enum {
 enum { MD_LJ_SHIFTED = 0, MD_LJ_TRUNC = 1 };      /* potential */
 enum { MD_FP64 = 0, MD_FP32_MIXED = 1 };          /* precision */
 enum { MD_CELLS_ONLY = 0, MD_NEIGHBOR_LIST = 1 }; /* mode */
-enum { MD_PIPE_TILED = 0, MD_PIPE_LAYERS = 1 };   /* pipeline */
+enum { MD_PIPE_TILED = 0, MD_PIPE_LAYERS = 1, MD_PIPE_ALLPAIRS = 2 }; /* pipeline */
 enum { MD_NL_AUTO = 0, MD_NL_LANES = 1, MD_NL_CELL_WAVES = 2 }; /* md_tuning.nl_method */
 
 /* Device flag bits (md_observables.flags). */
@@ -101,7 +101,16 @@ typedef struct {
                             within a cell the atoms follow the order of the atomics, so
                             the list order is not reproducible, its content is.
                             Requires MD_NEIGHBOR_LIST, newton3 = 0, reorder = 0; not in
-                            batches or trajectory mode */
+                            batches or trajectory mode.
+                            MD_PIPE_ALLPAIRS: the all-pairs force evaluation the paper
+                            compares against (section 4.2, alternative (2)): every atom
+                            against every other under the minimum image, partner
+                            positions staged through LDS in tiles, no cells and no list;
+                            md_build_cells only folds the positions into [0, L) and the
+                            drift of md_step keeps them there.  Work grows as N^2.
+                            Requires MD_CELLS_ONLY (whose box rule, L >= 3 r_cut, makes
+                            the minimum image unique) and reorder = 0; not in batches or
+                            trajectory mode */
 } md_params;
 
 /* Device buffers supplied by the caller (all device pointers). */
@@ -152,7 +161,8 @@ typedef struct {
 
 /* Array identifiers for md_layout (each lives inside the workspace). */
 enum {
-    MD_ARR_CELL_OF = 0,    /* int32[n]     cell of the atom in slot k (N1) */
+    MD_ARR_CELL_OF = 0,    /* int32[n]     cell of the atom in slot k (N1); the three cell
+                              arrays do not exist under MD_PIPE_ALLPAIRS (MD_ERR_ARG) */
     MD_ARR_CELL_START = 1, /* int32[nc^3+1] first entry of each cell in CELL_ATOMS (N2-N4) */
     MD_ARR_CELL_ATOMS = 2, /* int32[n]     slots grouped by cell, ascending id in a cell */
     MD_ARR_NL = 3,         /* uint16[cap][n_pad] in 4-entry chunks: the m-th neighbor of slot k
@@ -192,7 +202,7 @@ md_status md_bind(md_ctx* ctx, const md_buffers* bufs, void* hip_stream);
 /* md_build_cells (N1-N4, and the reorder): assign every atom to its cell,
  * group the slots by cell with ascending id inside a cell, and, with reorder
  * on, permute positions, velocities, forces and ids into that order.
- * Enqueued. */
+ * MD_PIPE_ALLPAIRS: fold the positions into [0, L) only.  Enqueued. */
 md_status md_build_cells(md_ctx* ctx);
 
 /* md_build_neighbors (N5): for every atom, the other atoms of the 27
@@ -211,9 +221,9 @@ md_status md_build_neighbors(md_ctx* ctx);
 md_status md_export_neighbors(md_ctx* ctx, int32_t* dst);
 
 /* md_forces (F1): per-atom force over the list (or the 27 cells in
- * MD_CELLS_ONLY mode), pairs closer than r_cut, plus per-workgroup partial
- * sums of the potential energy and the virial.  Requires the cells (and
- * list).  Enqueued. */
+ * MD_CELLS_ONLY mode, or every other atom under MD_PIPE_ALLPAIRS), pairs
+ * closer than r_cut, plus per-workgroup partial sums of the potential energy
+ * and the virial.  Requires the cells (and list).  Enqueued. */
 md_status md_forces(md_ctx* ctx);
 
 /* md_step: n_steps leapfrog steps, kick-drift-kick: v += dt/(2m) f; x += dt v;

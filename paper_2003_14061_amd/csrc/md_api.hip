@@ -73,7 +73,12 @@ static void plan_tiles(md_ctx* c, int cells)
     aux = (aux < k.scap ? aux : k.scap) / 64 * 64;
     k.scap_aux = aux < 64 ? 64 : aux;
     c->tile_cells = cells;
-    k.nblk_force = k.pipeline == MD_PIPE_LAYERS ? (k.n + k.block - 1) / k.block : force_blocks(k);
+    if (k.pipeline == MD_PIPE_LAYERS)
+        k.nblk_force = (k.n + k.block - 1) / k.block;
+    else if (k.pipeline == MD_PIPE_ALLPAIRS)
+        k.nblk_force = allpairs_home_blocks(k.n) * k.ap_split;
+    else
+        k.nblk_force = force_blocks(k);
     // list build: a lane per home atom of a mean tile (25% spare), or a
     // wave per home cell of the widest tile (at most 16 waves, each then
     // taking several cells)
@@ -110,9 +115,11 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
         (p.precision != MD_FP64 && p.precision != MD_FP32_MIXED) ||
         (p.mode != MD_CELLS_ONLY && p.mode != MD_NEIGHBOR_LIST) ||
         (p.newton3 != 0 && p.newton3 != 1) || (p.newton3 && p.mode != MD_NEIGHBOR_LIST) ||
-        (p.pipeline != MD_PIPE_TILED && p.pipeline != MD_PIPE_LAYERS) ||
+        (p.pipeline != MD_PIPE_TILED && p.pipeline != MD_PIPE_LAYERS &&
+         p.pipeline != MD_PIPE_ALLPAIRS) ||
         (p.pipeline == MD_PIPE_LAYERS &&
          (p.mode != MD_NEIGHBOR_LIST || p.newton3 != 0 || p.reorder != 0)) ||
+        (p.pipeline == MD_PIPE_ALLPAIRS && (p.mode != MD_CELLS_ONLY || p.reorder != 0)) ||
         p.nl_capacity < 0 || (p.reorder != 0 && p.reorder != 1) || p.block % 64 != 0 ||
         p.block < 64 || p.block > 1024)
         return MD_ERR_ARG;
@@ -157,6 +164,10 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
         n_layers = (int)ceil(occ + 6.0 * sqrt(occ) + 8.0);
     }
     c->geo.n_layers = n_layers;
+    // all-pairs: partner chunks per 64-atom home block
+    int ap_split = 0, ap_chunk = 0;
+    if (p.pipeline == MD_PIPE_ALLPAIRS) allpairs_split(p.n_atoms, &ap_split, &ap_chunk);
+    const int64_t ap_blocks = ap_split > 0 ? (int64_t)allpairs_home_blocks(p.n_atoms) * ap_split : 0;
 
     // workspace layout
     const int64_t ncell = (int64_t)nc * nc * nc;
@@ -176,7 +187,9 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
     b[R_SX] = b[R_SY] = b[R_SZ] = b[R_SVX] = b[R_SVY] = b[R_SVZ] = perm * sizeof(double) * n;
     b[R_SFX] = b[R_SFY] = b[R_SFZ] = perm * fsz * n;
     b[R_SID] = b[R_SCELL] = perm * sizeof(int32_t) * n;
-    b[R_FPART] = sizeof(double) * 2 * (size_t)max_force_blocks(n, ncell);
+    b[R_APART] = ap_split > 1 ? fsz * 3 * (size_t)ap_split * npad : 0;
+    const int64_t fblocks = max_force_blocks(n, ncell);
+    b[R_FPART] = sizeof(double) * 2 * (size_t)(ap_blocks > fblocks ? ap_blocks : fblocks);
     b[R_IPART] = sizeof(double) * 8 * kIntegrateGridMax;
     b[R_HIST] = sizeof(md_record) * kHistCap;
     size_t o = 0;
@@ -200,6 +213,8 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
     k.newton3 = p.newton3;
     k.pipeline = p.pipeline;
     k.n_layers = n_layers;
+    k.ap_split = ap_split;
+    k.ap_chunk = ap_chunk;
     k.L = p.L;
     k.invL = 1.0 / p.L;
     k.inv_w = (double)nc / p.L;
@@ -255,15 +270,20 @@ extern "C" md_status md_layout(const md_ctx* c, int32_t which, size_t* offset, s
     if (!c || !offset || !count) return MD_ERR_ARG;
     const int64_t n = c->prm.n_atoms;
     const bool layers = c->prm.pipeline == MD_PIPE_LAYERS;
+    const bool allpairs = c->prm.pipeline == MD_PIPE_ALLPAIRS;
     switch (which) {
-        case MD_ARR_CELL_OF: *offset = c->off[R_CELL_OF]; *count = n; break;
+        case MD_ARR_CELL_OF:
+            if (allpairs) return MD_ERR_ARG;
+            *offset = c->off[R_CELL_OF];
+            *count = n;
+            break;
         case MD_ARR_CELL_START:
-            if (layers) return MD_ERR_ARG;
+            if (layers || allpairs) return MD_ERR_ARG;
             *offset = c->off[R_CELL_START];
             *count = c->geo.n_cells + 1;
             break;
         case MD_ARR_CELL_ATOMS:
-            if (layers) return MD_ERR_ARG;
+            if (layers || allpairs) return MD_ERR_ARG;
             *offset = c->off[R_ORDER];
             *count = n;
             break;
@@ -330,6 +350,7 @@ extern "C" md_status md_bind(md_ctx* c, const md_buffers* bf, void* stream)
     k.sid = static_cast<int32_t*>(at(R_SID));
     k.layers = static_cast<int32_t*>(at(R_LAYERS));
     k.w32 = static_cast<int32_t*>(at(R_W32));
+    k.apart = at(R_APART);
     k.scell = static_cast<int32_t*>(at(R_SCELL));
     k.fpart = static_cast<double*>(at(R_FPART));
     k.ipart = static_cast<double*>(at(R_IPART));
@@ -352,7 +373,9 @@ static void cells_any(const KParams& k, int force, hipStream_t s)
 {
     if (k.pipeline == MD_PIPE_LAYERS)
         launch_layer_cells(k, force, s);
-    else
+    else if (k.pipeline == MD_PIPE_ALLPAIRS) {
+        if (force) launch_allpairs_fold(k, s);  // in a step the drift folds
+    } else
         launch_cells(k, force, s);
 }
 
@@ -368,6 +391,8 @@ static void forces_any(const KParams& k, hipStream_t s)
 {
     if (k.pipeline == MD_PIPE_LAYERS)
         launch_layer_forces(k, s);
+    else if (k.pipeline == MD_PIPE_ALLPAIRS)
+        launch_allpairs_forces(k, s);
     else
         launch_forces(k, s);
 }

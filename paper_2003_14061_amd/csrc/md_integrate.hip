@@ -97,6 +97,7 @@ __global__ __launch_bounds__(kIntThreads) void k_integrate(B b, int phase, int r
     double dmax2 = 0.0;
     const int stride = wg.n * blockDim.x;
     const bool drift_now = phase <= 1, track = phase <= 1 && p.mode == MD_NEIGHBOR_LIST;
+    const bool fold = p.pipeline == MD_PIPE_ALLPAIRS;
     for (int i = wg.id * blockDim.x + threadIdx.x; i < p.n; i += stride) {
         // every input first, so that one round of loads serves the iteration
         const double gx = (double)fx[i], gy = (double)fy[i], gz = (double)fz[i];
@@ -128,6 +129,11 @@ __global__ __launch_bounds__(kIntThreads) void k_integrate(B b, int phase, int r
             x = drift(x, p.dt, vx);
             y = drift(y, p.dt, vy);
             z = drift(z, p.dt, vz);
+            if (fold) {  // no cell build follows to fold them
+                x = wrap(x, p.L);
+                y = wrap(y, p.L);
+                z = wrap(z, p.L);
+            }
             p.x[i] = x;
             p.y[i] = y;
             p.z[i] = z;

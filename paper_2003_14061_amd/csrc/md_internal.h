@@ -58,6 +58,7 @@ struct KParams {
     int32_t *sid, *scell;
     int32_t *layers;  // layer matrix [ncell][n_layers] (MD_PIPE_LAYERS)
     int32_t *w32;     // neighbor matrix, 32-bit atom indices [cap][npad] (MD_PIPE_LAYERS)
+    void *apart;      // all-pairs per-chunk force partials [ap_split][3][npad] (MD_PIPE_ALLPAIRS)
     double *fpart;    // force-pass partials [nblk_force][2]: U, W
     double *ipart;    // per-atom kernel partials [int_grid][8]
     md_record* hist;
@@ -73,6 +74,7 @@ struct KParams {
     int32_t tiles_per_row, kx_max, n_tiles;
     int32_t scap;           // staged atoms a workgroup's LDS holds
     int32_t scap_aux;       // the same with a second 3-vector staged per atom
+    int32_t ap_split, ap_chunk;  // all-pairs: partner chunks per home block, atoms per chunk
 };
 
 // Arguments of one reverse-mode point (md_adjoint.hip).  lambda_x is the
@@ -166,6 +168,7 @@ __device__ __forceinline__ KParams global_view(const KParams& q)
     p.fpart = as_global(q.fpart); p.ipart = as_global(q.ipart);
     p.hist = as_global(q.hist);
     p.layers = as_global(q.layers); p.w32 = as_global(q.w32);
+    p.apart = as_global(q.apart);
     return p;
 }
 
@@ -235,6 +238,10 @@ void launch_layer_cells(const KParams& p, int force, hipStream_t s);
 void launch_layer_nl(const KParams& p, int force, hipStream_t s);
 void launch_layer_forces(const KParams& p, hipStream_t s);
 void launch_layer_export(const KParams& p, int32_t* out, hipStream_t s);
+int allpairs_home_blocks(int n);
+void allpairs_split(int n, int* split, int* chunk);
+void launch_allpairs_forces(const KParams& p, hipStream_t s);
+void launch_allpairs_fold(const KParams& p, hipStream_t s);
 
 void launch_clear(const KParams& p, hipStream_t s);
 void launch_cells(const KParams& p, int force, hipStream_t s);

@@ -24,7 +24,7 @@ MD_LJ_SHIFTED, MD_LJ_TRUNC = 0, 1
 MD_FP64, MD_FP32_MIXED = 0, 1
 MD_CELLS_ONLY, MD_NEIGHBOR_LIST = 0, 1
 MD_NL_AUTO, MD_NL_LANES, MD_NL_CELL_WAVES = 0, 1, 2
-MD_PIPE_TILED, MD_PIPE_LAYERS = 0, 1
+MD_PIPE_TILED, MD_PIPE_LAYERS, MD_PIPE_ALLPAIRS = 0, 1, 2
 (MD_ARR_CELL_OF, MD_ARR_CELL_START, MD_ARR_CELL_ATOMS, MD_ARR_NL, MD_ARR_NL_COUNT, MD_ARR_XREF,
  MD_ARR_LAYERS, MD_ARR_LAYER_COUNT) = range(8)
 
@@ -294,7 +294,10 @@ class Simulation:
         if not isinstance(vel, torch.Tensor):
             vel = np.asarray(vel, dtype=np.float64)
         n = pos.shape[0]
-        pipe = {"tiled": MD_PIPE_TILED, "layers": MD_PIPE_LAYERS}[pipeline]
+        pipe = {"tiled": MD_PIPE_TILED, "layers": MD_PIPE_LAYERS,
+                "allpairs": MD_PIPE_ALLPAIRS}[pipeline]
+        if pipe == MD_PIPE_ALLPAIRS:
+            neighbor_list = False  # no cells and no list: every pair is tested
         if reorder is None:
             reorder = bool(neighbor_list) and pipe == MD_PIPE_TILED
         self.params = Params(int(n), MD_LJ_SHIFTED if shifted else MD_LJ_TRUNC, float(L),

@@ -85,8 +85,10 @@ def test_geometry_of_the_workloads():
     dict(n=0), dict(r_cut=-1.0), dict(dt=0.0), dict(skin=-0.1), dict(block=100),
     dict(block=2048), dict(precision=7), dict(mode=3), dict(reorder=2), dict(cap=-1),
     dict(newton3=2), dict(newton3=-1), dict(newton3=1, mode=md.MD_CELLS_ONLY),
-    dict(pipeline=2), dict(pipeline=1, reorder=1), dict(pipeline=1, reorder=0, newton3=1),
-    dict(pipeline=1, reorder=0, mode=md.MD_CELLS_ONLY),
+    dict(pipeline=3), dict(pipeline=-1), dict(pipeline=1, reorder=1),
+    dict(pipeline=1, reorder=0, newton3=1), dict(pipeline=1, reorder=0, mode=md.MD_CELLS_ONLY),
+    dict(pipeline=2, reorder=0), dict(pipeline=2, reorder=1, mode=md.MD_CELLS_ONLY),
+    dict(pipeline=2, reorder=0, mode=md.MD_CELLS_ONLY, newton3=1),
 ])
 def test_invalid_parameters_are_rejected(bad):
     ctx = C.c_void_p()
@@ -174,3 +176,34 @@ def test_trajectory_workspace_is_validated_on_the_host():
             assert md.md_traj_workspace_bytes(ctx, bad) == 0
     finally:
         md.md_destroy(ctx)
+
+
+def test_allpairs_pipeline_geometry_and_arrays():
+    """The all-pairs comparison pipeline: cells-only box rule, no cell arrays,
+    and room for one energy partial per workgroup and the chunk partials."""
+    for n in (40, 4000, 100000, 256000):
+        p = params(n=n, rho=0.8 if n > 40 else 0.3, mode=md.MD_CELLS_ONLY, reorder=0,
+                   pipeline=2)
+        ctx = md.md_init(p)
+        try:
+            g = md.md_geometry(ctx)
+            assert g.nc >= 3 and g.cell_width >= p.r_cut
+            for which in (md.MD_ARR_CELL_OF, md.MD_ARR_CELL_START, md.MD_ARR_CELL_ATOMS,
+                          md.MD_ARR_LAYERS, md.MD_ARR_XREF):
+                with pytest.raises(md.MDError):
+                    md.md_layout(ctx, which)
+            # home blocks of 64 atoms times partner chunks of whole 256-atom tiles;
+            # the chunk partials: 3 force components per chunk and padded atom
+            blocks = -(-n // 64)
+            tiles = -(-n // 256)
+            split = max(1, min(-(-2048 // blocks), tiles))
+            chunk = -(-(-(-n // split)) // 256) * 256
+            split = -(-n // chunk)
+            need = 16 * blocks * split + (24 * split * g.n_pad if split > 1 else 0)
+            assert md.md_workspace_bytes(ctx) >= need
+        finally:
+            md.md_destroy(ctx)
+    # too small a box for a unique minimum image at this cutoff
+    ctx = C.c_void_p()
+    bad = params(n=20, rho=0.8, mode=md.MD_CELLS_ONLY, reorder=0, pipeline=2)
+    assert md.lib().md_init(C.byref(bad), C.byref(ctx)) == -2
