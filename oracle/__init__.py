@@ -27,6 +27,17 @@ class Sys(C.Structure):
                 ("use_nl", C.c_int32), ("nl_cap", C.c_int32)]
 
 
+class Bonded(C.Structure):
+    """Chain topology and bonded parameters (md_oracle_bonded.h)."""
+    _fields_ = [("chain_length", C.c_int32), ("pad", C.c_int32), ("fene_k", C.c_double),
+                ("fene_r0", C.c_double), ("bend_k", C.c_double), ("tors_c", C.c_double * 4)]
+
+
+def make_bonded(chain_length, fene_k=30.0, fene_r0=1.5, bend_k=0.0, tors_c=(0.0, 0.0, 0.0, 0.0)):
+    return Bonded(int(chain_length), 0, float(fene_k), float(fene_r0), float(bend_k),
+                  (C.c_double * 4)(*[float(c) for c in tors_c]))
+
+
 class GrSpec(C.Structure):
     _fields_ = [("n_bins", C.c_int32), ("rmax", C.c_double), ("width", C.c_double)]
 
@@ -111,6 +122,15 @@ def lib():
         L.or_traj_adjoint.restype = C.c_int32
         L.or_traj_adjoint.argtypes = ([_SP, _GP, C.c_int32, _D, _D, _D, _D, _D, _D, C.c_double,
                                        C.c_void_p, _PD, C.c_void_p] + [_D] * 6 + [_D])
+        # bonded chains (md_oracle_bonded.h)
+        _BP = C.POINTER(Bonded)
+        L.or_forces_bonded.restype = C.c_int32
+        L.or_forces_bonded.argtypes = [_SP, _BP, _D, _D, _D] + fo
+        L.or_energy_bonded.restype = C.c_double
+        L.or_energy_bonded.argtypes = [_SP, _BP, _D, _D, _D]
+        L.or_run_bonded.restype = C.c_int32
+        L.or_run_bonded.argtypes = [_SP, _BP, C.c_int32, _D, _D, _D, _D, _D, _D, _D, _D, _D,
+                                    C.c_void_p]
         _LIB = L
     return _LIB
 
@@ -383,3 +403,41 @@ def traj_adjoint(s, g, n_steps, pos, vel, gU, gG=None):
         raise RuntimeError(_TRAJ_ERR.get(r, f"oracle error {r}"))
     return {"ubar": ub.value, "g": out[: g.n_bins], "grad_x0": np.stack(o[:3], 1),
             "grad_v0": np.stack(o[3:], 1), "grad_theta": th}
+
+
+# ---------------------------------------------------------------------------
+# Bonded chains (md_oracle_bonded.h): FENE bonds, bond angles, dihedrals of
+# linear chains of consecutive ids, section 4.4 item (2).
+
+def forces_bonded(s, b, pos):
+    """Bonded forces alone: dict f, u (energy booked to each term's first
+    atom), w (bond virial), s (rounding-error scale)."""
+    x, y, z = _xyz(pos)
+    o = _fout(s.n)
+    r = lib().or_forces_bonded(C.byref(s), C.byref(b), x, y, z, *_ptrs(o))
+    if r < 0:
+        raise RuntimeError("bonded forces undefined (bad topology or a bond at R0)")
+    return _pack(o)
+
+
+def energy_bonded(s, b, pos):
+    return float(lib().or_energy_bonded(C.byref(s), C.byref(b), *_xyz(pos)))
+
+
+def run_bonded(s, b, pos, vel, n_steps):
+    """As run(), with the bonded forces of b added to the pair forces."""
+    x, y, z = _xyz(pos)
+    vx, vy, vz = _xyz(vel)
+    fx, fy, fz = np.zeros(s.n), np.zeros(s.n), np.zeros(s.n)
+    obs = (Obs * max(n_steps, 1))()
+    r = lib().or_run_bonded(C.byref(s), C.byref(b), int(n_steps), x, y, z, vx, vy, vz,
+                            fx, fy, fz, C.cast(obs, C.c_void_p))
+    if r < 0:
+        raise RuntimeError({-1: "bad arguments", -2: "box too small for 3 cells per side",
+                            -3: "neighbor list overflow", -4: "a bond reached R0"}
+                           .get(r, f"oracle error {r}"))
+    dt = np.dtype([("U", "f8"), ("K", "f8"), ("W", "f8"), ("P", "f8", 3), ("dmax2", "f8"),
+                   ("rebuilt", "i4"), ("max_nl", "i4")])
+    arr = np.frombuffer(bytes(obs), dtype=dt)[:n_steps].copy()
+    return (np.stack([x, y, z], 1), np.stack([vx, vy, vz], 1), np.stack([fx, fy, fz], 1),
+            arr, int(r))

@@ -10,7 +10,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SOURCES = ["md_oracle.c", "md_oracle_adjoint.c"]
+SOURCES = ["md_oracle.c", "md_oracle_adjoint.c", "md_oracle_bonded.c"]
 
 
 def build(verbose: bool = False) -> str:

@@ -524,6 +524,16 @@ int32_t or_run(const or_sys* s, int32_t n_steps,
                double* fx, double* fy, double* fz,
                or_obs* obs)
 {
+    return or_run_hooked(s, NULL, NULL, n_steps, x, y, z, vx, vy, vz, fx, fy, fz, obs);
+}
+
+int32_t or_run_hooked(const or_sys* s, or_force_hook hook, const void* hook_ctx,
+                      int32_t n_steps,
+                      double* x, double* y, double* z,
+                      double* vx, double* vy, double* vz,
+                      double* fx, double* fy, double* fz,
+                      or_obs* obs)
+{
     if (s->n <= 0 || n_steps < 0 || s->L <= 0.0) return -1;
     double r_cell = s->use_nl ? s->r_cut + s->skin : s->r_cut;
     run_ws ws;
@@ -547,6 +557,7 @@ int32_t or_run(const or_sys* s, int32_t n_steps,
     int32_t longest = rebuild(s, &ws, x, y, z);
     if (longest > s->nl_cap) err = -3;
     if (!err) forces(s, &ws, x, y, z, fx, fy, fz);
+    if (!err && hook) err = hook(hook_ctx, s, x, y, z, fx, fy, fz, ws.u_i, ws.w_i);
 
     for (int32_t step = 0; step < n_steps && !err; ++step) {
         or_kick(s, vx, vy, vz, fx, fy, fz);
@@ -569,6 +580,10 @@ int32_t or_run(const or_sys* s, int32_t n_steps,
             if (s->use_nl) ++n_rebuild;
         }
         forces(s, &ws, x, y, z, fx, fy, fz);
+        if (hook) {
+            err = hook(hook_ctx, s, x, y, z, fx, fy, fz, ws.u_i, ws.w_i);
+            if (err) break;
+        }
         or_kick(s, vx, vy, vz, fx, fy, fz);
         if (obs) {
             or_obs* o = &obs[step];

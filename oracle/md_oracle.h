@@ -153,6 +153,22 @@ int32_t or_run(const or_sys* s, int32_t n_steps,
                double* fx, double* fy, double* fz,
                or_obs* obs);
 
+/* Extra forces added after every pair-force evaluation of a run: the hook
+ * adds to the forces and to the per-atom energy and virial (id order) and
+ * returns 0, or a negative code that ends the run with that code. */
+typedef int32_t (*or_force_hook)(const void* ctx, const or_sys* s,
+                                 const double* x, const double* y, const double* z,
+                                 double* fx, double* fy, double* fz,
+                                 double* u_i, double* w_i);
+
+/* or_run with a force hook (hook NULL: exactly or_run). */
+int32_t or_run_hooked(const or_sys* s, or_force_hook hook, const void* hook_ctx,
+                      int32_t n_steps,
+                      double* x, double* y, double* z,
+                      double* vx, double* vy, double* vz,
+                      double* fx, double* fy, double* fz,
+                      or_obs* obs);
+
 /* number of OpenMP threads the per-atom loops use (1 without OpenMP) */
 int32_t or_threads(void);
 

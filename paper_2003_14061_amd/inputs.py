@@ -173,3 +173,76 @@ def ensemble(n_replicas: int = 64, seed: int = 4, T: float = 1.0, dt: float = 0.
         w.vel = thermal_velocities(n, T, rng)
         reps.append(w)
     return reps
+
+
+def snake_sites(n_side: int, L: float) -> np.ndarray:
+    """The n_side^3 simple-cubic sites of sc_positions, ordered along a
+    boustrophedon path: x runs back and forth along each row, the rows of a
+    plane back and forth in y, and the planes in z with every other plane
+    walked in reverse, so that consecutive sites are always nearest
+    neighbors (lattice spacing L / n_side apart)."""
+    a = L / n_side
+    order = []
+    for z in range(n_side):
+        plane = []
+        for y in range(n_side):
+            xs = range(n_side) if y % 2 == 0 else range(n_side - 1, -1, -1)
+            plane.extend((x, y, z) for x in xs)
+        if z % 2 == 1:
+            plane.reverse()
+        order.extend(plane)
+    return np.ascontiguousarray((np.array(order, dtype=np.float64) + 0.5) * a)
+
+
+@dataclasses.dataclass
+class PolymerMelt:
+    """Linear chains of consecutive ids (atoms c*M .. c*M + M - 1 form chain
+    c) cut from a boustrophedon path through a simple-cubic lattice at number
+    density rho, Gaussian-jittered, with thermal velocities."""
+    name: str
+    n_side: int
+    chain_length: int
+    rho: float
+    T: float
+    dt: float
+    r_cut: float
+    skin: float
+    jitter: float
+    seed: int
+    n: int = 0
+    L: float = 0.0
+    pos: np.ndarray | None = None
+    vel: np.ndarray | None = None
+
+    def materialize(self) -> "PolymerMelt":
+        self.n = self.n_side ** 3
+        if self.n % self.chain_length:
+            raise ValueError("the lattice does not divide into whole chains")
+        rng = np.random.default_rng(self.seed)
+        self.L = box_length(self.n, self.rho)
+        self.pos = jitter(snake_sites(self.n_side, self.L), self.L, self.jitter, rng)
+        self.vel = thermal_velocities(self.n, self.T, rng)
+        return self
+
+
+def polymer_preset(name: str, **over) -> PolymerMelt:
+    """Polymer melts by descriptive name.
+
+    melt_256k    4096 chains of 64, 64^3 = 262144 atoms, rho 0.85, T 1, dt 0.005,
+                 WCA between all atoms, skin 0.3
+    melt_32k     1024 chains of 32, 32^3 = 32768 atoms, otherwise the same
+    melt_4k      256 chains of 16, 16^3 = 4096 atoms, otherwise the same
+    """
+    table = {
+        "melt_256k": dict(n_side=64, chain_length=64, rho=0.85, T=1.0, dt=0.005,
+                          r_cut=WCA_CUT, skin=0.3, jitter=0.05, seed=21),
+        "melt_32k": dict(n_side=32, chain_length=32, rho=0.85, T=1.0, dt=0.005,
+                         r_cut=WCA_CUT, skin=0.3, jitter=0.05, seed=22),
+        "melt_4k": dict(n_side=16, chain_length=16, rho=0.85, T=1.0, dt=0.005,
+                        r_cut=WCA_CUT, skin=0.3, jitter=0.05, seed=23),
+    }
+    if name not in table:
+        raise KeyError(f"unknown polymer workload {name!r}; known: {sorted(table)}")
+    kw = dict(table[name])
+    kw.update(over)
+    return PolymerMelt(name=name, **kw)
