@@ -47,6 +47,8 @@ def parse():
                     help="skip the paper's layer-matrix pipeline (thread-per-atom kernels)")
     ap.add_argument("--no-allpairs", action="store_true",
                     help="skip the all-pairs comparison on the 4000-atom WCA system")
+    ap.add_argument("--no-polymer", action="store_true",
+                    help="skip the bonded polymer melt (262 144 atoms in chains of 64)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward ratio of the differentiable run")
     ap.add_argument("--no-main", action="store_true",
@@ -240,6 +242,52 @@ def run_allpairs():
               file=sys.stderr, flush=True)
     return {"workload": "WCA (LJ cut and shifted at r_c=2^(1/6) sigma), FCC, rho=0.8, T=1, "
                         "dt=0.005; list pipelines with skin 0.3", "by_n": out}
+
+
+POLYMER_BONDED = dict(fene_k=30.0, fene_r0=1.5, bend_k=1.5)
+
+
+def run_polymer(steps=500, warmup=50):
+    """Bonded chains (section 4.4, item (2)): 4096 chains of 64 atoms (64^3 =
+    262 144), rho 0.85, T 1, dt 0.005, WCA between all atoms, skin 0.3, FENE
+    bonds (k 30, R0 1.5) and bending k_b 1.5, FP64, tiled pipeline.  The same
+    system without the bonded terms gives the bonded overhead."""
+    import torch
+
+    from paper_2003_14061_amd import inputs, md
+
+    m = inputs.polymer_preset("melt_256k").materialize()
+    out = {}
+    for key, bonded in (("bonded", dict(chain_length=m.chain_length, **POLYMER_BONDED)),
+                        ("pairs_only", None)):
+        sim = md.Simulation(m.pos, m.vel, m.L, r_cut=m.r_cut, skin=m.skin, dt=m.dt,
+                            bonded=bonded)
+        sim.prepare()
+        sim.step(warmup)
+        o0 = sim.reduce()
+        sim.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        f_ms, f_n = sim.get_timing()
+        sim.set_timing(False)
+        o1 = sim.reduce()
+        out[key] = {"value": round(m.n * steps / (t1 - t0), 1),
+                    "ms_per_step": round(1e3 * (t1 - t0) / steps, 6),
+                    "force_ms_avg": round(f_ms / max(f_n, 1), 6),
+                    "rebuilds": int(o1["n_rebuilds"] - o0["n_rebuilds"]),
+                    "energy_drift_per_atom": (o1["U"] + o1["K"] - o0["U"] - o0["K"]) / m.n}
+        del sim
+        torch.cuda.synchronize()
+    return {"workload": "melt_256k: 4096 chains of 64 (snake-lattice start), rho=0.85, T=1, "
+                        "dt=0.005, WCA r_c=2^(1/6) sigma, skin 0.3; FENE k=30, R0=1.5; bending "
+                        "k_b=1.5; FP64",
+            **out,
+            "bonded_overhead_ms_per_step": round(out["bonded"]["ms_per_step"]
+                                                 - out["pairs_only"]["ms_per_step"], 6),
+            "kernels": "k_bond_map (gated with the cell rebuild) + k_bonded (thread per atom)"}
 
 
 def run_adjoint(precision, repeats=3):
@@ -503,6 +551,10 @@ def main():
                                        "one HIP graph launch per 500 steps")
     if not args.no_allpairs:
         out["paper_allpairs"] = run_allpairs()
+    if not args.no_polymer:
+        out["polymer_melt"] = run_polymer()
+        print(f"[bench] polymer melt done: {out['polymer_melt']['bonded']['value']:.3e} "
+              "atom-steps/s", file=sys.stderr, flush=True)
     if not args.no_adjoint:
         adj = {}
         for prec, key in (("fp64", "fp64"), ("fp32", "fp32_mixed")):

@@ -51,8 +51,11 @@ typedef enum {
     MD_ERR_HIP = -5,            /* a HIP runtime call failed */
     MD_ERR_NOT_BOUND = -6,      /* md_bind has not been called */
     MD_ERR_STATE = -7,          /* call out of order (e.g. step before forces) */
-    MD_ERR_LAYER_OVERFLOW = -8  /* a cell held more atoms than the layer matrix has layers
+    MD_ERR_LAYER_OVERFLOW = -8, /* a cell held more atoms than the layer matrix has layers
                                    (MD_PIPE_LAYERS) */
+    MD_ERR_BOND_BROKEN = -9,    /* a bonded pair reached the FENE limit R0 (md_set_bonded) */
+    MD_ERR_TOPOLOGY = -10       /* the permanent ids are not a permutation of 0 .. N-1, so
+                                   the chains of md_set_bonded are undefined */
 } md_status;
 
 enum { MD_LJ_SHIFTED = 0, MD_LJ_TRUNC = 1 };      /* potential */
@@ -62,7 +65,8 @@ enum { MD_PIPE_TILED = 0, MD_PIPE_LAYERS = 1, MD_PIPE_ALLPAIRS = 2 }; /* pipelin
 enum { MD_NL_AUTO = 0, MD_NL_LANES = 1, MD_NL_CELL_WAVES = 2 }; /* md_tuning.nl_method */
 
 /* Device flag bits (md_observables.flags). */
-enum { MD_FLAG_NL_OVERFLOW = 1, MD_FLAG_NONFINITE = 2, MD_FLAG_LAYER_OVERFLOW = 4 };
+enum { MD_FLAG_NL_OVERFLOW = 1, MD_FLAG_NONFINITE = 2, MD_FLAG_LAYER_OVERFLOW = 4,
+       MD_FLAG_BOND_BROKEN = 8, MD_FLAG_TOPOLOGY = 16 };
 
 /* System and method parameters, copied by md_init.  Lengths in the units of
  * sigma's length, energies in eps's units. */
@@ -184,6 +188,39 @@ enum {
  * MD_ERR_ARG for bad values, MD_ERR_BOX_TOO_SMALL when floor(L / cell
  * width) < 3. */
 md_status md_init(const md_params* params, md_ctx** out);
+
+/* Bonded chains (section 4.4, item (2): polymers as atoms linked by elastic
+ * bonds, with a bond-angle and an optional dihedral interaction, on top of
+ * the pair forces between all atoms).  The paper gives no functional forms;
+ * these are used:
+ *   bond      FENE  U = -(fene_k fene_r0^2 / 2) ln(1 - r^2 / fene_r0^2)
+ *   angle     U = bend_k (1 - cos theta), theta the angle between the bond
+ *             vectors b1 = r_j - r_i and b2 = r_k - r_j of consecutive bonds
+ *             (zero for a straight chain)
+ *   dihedral  U = sum_{m=0..3} tors_c[m] cos^m phi over three consecutive
+ *             bonds, cos phi = n1.n2 / (|n1||n2|), n1 = b1 x b2, n2 = b2 x b3
+ *             (phi = 0 cis, pi trans)
+ * Chains are linear: the atoms with permanent ids c*M .. c*M + M - 1 form
+ * chain c in that order (M = chain_length).  Bond vectors take the minimum
+ * image.  A term whose coefficient is zero is skipped. */
+typedef struct {
+    int32_t chain_length;  /* M >= 2; n_atoms must be a multiple of M */
+    int32_t pad;
+    double  fene_k;        /* >= 0 */
+    double  fene_r0;       /* > 0; a bond reaching it latches MD_FLAG_BOND_BROKEN */
+    double  bend_k;
+    double  tors_c[4];
+} md_bonded;
+
+/* md_set_bonded: add the bonded forces of `b` to every force evaluation
+ * (md_forces, md_step), their energy to U and the bonds' virial to W.  NULL
+ * removes them.  Call before md_bind (the workspace grows by an id-to-slot
+ * map and the bonded partials: query md_workspace_bytes afterwards);
+ * MD_ERR_STATE once bound, MD_ERR_ARG for bad values.  Each atom's thread
+ * evaluates the bonded terms it takes part in (no atomics).  Not available in
+ * batches or trajectory mode.  The permanent ids must be a permutation of
+ * 0 .. N-1, else md_reduce reports MD_ERR_TOPOLOGY. */
+md_status md_set_bonded(md_ctx* ctx, const md_bonded* b);
 
 /* Bytes of workspace the context needs (0 for a NULL context). */
 size_t md_workspace_bytes(const md_ctx* ctx);

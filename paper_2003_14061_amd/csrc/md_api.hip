@@ -33,6 +33,8 @@ extern "C" const char* md_status_str(int32_t st)
         case MD_ERR_NOT_BOUND: return "buffers not bound (call md_bind)";
         case MD_ERR_STATE: return "call out of order";
         case MD_ERR_LAYER_OVERFLOW: return "layer matrix overflow: a cell held more atoms than layers";
+        case MD_ERR_BOND_BROKEN: return "a bond reached the FENE limit R0";
+        case MD_ERR_TOPOLOGY: return "atom ids are not a permutation of 0..N-1 (chains undefined)";
         default: return "unknown status";
     }
 }
@@ -96,6 +98,17 @@ static void plan_tiles(md_ctx* c, int cells)
 }
 
 static md_status hip_ok(hipError_t e) { return e == hipSuccess ? MD_OK : MD_ERR_HIP; }
+
+// Offsets of the workspace regions from their sizes.
+static void relayout(md_ctx* c)
+{
+    size_t o = 0;
+    for (int r = 0; r < R_COUNT; ++r) {
+        c->off[r] = o;
+        o += align_up(c->bytes[r]);
+    }
+    c->ws_bytes = o;
+}
 
 static md_status launched() { return hip_ok(hipGetLastError()); }
 
@@ -192,12 +205,7 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
     b[R_FPART] = sizeof(double) * 2 * (size_t)(ap_blocks > fblocks ? ap_blocks : fblocks);
     b[R_IPART] = sizeof(double) * 8 * kIntegrateGridMax;
     b[R_HIST] = sizeof(md_record) * kHistCap;
-    size_t o = 0;
-    for (int r = 0; r < R_COUNT; ++r) {
-        c->off[r] = o;
-        o += align_up(b[r]);
-    }
-    c->ws_bytes = o;
+    relayout(c);
 
     KParams& k = c->kp;
     memset(&k, 0, sizeof(k));
@@ -257,6 +265,38 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
 }
 
 extern "C" size_t md_workspace_bytes(const md_ctx* c) { return c ? c->ws_bytes : 0; }
+
+extern "C" md_status md_set_bonded(md_ctx* c, const md_bonded* b)
+{
+    if (!c) return MD_ERR_ARG;
+    if (c->bound) return MD_ERR_STATE;
+    KParams& k = c->kp;
+    if (!b) {
+        k.bonded_on = 0;
+        c->bytes[R_SLOT_OF] = c->bytes[R_BPART] = 0;
+        relayout(c);
+        return MD_OK;
+    }
+    const bool finite = isfinite(b->fene_k) && isfinite(b->fene_r0) && isfinite(b->bend_k) &&
+                        isfinite(b->tors_c[0]) && isfinite(b->tors_c[1]) &&
+                        isfinite(b->tors_c[2]) && isfinite(b->tors_c[3]);
+    if (!finite || b->chain_length < 2 || c->prm.n_atoms % b->chain_length != 0 ||
+        !(b->fene_r0 > 0.0) || b->fene_k < 0.0)
+        return MD_ERR_ARG;
+    k.bonded_on = 1;
+    k.chain_len = b->chain_length;
+    k.fene_k = b->fene_k;
+    k.fene_r02 = b->fene_r0 * b->fene_r0;
+    k.bend_k = b->bend_k;
+    for (int m = 0; m < 4; ++m) k.tors_c[m] = b->tors_c[m];
+    k.tors_on = b->tors_c[0] != 0.0 || b->tors_c[1] != 0.0 || b->tors_c[2] != 0.0 ||
+                b->tors_c[3] != 0.0;
+    k.nblk_bonded = bonded_blocks(k.n);
+    c->bytes[R_SLOT_OF] = sizeof(int32_t) * (size_t)k.n;
+    c->bytes[R_BPART] = sizeof(double) * 2 * (size_t)k.nblk_bonded;
+    relayout(c);
+    return MD_OK;
+}
 
 extern "C" md_status md_geometry(const md_ctx* c, md_grid* out)
 {
@@ -351,6 +391,8 @@ extern "C" md_status md_bind(md_ctx* c, const md_buffers* bf, void* stream)
     k.layers = static_cast<int32_t*>(at(R_LAYERS));
     k.w32 = static_cast<int32_t*>(at(R_W32));
     k.apart = at(R_APART);
+    k.slot_of = static_cast<int32_t*>(at(R_SLOT_OF));
+    k.bpart = static_cast<double*>(at(R_BPART));
     k.scell = static_cast<int32_t*>(at(R_SCELL));
     k.fpart = static_cast<double*>(at(R_FPART));
     k.ipart = static_cast<double*>(at(R_IPART));
@@ -377,6 +419,7 @@ static void cells_any(const KParams& k, int force, hipStream_t s)
         if (force) launch_allpairs_fold(k, s);  // in a step the drift folds
     } else
         launch_cells(k, force, s);
+    if (k.bonded_on) launch_bond_map(k, force, s);  // after any permutation of the slots
 }
 
 static void neighbors_any(const KParams& k, int force, hipStream_t s)
@@ -395,6 +438,7 @@ static void forces_any(const KParams& k, hipStream_t s)
         launch_allpairs_forces(k, s);
     else
         launch_forces(k, s);
+    if (k.bonded_on) launch_bonded(k, s);  // adds to the pair forces
 }
 
 extern "C" md_status md_build_cells(md_ctx* c)
@@ -531,6 +575,8 @@ extern "C" md_status md_reduce(md_ctx* c, md_observables* out)
     out->max_occupancy = d.max_occ;
     out->max_nl = d.max_nl;
     out->flags = d.flags;
+    if (d.flags & MD_FLAG_TOPOLOGY) return MD_ERR_TOPOLOGY;
+    if (d.flags & MD_FLAG_BOND_BROKEN) return MD_ERR_BOND_BROKEN;
     if (d.flags & MD_FLAG_LAYER_OVERFLOW) return MD_ERR_LAYER_OVERFLOW;
     if (d.flags & MD_FLAG_NL_OVERFLOW) return MD_ERR_NL_OVERFLOW;
     if (d.flags & MD_FLAG_NONFINITE) return MD_ERR_NONFINITE;
@@ -594,7 +640,7 @@ static md_status traj_check(md_ctx* c, const md_traj_params* tp, void* ws, TrajL
     if (!c || !tp || !ws || !traj_layout(c, tp, L)) return MD_ERR_ARG;
     if (!c->bound) return MD_ERR_NOT_BOUND;
     if (c->prm.mode != MD_NEIGHBOR_LIST || c->prm.reorder != 0 || c->prm.newton3 != 0 ||
-        c->prm.pipeline != MD_PIPE_TILED)
+        c->prm.pipeline != MD_PIPE_TILED || c->kp.bonded_on)
         return MD_ERR_ARG;
     if (((uintptr_t)ws) % kAlign != 0) return MD_ERR_ARG;
     if (tp->n_bins > 0 && tp->gr_rmax + 3.0 * tp->gr_width > c->prm.r_cut + c->prm.skin)

@@ -17,7 +17,7 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 enum Region {
     R_DEV, R_CELL_COUNT, R_CELL_START, R_CELL_OF, R_SLOT, R_ORDER, R_TMP, R_NL, R_NL_COUNT,
     R_XR, R_YR, R_ZR, R_SX, R_SY, R_SZ, R_SVX, R_SVY, R_SVZ, R_SFX, R_SFY, R_SFZ, R_SID,
-    R_SCELL, R_LAYERS, R_W32, R_APART, R_FPART, R_IPART, R_HIST, R_COUNT
+    R_SCELL, R_LAYERS, R_W32, R_APART, R_SLOT_OF, R_BPART, R_FPART, R_IPART, R_HIST, R_COUNT
 };
 
 }  // namespace md

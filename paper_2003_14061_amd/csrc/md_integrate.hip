@@ -61,8 +61,12 @@ __device__ void record_step(const KParams& p, int n_wg, int record_every, double
     __syncthreads();
     if (threadIdx.x == 0) dd->step = step;
     if (!(record_every > 0 && step % record_every == 0)) return;
-    const double U = finish_sum(p.fpart, p.nblk_force, 2, 0, red);
-    const double W = finish_sum(p.fpart, p.nblk_force, 2, 1, red);
+    double U = finish_sum(p.fpart, p.nblk_force, 2, 0, red);
+    double W = finish_sum(p.fpart, p.nblk_force, 2, 1, red);
+    if (p.bonded_on) {
+        U += finish_sum(p.bpart, p.nblk_bonded, 2, 0, red);
+        W += finish_sum(p.bpart, p.nblk_bonded, 2, 1, red);
+    }
     const double K = finish_sum(p.ipart, n_wg, 8, 0, red);
     const double Px = finish_sum(p.ipart, n_wg, 8, 1, red);
     const double Py = finish_sum(p.ipart, n_wg, 8, 2, red);
@@ -203,8 +207,12 @@ __global__ __launch_bounds__(kIntThreads) void k_observe(KParams p)
         for (int k = 0; k < 4; ++k) o[k] = acc[k];
     }
     if (!last_block(p.dev, gridDim.x)) return;
-    const double U = finish_sum(p.fpart, p.nblk_force, 2, 0, red);
-    const double W = finish_sum(p.fpart, p.nblk_force, 2, 1, red);
+    double U = finish_sum(p.fpart, p.nblk_force, 2, 0, red);
+    double W = finish_sum(p.fpart, p.nblk_force, 2, 1, red);
+    if (p.bonded_on) {
+        U += finish_sum(p.bpart, p.nblk_bonded, 2, 0, red);
+        W += finish_sum(p.bpart, p.nblk_bonded, 2, 1, red);
+    }
     double s[4];
     for (int k = 0; k < 4; ++k) s[k] = finish_sum(p.ipart, gridDim.x, 8, k, red);
     if (threadIdx.x == 0) {

@@ -75,6 +75,11 @@ struct KParams {
     int32_t scap;           // staged atoms a workgroup's LDS holds
     int32_t scap_aux;       // the same with a second 3-vector staged per atom
     int32_t ap_split, ap_chunk;  // all-pairs: partner chunks per home block, atoms per chunk
+    // bonded chains (md_set_bonded): chain of id i is i / chain_len
+    int32_t bonded_on, chain_len, nblk_bonded, tors_on;
+    double fene_k, fene_r02, bend_k, tors_c[4];
+    int32_t *slot_of;  // [n] current slot of each permanent id
+    double *bpart;     // [nblk_bonded][2] bonded energy and virial partials
 };
 
 // Arguments of one reverse-mode point (md_adjoint.hip).  lambda_x is the
@@ -169,6 +174,7 @@ __device__ __forceinline__ KParams global_view(const KParams& q)
     p.hist = as_global(q.hist);
     p.layers = as_global(q.layers); p.w32 = as_global(q.w32);
     p.apart = as_global(q.apart);
+    p.slot_of = as_global(q.slot_of); p.bpart = as_global(q.bpart);
     return p;
 }
 
@@ -242,6 +248,9 @@ int allpairs_home_blocks(int n);
 void allpairs_split(int n, int* split, int* chunk);
 void launch_allpairs_forces(const KParams& p, hipStream_t s);
 void launch_allpairs_fold(const KParams& p, hipStream_t s);
+int bonded_blocks(int n);
+void launch_bond_map(const KParams& p, int force, hipStream_t s);
+void launch_bonded(const KParams& p, hipStream_t s);
 
 void launch_clear(const KParams& p, hipStream_t s);
 void launch_cells(const KParams& p, int force, hipStream_t s);

@@ -36,7 +36,7 @@ EXPORTS = ("md_init", "md_workspace_bytes", "md_geometry", "md_layout", "md_bind
            "md_batch_bind", "md_batch_prepare", "md_batch_forces", "md_batch_layout",
            "md_batch_run", "md_batch_set_tuning",
            "md_batch_get_tuning", "md_batch_autotune", "md_batch_destroy", "md_destroy",
-           "md_status_str")
+           "md_status_str", "md_set_bonded")
 
 
 class MDError(RuntimeError):
@@ -57,6 +57,13 @@ class Params(C.Structure):
 class Buffers(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz",
                                            "id", "workspace")]
+
+
+class Bonded(C.Structure):
+    """md_bonded: linear chains of consecutive ids, FENE bonds, bond angles,
+    dihedrals (section 4.4, item (2))."""
+    _fields_ = [("chain_length", C.c_int32), ("pad", C.c_int32), ("fene_k", C.c_double),
+                ("fene_r0", C.c_double), ("bend_k", C.c_double), ("tors_c", C.c_double * 4)]
 
 
 class Grid(C.Structure):
@@ -139,6 +146,7 @@ def lib():
         "md_batch_destroy": (None, [P]),
         "md_destroy": (None, [P]),
         "md_status_str": (C.c_char_p, [C.c_int32]),
+        "md_set_bonded": (C.c_int, [P, C.POINTER(Bonded)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -163,6 +171,17 @@ def md_init(params: Params):
     ctx = C.c_void_p()
     _check(lib().md_init(C.byref(params), C.byref(ctx)), "md_init")
     return ctx
+
+
+def md_set_bonded(ctx, chain_length=None, fene_k=30.0, fene_r0=1.5, bend_k=0.0,
+                  tors_c=(0.0, 0.0, 0.0, 0.0)):
+    """Bonded chains (chain_length None removes them)."""
+    if chain_length is None:
+        _check(lib().md_set_bonded(ctx, None), "md_set_bonded")
+        return
+    b = Bonded(int(chain_length), 0, float(fene_k), float(fene_r0), float(bend_k),
+               (C.c_double * 4)(*[float(c) for c in tors_c]))
+    _check(lib().md_set_bonded(ctx, C.byref(b)), "md_set_bonded")
 
 
 def md_workspace_bytes(ctx) -> int:
@@ -277,13 +296,16 @@ class Simulation:
     """One periodic system on one GPU: tensors, context, and the calls in order.
 
     pos, vel: (N, 3) arrays in id order.  All per-atom tensors are float64
-    except the forces in FP32-mixed mode (float32).
+    except the forces in FP32-mixed mode (float32).  pipeline: "tiled",
+    "layers" (the paper's own steps) or "allpairs" (every pair, no cells);
+    bonded: None, or md_set_bonded's keywords (chain_length, fene_k, fene_r0,
+    bend_k, tors_c) for linear chains of consecutive ids.
     """
 
     def __init__(self, pos, vel, L, *, r_cut, dt, skin=0.3, eps=1.0, sigma=1.0, mass=1.0,
                  shifted=True, precision="fp64", neighbor_list=True, reorder=None,
-                 newton3=False, nl_capacity=0, block=256, pipeline="tiled", device="cuda",
-                 stream=None):
+                 newton3=False, nl_capacity=0, block=256, pipeline="tiled", bonded=None,
+                 device="cuda", stream=None):
         import torch
 
         if not torch.cuda.is_available():
@@ -311,6 +333,8 @@ class Simulation:
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.ctx = md_init(self.params)
+        if bonded is not None:  # dict of md_set_bonded's keywords
+            md_set_bonded(self.ctx, **bonded)
         self._tuning = None
         self.grid = md_geometry(self.ctx)
         def t(a):

@@ -207,3 +207,28 @@ def test_allpairs_pipeline_geometry_and_arrays():
     ctx = C.c_void_p()
     bad = params(n=20, rho=0.8, mode=md.MD_CELLS_ONLY, reorder=0, pipeline=2)
     assert md.lib().md_init(C.byref(bad), C.byref(ctx)) == -2
+
+
+def test_bonded_chains_are_validated_and_grow_the_workspace():
+    p = params(n=4096, rho=0.85, reorder=1)
+    ctx = md.md_init(p)
+    try:
+        base = md.md_workspace_bytes(ctx)
+        lib = md.lib()
+        bad = [dict(chain_length=1), dict(chain_length=3),  # 4096 is not a multiple of 3
+               dict(chain_length=16, fene_r0=0.0), dict(chain_length=16, fene_k=-1.0),
+               dict(chain_length=16, bend_k=float("nan"))]
+        for kw in bad:
+            args = dict(fene_k=30.0, fene_r0=1.5, bend_k=0.0)
+            args.update(kw)
+            b = md.Bonded(args["chain_length"], 0, args["fene_k"], args["fene_r0"],
+                          args["bend_k"], (C.c_double * 4)(0, 0, 0, 0))
+            assert lib.md_set_bonded(ctx, C.byref(b)) == -1, kw
+        md.md_set_bonded(ctx, chain_length=16, bend_k=1.5, tors_c=(0.1, 0.2, 0.3, 0.4))
+        grown = md.md_workspace_bytes(ctx)
+        # an id-to-slot map and two partials per 256-atom workgroup, 256-byte aligned
+        assert grown - base == 4 * 4096 + 16 * 16
+        md.md_set_bonded(ctx, None)
+        assert md.md_workspace_bytes(ctx) == base
+    finally:
+        md.md_destroy(ctx)

@@ -1,0 +1,150 @@
+"""Bonded polymer chains (md_set_bonded, section 4.4 item (2)) on the GPU
+against the oracle: the pair forces of the chosen pipeline plus FENE bonds,
+bond angles and dihedrals.
+
+Contract: forces within 1e-12 (FP64) and 1e-5 (FP32-mixed) of the oracle's,
+per atom against the summed scales of the pair and bonded terms and
+normwise; U and W (pair + bonded) to the same bounds; short runs follow the
+oracle's bonded run; chains crossing the periodic boundary, slots permuted
+by the reorder or not, chains of two atoms (bonds only), and the latched
+errors for a bond at its FENE limit and for ids that are not a permutation."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2003_14061_amd import inputs
+from paper_2003_14061_amd import md
+
+from gpu_helpers import WCA, min_image
+from test_oracle_bonded import walk_chains
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+ALL = dict(fene_k=30.0, fene_r0=1.5, bend_k=1.5, tors_c=(0.2, 0.5, 0.1, -0.3))
+
+
+def oracle_forces(s_nb, b, pos, pipeline):
+    """Pair forces of the oracle (list or all pairs) plus its bonded forces."""
+    if pipeline == "allpairs":
+        ref = oracle.forces_allpairs(s_nb, pos)
+    else:
+        nc = oracle.cells_per_side(s_nb.L, s_nb.r_cut + s_nb.skin)
+        cells = oracle.build_cells(s_nb, nc, pos)
+        cnt, nl, _ = oracle.build_nl(s_nb, nc, pos, cells)
+        ref = oracle.forces_nl(s_nb, pos, cnt, nl)
+    bd = oracle.forces_bonded(s_nb, b, pos)
+    return {"f": ref["f"] + bd["f"], "u": ref["u"] + bd["u"], "w": ref["w"] + bd["w"],
+            "s": ref["s"] + bd["s"]}
+
+
+def errors(f, ref):
+    d = np.linalg.norm(f - ref["f"], axis=1)
+    per_atom = float(np.max(d / np.maximum(ref["s"], 1e-300)))
+    normwise = float(np.linalg.norm(f - ref["f"]) / np.linalg.norm(ref["f"]))
+    return per_atom, normwise
+
+
+def melt(n_side=16, M=16, seed=23):
+    return inputs.polymer_preset("melt_4k", n_side=n_side, chain_length=M, seed=seed).materialize()
+
+
+CASES = [("tiled", True, "fp64"), ("tiled", False, "fp64"), ("tiled", True, "fp32"),
+         ("layers", False, "fp64"), ("allpairs", False, "fp64"), ("allpairs", False, "fp32")]
+
+
+@pytest.mark.parametrize("pipeline,reorder,precision", CASES)
+def test_bonded_melt_forces_match_the_oracle(pipeline, reorder, precision):
+    m = melt()
+    sim = md.Simulation(m.pos, m.vel, m.L, r_cut=m.r_cut, skin=m.skin, dt=m.dt,
+                        precision=precision, reorder=reorder, pipeline=pipeline,
+                        bonded=dict(chain_length=m.chain_length, **ALL))
+    sim.prepare()
+    obs = sim.reduce()
+    use_nl = pipeline != "allpairs"
+    s = oracle.make_sys(m.n, m.L, r_cut=m.r_cut, skin=m.skin if use_nl else 0.0, dt=m.dt,
+                        use_nl=use_nl, nl_cap=max(sim.grid.nl_capacity, 1))
+    b = oracle.make_bonded(m.chain_length, **ALL)
+    ref = oracle_forces(s, b, m.pos, pipeline)
+    per_atom, normwise = errors(sim.state()["f"], ref)
+    tol = TOL[precision]
+    assert per_atom <= tol and normwise <= tol, (per_atom, normwise)
+    assert abs(obs["U"] - ref["u"].sum()) <= tol * np.abs(ref["u"]).sum()
+    assert obs["W"] == pytest.approx(ref["w"].sum(), rel=10 * tol, abs=1e-9)
+    assert obs["flags"] == 0
+
+
+@pytest.mark.parametrize("M", [2, 3, 7])
+def test_bonded_random_walk_chains(M):
+    """Non-degenerate random-walk chains in a dilute box, every term on; chains
+    of 2 have bonds only, chains of 3 no dihedral."""
+    L = 16.0
+    nch = (700 // M)
+    pos = walk_chains(nch, M, L, seed=31 + M)
+    n = len(pos)
+    vel = np.zeros_like(pos)
+    sim = md.Simulation(pos, vel, L, r_cut=WCA, skin=0.3, dt=0.002,
+                        bonded=dict(chain_length=M, **ALL))
+    sim.prepare()
+    obs = sim.reduce(check=False)
+    s = oracle.make_sys(n, L, r_cut=WCA, skin=0.3, dt=0.002, nl_cap=sim.grid.nl_capacity)
+    b = oracle.make_bonded(M, **ALL)
+    ref = oracle_forces(s, b, pos, "tiled")
+    per_atom, normwise = errors(sim.state()["f"], ref)
+    assert per_atom <= 1e-12 and normwise <= 1e-12, (per_atom, normwise)
+    assert abs(obs["U"] - ref["u"].sum()) <= 1e-12 * np.abs(ref["u"]).sum()
+
+
+@pytest.mark.parametrize("pipeline", ["tiled", "allpairs"])
+def test_bonded_short_run_follows_the_oracle(pipeline):
+    steps = 40
+    m = melt(n_side=12, M=12, seed=29)
+    sim = md.Simulation(m.pos, m.vel, m.L, r_cut=m.r_cut, skin=m.skin, dt=0.002,
+                        pipeline=pipeline, bonded=dict(chain_length=m.chain_length, **ALL))
+    use_nl = pipeline != "allpairs"
+    s = oracle.make_sys(m.n, m.L, r_cut=m.r_cut, skin=m.skin if use_nl else 0.0, dt=0.002,
+                        use_nl=use_nl, nl_cap=max(sim.grid.nl_capacity, 1))
+    b = oracle.make_bonded(m.chain_length, **ALL)
+    sim.prepare()
+    sim.step(steps, record_every=1)
+    h = sim.history()
+    st = sim.state()
+    p_ref, v_ref, _, o_ref, nreb = oracle.run_bonded(s, b, m.pos, m.vel, steps)
+    e_scale = np.abs(o_ref["U"]).max() + np.abs(o_ref["K"]).max()
+    assert np.max(np.abs(h["U"] - o_ref["U"])) <= 1e-10 * e_scale
+    assert np.max(np.abs(h["K"] - o_ref["K"])) <= 1e-10 * e_scale
+    assert np.max(np.abs(h["W"] - o_ref["W"])) <= 1e-9 * (np.abs(o_ref["W"]).max() + 1)
+    assert np.abs(min_image(st["pos"] - p_ref, m.L)).max() < 1e-10
+    assert np.abs(st["vel"] - v_ref).max() < 1e-9
+    if use_nl:
+        assert sim.reduce()["n_rebuilds"] == nreb
+
+
+def test_bond_at_the_fene_limit_is_latched():
+    m = melt(n_side=8, M=8, seed=3)
+    pos = m.pos.copy()
+    # pull atom 1 of chain 0 away from atom 0 by more than R0 (and from atom 2)
+    pos[1] = np.mod(pos[0] + np.array([1.6, 0.0, 0.0]), m.L)
+    sim = md.Simulation(pos, m.vel, m.L, r_cut=m.r_cut, skin=m.skin, dt=m.dt,
+                        bonded=dict(chain_length=8, fene_k=30.0, fene_r0=1.5))
+    sim.prepare()
+    with pytest.raises(md.MDError) as e:
+        sim.reduce()
+    assert e.value.status == -9
+    assert sim.reduce(check=False)["flags"] & 8
+
+
+def test_ids_that_are_not_a_permutation_are_latched():
+    m = melt(n_side=8, M=8, seed=4)
+    sim = md.Simulation(m.pos, m.vel, m.L, r_cut=m.r_cut, skin=m.skin, dt=m.dt, reorder=False,
+                        bonded=dict(chain_length=8, fene_k=30.0, fene_r0=1.5))
+    with torch.no_grad():
+        sim.id[13] = 12  # id 13 is missing, 12 appears twice
+    torch.cuda.synchronize()
+    sim.prepare()
+    with pytest.raises(md.MDError) as e:
+        sim.reduce()
+    assert e.value.status == -10
+    assert sim.reduce(check=False)["flags"] & 16
