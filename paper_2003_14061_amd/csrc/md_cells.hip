@@ -10,9 +10,9 @@
 //   k_cellsort   inside each cell, ascending permanent id (the paper leaves
 //                the order open; a fixed order makes the list reproducible):
 //                each atom's place is the number of its cell's members with
-//                a smaller id
-//   k_permute /  with reorder on: atom data permuted into cell order
-//   k_copyback
+//                a smaller id; with reorder on it also writes the atom's data
+//                to that place in the scratch arrays
+//   k_copyback   with reorder on: the scratch arrays back into the state
 //
 // Every kernel returns at once unless the rebuild flag is set (or the call
 // forces the build), so a step's launch sequence is fixed.  Each kernel is a
@@ -196,8 +196,10 @@ __global__ void k_scatter(B b, int force)
 
 // Canonical order inside each cell: ascending permanent id.  One lane per
 // atom counts the members of its cell with a smaller id (ids are distinct);
-// that count is its place.
-template <class B>
+// that count is its place.  With kPermute the atom's data go to that place
+// in the scratch arrays (the permutation into cell order, scattered from the
+// atom rather than gathered by a second pass).
+template <typename F, class B, bool kPermute>
 __global__ void k_cellsort(B b, int force)
 {
     Wg wg;
@@ -211,30 +213,21 @@ __global__ void k_cellsort(B b, int force)
         const int key = p.id[s];
         int rank = 0;
         for (int j = 0; j < cnt; ++j) rank += p.id[p.tmp[a + j]] < key ? 1 : 0;
-        p.order[a + rank] = s;
-    }
-}
-
-template <typename F, class B>
-__global__ void k_permute(B b, int force)
-{
-    Wg wg;
-    KParams p;
-    if (!b.fetch(G_ATOMS, wg, p)) return;
-    if (!rebuild_on(p, force)) return;
-    for (int q = wg.id * blockDim.x + threadIdx.x; q < p.n; q += wg.n * blockDim.x) {
-        const int o = p.order[q];
-        p.sx[q] = p.x[o];
-        p.sy[q] = p.y[o];
-        p.sz[q] = p.z[o];
-        p.svx[q] = p.vx[o];
-        p.svy[q] = p.vy[o];
-        p.svz[q] = p.vz[o];
-        reinterpret_cast<F*>(p.sfx)[q] = static_cast<const F*>(p.fx)[o];
-        reinterpret_cast<F*>(p.sfy)[q] = static_cast<const F*>(p.fy)[o];
-        reinterpret_cast<F*>(p.sfz)[q] = static_cast<const F*>(p.fz)[o];
-        p.sid[q] = p.id[o];
-        p.scell[q] = p.cell_of[o];
+        const int d = a + rank;
+        p.order[d] = s;
+        if (kPermute) {
+            p.sx[d] = p.x[s];
+            p.sy[d] = p.y[s];
+            p.sz[d] = p.z[s];
+            p.svx[d] = p.vx[s];
+            p.svy[d] = p.vy[s];
+            p.svz[d] = p.vz[s];
+            reinterpret_cast<F*>(p.sfx)[d] = static_cast<const F*>(p.fx)[s];
+            reinterpret_cast<F*>(p.sfy)[d] = static_cast<const F*>(p.fy)[s];
+            reinterpret_cast<F*>(p.sfz)[d] = static_cast<const F*>(p.fz)[s];
+            p.sid[d] = key;
+            p.scell[d] = c;
+        }
     }
 }
 
@@ -274,15 +267,14 @@ static void cells_seq(const B& b, const LaunchShape& sh, int force, hipStream_t 
     hipLaunchKernelGGL(k_bin<B>, atoms, blk, 0, s, b, force);
     hipLaunchKernelGGL(k_scan<B>, dim3(sh.grid[G_ONE]), dim3(kScanThreads), 0, s, b, force);
     hipLaunchKernelGGL(k_scatter<B>, atoms, blk, 0, s, b, force);
-    hipLaunchKernelGGL(k_cellsort<B>, atoms, blk, 0, s, b, force);
-    if (sh.reorder) {
-        if (sh.precision == MD_FP64) {
-            hipLaunchKernelGGL((k_permute<double, B>), atoms, blk, 0, s, b, force);
-            hipLaunchKernelGGL((k_copyback<double, B>), atoms, blk, 0, s, b, force);
-        } else {
-            hipLaunchKernelGGL((k_permute<float, B>), atoms, blk, 0, s, b, force);
-            hipLaunchKernelGGL((k_copyback<float, B>), atoms, blk, 0, s, b, force);
-        }
+    if (!sh.reorder) {
+        hipLaunchKernelGGL((k_cellsort<double, B, false>), atoms, blk, 0, s, b, force);
+    } else if (sh.precision == MD_FP64) {
+        hipLaunchKernelGGL((k_cellsort<double, B, true>), atoms, blk, 0, s, b, force);
+        hipLaunchKernelGGL((k_copyback<double, B>), atoms, blk, 0, s, b, force);
+    } else {
+        hipLaunchKernelGGL((k_cellsort<float, B, true>), atoms, blk, 0, s, b, force);
+        hipLaunchKernelGGL((k_copyback<float, B>), atoms, blk, 0, s, b, force);
     }
 }
 
