@@ -143,3 +143,15 @@ def test_allpairs_coincident_atoms_are_flagged():
         sim.reduce()
     assert e.value.status == -4
     assert sim.reduce(check=False)["flags"] & 2
+
+
+def test_allpairs_has_no_cells_and_no_list():
+    sim, _, _, _, _ = setup("wca40_tiny")
+    sim.prepare()
+    with pytest.raises(md.MDError):
+        sim.cells()
+    with pytest.raises(md.MDError):
+        sim.neighbor_list()
+    with pytest.raises(md.MDError):
+        md.md_build_neighbors(sim.ctx)
+    assert sim.reduce()["flags"] == 0

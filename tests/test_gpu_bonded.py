@@ -148,3 +148,16 @@ def test_ids_that_are_not_a_permutation_are_latched():
         sim.reduce()
     assert e.value.status == -10
     assert sim.reduce(check=False)["flags"] & 16
+
+
+def test_bonded_chains_are_not_in_trajectory_mode():
+    m = melt(n_side=8, M=8, seed=5)
+    sim = md.Simulation(m.pos, m.vel, m.L, r_cut=m.r_cut, skin=m.skin, dt=m.dt, reorder=False,
+                        bonded=dict(chain_length=8, fene_k=30.0, fene_r0=1.5, bend_k=1.0))
+    with pytest.raises(md.MDError) as e:
+        sim.traj_forward(4, 2)
+    assert e.value.status == -1
+    # the run itself is unaffected
+    sim.prepare()
+    sim.step(5)
+    assert sim.reduce()["flags"] == 0
