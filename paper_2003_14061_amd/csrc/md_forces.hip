@@ -168,8 +168,11 @@ __global__ void k_zero_forces(B b)
     }
 }
 
+// Six waves per SIMD (at most 80 VGPRs): three workgroups of the default
+// shape fit a CU by LDS, and the compiler's own allocation otherwise crosses
+// the five-wave line, which costs more than the two spilled registers.
 template <typename F, typename Acc, int LANES, class B>
-__global__ void k_forces_tiles(B b)
+__global__ __attribute__((amdgpu_waves_per_eu(6))) void k_forces_tiles(B b)
 {
     Wg wg;
     KParams p;

@@ -86,7 +86,8 @@ struct Stage {
     MD_LDS int* off;              // [ntab + 1] LDS offset of each staged cell
     MD_LDS int* slot;             // [ntab] global slot of each staged cell's first atom
     MD_LDS int* flag;             // [ntab] wrap bits
-    MD_LDS int* scan;             // [kWave] scratch
+    MD_LDS int* scan;             // [kWave] scratch of the scan; afterwards [0], [1]: the
+                                  // columns where the staged x index wraps to 0 (or stride)
     int ntab, stride, total, cap;
     bool fits;                    // total + 1 <= cap: positions (and sentinel) staged
 };
@@ -182,22 +183,36 @@ __device__ __forceinline__ void stage_tables(const KParams& p, const Tile& g, St
         carry += tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) s.off[s.ntab] = carry;
+    if (threadIdx.x == 0) {
+        s.off[s.ntab] = carry;
+        // staged column q holds cell x = cx0 - 1 + q (mod nc); along a staged row
+        // the slots run on from cell to cell except where x wraps from nc - 1 to
+        // 0, at q = 1 - cx0 (mod nc), at most twice in the kx + 2 columns
+        int q1 = (1 - g.cx0) % nc;
+        q1 = q1 <= 0 ? q1 + nc : q1;
+        s.scan[0] = q1 <= g.kx + 1 ? q1 : s.stride;
+        s.scan[1] = q1 + nc <= g.kx + 1 ? q1 + nc : s.stride;
+    }
     s.total = carry;
     s.fits = carry < s.cap;
     __syncthreads();
 }
 
-// Last staged cell t with off[t] <= k (k < total), i.e. the cell holding
-// staged entry k (empty cells are skipped by taking the last match).
-__device__ __forceinline__ int staged_cell(const Stage& s, int k)
+// First staged cell t of the run of slot-contiguous cells holding staged
+// entry k (k < total): its staged row from the 9 row starts (off of each
+// row's first cell; independent LDS reads, the same address in every lane),
+// then the wrap break(s) of that row.  The slot of entry k is then
+// s.slot[t] + (k - s.off[t]).
+__device__ __forceinline__ int staged_run(const Stage& s, int k)
 {
-    int lo = 0, hi = s.ntab - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s.off[mid] <= k) lo = mid; else hi = mid - 1;
-    }
-    return lo;
+    int sg = 0;
+#pragma unroll
+    for (int r = 1; r < 9; ++r) sg += k >= s.off[r * s.stride] ? 1 : 0;
+    const int t0 = sg * s.stride, qb0 = s.scan[0], qb1 = s.scan[1];
+    int t = t0;
+    if (k >= s.off[t0 + qb0]) t = t0 + qb0;
+    if (k >= s.off[t0 + qb1]) t = t0 + qb1;
+    return t;
 }
 
 // Positions of the staged atoms into LDS (when they fit), plus the sentinel;
@@ -217,7 +232,7 @@ __device__ __forceinline__ void stage_atoms(const KParams& p, const Stage& s, co
         for (int u = 0; u < U; ++u) {
             const int k = k0 + u * blockDim.x;
             if (k < s.total) {
-                const int t = staged_cell(s, k);
+                const int t = staged_run(s, k);
                 const int j = atom_at(p, s.slot[t] + (k - s.off[t]));
                 px[u] = p.x[j];
                 py[u] = p.y[j];
@@ -264,7 +279,7 @@ __device__ __forceinline__ void stage_positions(const KParams& p, const Stage& s
 // Atom (storage slot) of staged entry e.
 __device__ __forceinline__ int staged_slot(const KParams& p, const Stage& s, int e)
 {
-    const int t = staged_cell(s, e);
+    const int t = staged_run(s, e);
     return atom_at(p, s.slot[t] + (e - s.off[t]));
 }
 
