@@ -170,7 +170,7 @@ __global__ void k_zero_forces(B b)
 
 // Six waves per SIMD (at most 80 VGPRs): three workgroups of the default
 // shape fit a CU by LDS, and the compiler's own allocation otherwise crosses
-// the five-wave line, which costs more than the two spilled registers.
+// the five-wave line.
 template <typename F, typename Acc, int LANES, class B>
 __global__ __attribute__((amdgpu_waves_per_eu(6))) void k_forces_tiles(B b)
 {
@@ -198,7 +198,12 @@ __global__ __attribute__((amdgpu_waves_per_eu(6))) void k_forces_tiles(B b)
             double xi, yi, zi;
             home_position(p, s, h0, h, slot_i, xi, yi, zi);
             ForceOp<Acc> op{p, a};
-            walk_home<LANES>(p, s, mode, slot_i, sub, p.nl_count[slot_i], xi, yi, zi, op);
+            // the lane's list-row offset is formed here for each pass: hoisted out
+            // of the pass loop it is a 64-bit value live across the whole kernel
+            // (the empty asm hides that sub is the same in every pass)
+            int sub_p = sub;
+            asm volatile("" : "+v"(sub_p));
+            walk_home<LANES>(p, s, mode, slot_i, sub_p, p.nl_count[slot_i], xi, yi, zi, op);
         }
         if (LANES > 1) {
             a.fx = lane_group_sum<LANES>(a.fx);
