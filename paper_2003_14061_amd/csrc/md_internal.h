@@ -143,11 +143,16 @@ __host__ __device__ inline int grid_of(const KParams& p, GridKind k)
 }
 
 // A pointer the caller knows to address global memory (so the compiler
-// emits global, not flat, accesses through it).
+// emits global, not flat, accesses through it).  A plain cast to the global
+// address space and back is folded away as a no-op pair, losing the fact;
+// the empty asm makes the global-space value opaque, so the generic pointer
+// is visibly derived from a global one and its accesses are rewritten.
 template <class T>
 __device__ __forceinline__ T* as_global(T* q)
 {
-    return (T*)((__attribute__((address_space(1))) T*)q);
+    auto g = (__attribute__((address_space(1))) T*)q;
+    asm("" : "+s"(g));
+    return (T*)g;
 }
 
 // A register copy of a parameter block read from device memory, with every
