@@ -86,8 +86,8 @@ __global__ void k_forces_half(B b)
     Stage s = stage_layout(p, smem, p.scap_aux, true);
     stage_tables(p, g, s);
     const int nh = home_count(s), h0 = home_first_lds(s), slot0 = home_first_slot(s);
-    const int mode = image_mode(p, tile_interior(p, g));
-    stage_positions(p, s);
+    const int mode = staged_image_mode(p, s, tile_interior(p, g));
+    stage_positions_imaged(p, s);
     // the accumulators, in the aux region (F-typed, interleaved)
     MD_LDS F* r = reinterpret_cast<MD_LDS F*>(s.a3);
     if (s.fits) {
@@ -183,8 +183,8 @@ __global__ __attribute__((amdgpu_waves_per_eu(6))) void k_forces_tiles(B b)
     Stage s = stage_layout(p, smem);
     stage_tables(p, g, s);
     const int nh = home_count(s), h0 = home_first_lds(s), slot0 = home_first_slot(s);
-    const int mode = image_mode(p, tile_interior(p, g));
-    stage_positions(p, s);
+    const int mode = staged_image_mode(p, s, tile_interior(p, g));
+    stage_positions_imaged(p, s);
     __syncthreads();
     const int per_pass = blockDim.x / LANES;
     const int sub = threadIdx.x % LANES;

@@ -220,12 +220,19 @@ __device__ __forceinline__ int staged_run(const Stage& s, int k)
 // sentinel).  Each thread takes entries tid, tid + blockDim, ... four at a
 // time, so that several loads are in flight per thread.  No barrier: the
 // caller syncs.
-template <bool kAux>
+//
+// kShift (grids of at least 5 cells per side): every staged cell that wraps
+// is staged as its periodic image next to the tile, shifted by -L on the low
+// side of an axis (staged column 0, row y or z index -1) and +L on the high
+// side, so that the raw difference of a home atom and any staged partner is
+// already the minimum image and the pair loop needs no image rule.
+template <bool kAux, bool kShift = false>
 __device__ __forceinline__ void stage_atoms(const KParams& p, const Stage& s, const double* vx,
                                             const double* vy, const double* vz)
 {
     if (!s.fits) return;
     constexpr int U = 4;
+    const bool shift = kShift && p.nc >= 5;
     for (int k0 = threadIdx.x; k0 < s.total; k0 += U * blockDim.x) {
         double px[U], py[U], pz[U], qx[U], qy[U], qz[U];
 #pragma unroll
@@ -237,6 +244,13 @@ __device__ __forceinline__ void stage_atoms(const KParams& p, const Stage& s, co
                 px[u] = p.x[j];
                 py[u] = p.y[j];
                 pz[u] = p.z[j];
+                const int fl = shift ? s.flag[t] : 0;
+                if (fl) {
+                    const int sg = t / s.stride, q = t - sg * s.stride;
+                    if (fl & 1) px[u] += q == 0 ? -p.L : p.L;
+                    if (fl & 2) py[u] += sg % 3 == 0 ? -p.L : p.L;
+                    if (fl & 4) pz[u] += sg / 3 == 0 ? -p.L : p.L;
+                }
                 if (kAux) {
                     qx[u] = vx[j];
                     qy[u] = vy[j];
@@ -276,6 +290,13 @@ __device__ __forceinline__ void stage_positions(const KParams& p, const Stage& s
     stage_atoms<false>(p, s, nullptr, nullptr, nullptr);
 }
 
+// Staged positions as periodic images next to the tile (see stage_atoms);
+// pair loops over them take image mode staged_image_mode.
+__device__ __forceinline__ void stage_positions_imaged(const KParams& p, const Stage& s)
+{
+    stage_atoms<false, true>(p, s, nullptr, nullptr, nullptr);
+}
+
 // Atom (storage slot) of staged entry e.
 __device__ __forceinline__ int staged_slot(const KParams& p, const Stage& s, int e)
 {
@@ -284,7 +305,8 @@ __device__ __forceinline__ int staged_slot(const KParams& p, const Stage& s, int
 }
 
 // Minimum image of a staged pair.  kImage: 0 -- no wrap anywhere in the
-// tile, the raw difference is exact; 1 -- at least 5 cells per side: the raw
+// tile, or the wrapped cells staged as shifted images: the raw difference is
+// the minimum image; 1 -- at least 5 cells per side: the raw
 // difference, minus L*sign(d) in each flagged coordinate; 2 -- fewer than 5
 // cells per side: d - L*rint(d/L) in every coordinate.
 template <int kImage>
@@ -309,6 +331,14 @@ __device__ __forceinline__ void image(const KParams& p, int fl, double& dx, doub
 __device__ __forceinline__ int image_mode(const KParams& p, bool interior)
 {
     return p.nc < 5 ? 2 : (interior ? 0 : 1);
+}
+
+// The image rule over positions staged by stage_positions_imaged: none when
+// they are in LDS (wrapped cells are already shifted), the list's wrap bits
+// when the partners are read from global memory.
+__device__ __forceinline__ int staged_image_mode(const KParams& p, const Stage& s, bool interior)
+{
+    return image_mode(p, interior || s.fits);
 }
 
 // Home atoms of a tile: the kx cells q = 1..kx of the middle row (s = 4),
