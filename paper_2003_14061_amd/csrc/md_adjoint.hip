@@ -151,8 +151,8 @@ __global__ void k_adj_point(KParams p, AdjArgs q)
     Stage s = stage_layout(p, smem, q.cap, true);
     stage_tables(p, g, s);
     const int nh = home_count(s), h0 = home_first_lds(s), slot0 = home_first_slot(s);
-    const int mode = image_mode(p, tile_interior(p, g));
-    stage_atoms<true>(p, s, q.vx, q.vy, q.vz);
+    const int mode = staged_image_mode(p, s, tile_interior(p, g));
+    stage_atoms<true, true>(p, s, q.vx, q.vy, q.vz);
     __syncthreads();
     const double lu = q.loss_scale != 0.0 ? q.gobs[0] * q.loss_scale : 0.0;
     const int per_pass = blockDim.x / LANES;
@@ -287,8 +287,8 @@ __global__ void k_gr_hist(KParams p, GrArgs g, int cap)
     Stage s = stage_layout(p, smem, cap, false);
     stage_tables(p, t, s);
     const int nh = home_count(s), h0 = home_first_lds(s), slot0 = home_first_slot(s);
-    const int mode = image_mode(p, tile_interior(p, t));
-    stage_positions(p, s);
+    const int mode = staged_image_mode(p, s, tile_interior(p, t));
+    stage_positions_imaged(p, s);
     __syncthreads();
     const double reach = g.rmax + 3.0 * g.width;
     GrOp op{g, lh, reach * reach};
@@ -348,8 +348,8 @@ __global__ void k_gr_grad(KParams p, GrArgs g, int cap)
     Stage s = stage_layout(p, smem, cap, false);
     stage_tables(p, t, s);
     const int nh = home_count(s), h0 = home_first_lds(s), slot0 = home_first_slot(s);
-    const int mode = image_mode(p, tile_interior(p, t));
-    stage_positions(p, s);
+    const int mode = staged_image_mode(p, s, tile_interior(p, t));
+    stage_positions_imaged(p, s);
     __syncthreads();
     const double reach = g.rmax + 3.0 * g.width;
     for (int h = threadIdx.x; h < nh; h += blockDim.x) {
