@@ -146,7 +146,9 @@ __host__ __device__ inline int grid_of(const KParams& p, GridKind k)
 // emits global, not flat, accesses through it).  A plain cast to the global
 // address space and back is folded away as a no-op pair, losing the fact;
 // the empty asm makes the global-space value opaque, so the generic pointer
-// is visibly derived from a global one and its accesses are rewritten.
+// is visibly derived from a global one and its accesses are rewritten.  The
+// asm operand is a scalar register: q must be the same in every lane of the
+// wave (a parameter-block pointer, chosen per workgroup).
 template <class T>
 __device__ __forceinline__ T* as_global(T* q)
 {
