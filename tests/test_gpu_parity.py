@@ -35,6 +35,9 @@ CASES = {
     "lj32000_nl": (32000, 0.8, 2.5, 0.05, True, True, {}),
     "lj5000_random": (5000, 0.5, 2.5, 0.0, False, True, {}),
     "wca108_nc3": (108, 0.8, WCA, 0.08, True, True, {}),
+    # 5 cells per side: the smallest grid whose force passes stage wrapped
+    # cells as shifted images
+    "lj2916_nc5": (2916, 0.8, 2.5, 0.05, True, True, {}),
     "lj4000_noreorder": (4000, 0.8442, 2.5, 0.05, True, True, {"reorder": False}),
     "wca6000_block64": (6000, 0.8, WCA, 0.1, True, True, {"block": 64}),
     "lj9000_block1024": (9000, 0.7, 2.5, 0.1, True, True, {"block": 1024}),
@@ -256,7 +259,7 @@ TUNINGS = ([dict(force_lanes=l, force_block=b) for l in (1, 2, 4, 8) for b in (2
 
 
 @pytest.mark.parametrize("name", ["lj32000_nl", "wca13500_nl", "lj5000_random", "wca108_nc3",
-                                  "lj4000_noreorder"])
+                                  "lj4000_noreorder", "lj2916_nc5"])
 def test_every_tuning_matches_the_oracle(name):
     sim, s, pos, vel = setup(name)
     sim.build_cells()
