@@ -450,11 +450,40 @@ __device__ __forceinline__ void home_position(const KParams& p, const Stage& s, 
     }
 }
 
+// DPP lane moves: lane i of each quad takes lane i ^ 1 or i ^ 2 of the quad;
+// the half-row mirror gives lane i of each group of 8 lane 7 - i.
+constexpr int kDppQuadXor1 = 0xB1;   // quad_perm(1, 0, 3, 2)
+constexpr int kDppQuadXor2 = 0x4E;   // quad_perm(2, 3, 0, 1)
+constexpr int kDppHalfMirror = 0x141;
+
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_move(T v)
+{
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(T) == 4) {
+        const int b = __builtin_bit_cast(int, v);
+        return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, b, CTRL, 0xF, 0xF, false));
+    } else {
+        const uint64_t b = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo =
+            (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32),
+                                                                  CTRL, 0xF, 0xF, false);
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    }
+}
+
+// Sum over aligned groups of LANES lanes (1, 2, 4 or 8); every lane of a
+// group gets the group's sum.  The lane exchanges are DPP moves on the VALU
+// (a shuffle would go through LDS, which the pair loops keep busy).  Every
+// lane of the wave must be active.
 template <int LANES, typename T>
 __device__ __forceinline__ T lane_group_sum(T v)
 {
-#pragma unroll
-    for (int o = LANES / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    static_assert(LANES == 1 || LANES == 2 || LANES == 4 || LANES == 8, "lanes per atom");
+    if constexpr (LANES == 8) v += dpp_move<kDppHalfMirror>(v);
+    if constexpr (LANES >= 4) v += dpp_move<kDppQuadXor2>(v);
+    if constexpr (LANES >= 2) v += dpp_move<kDppQuadXor1>(v);
     return v;
 }
 
