@@ -53,7 +53,9 @@ static void plan_tiles(md_ctx* c, int cells)
     const int nc = k.nc;
     const double occ = (double)k.n / ((double)nc * nc * nc);
     if (cells <= 0) {
-        const double home = 1.25 * k.force_block / k.force_lanes;
+        // about 1.25 x force_block / 4 home atoms per tile, whatever the lanes
+        // per atom: at 2 lanes the same tile size measured best as well
+        const double home = 1.25 * k.force_block / 4.0;
         cells = (int)floor(home / (occ > 1e-9 ? occ : 1e-9));
     }
     const int kx_cap = nc < 128 ? nc : 128;
@@ -254,7 +256,9 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
         k.inner_hi = 0.0;  // empty range: always take the minimum image
     }
     k.block = p.block;
-    k.force_lanes = 4;
+    // FP64: 4 lanes per atom; FP32-mixed: 2 (its shorter pair arithmetic
+    // leaves the lane-sum and pass overheads a larger share)
+    k.force_lanes = p.precision == MD_FP64 ? 4 : 2;
     k.force_block = 512;
     c->nl_block_req = 0;
     k.int_grid = kIntegrateGridDefault;
