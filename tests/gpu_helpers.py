@@ -26,14 +26,17 @@ def state(n, rho, seed, jitter=0.0, lattice=True):
 
 
 def pair(pos, vel, L, *, r_cut, dt=0.005, skin=0.3, nl=True, shifted=True,
-         precision="fp64", reorder=None, nl_capacity=0, block=256, newton3=False):
+         precision="fp64", reorder=None, nl_capacity=0, block=256, newton3=False,
+         eps=1.0, sigma=1.0, mass=1.0, pipeline="tiled"):
     """A GPU Simulation and the oracle system description with the same
     parameters (same list capacity)."""
     sim = md.Simulation(pos, vel, L, r_cut=r_cut, dt=dt, skin=skin, shifted=shifted,
                         precision=precision, neighbor_list=nl, reorder=reorder,
-                        nl_capacity=nl_capacity, block=block, newton3=newton3)
+                        nl_capacity=nl_capacity, block=block, newton3=newton3, eps=eps,
+                        sigma=sigma, mass=mass, pipeline=pipeline)
     cap = sim.grid.nl_capacity if nl else 1
-    s = oracle.make_sys(len(pos), L, r_cut=r_cut, skin=skin if nl else 0.0, dt=dt,
+    s = oracle.make_sys(len(pos), L, r_cut=r_cut, skin=skin if nl else 0.0, dt=dt, eps=eps,
+                        sigma=sigma, mass=mass,
                         potential=oracle.LJ_SHIFTED if shifted else oracle.LJ_TRUNC,
                         use_nl=nl, nl_cap=max(cap, 1))
     return sim, s
@@ -80,6 +83,27 @@ def check_nl(sim, s, pos, cells, half=False):
     o = np.where(np.arange(cap)[None, :] < o_cnt[:, None], o_nl[:, :cap], -1)
     assert np.array_equal(g_id, o), "list entries or their order differ"
     return o_cnt, o_nl
+
+
+def compare_lists(ids, cnt, nl, o_cnt, o_nl, chunk=1 << 18):
+    """Every list of the GPU (slot space: cnt[n_pad], nl[cap, n_pad] decoded to
+    slots) against the oracle's (id space: o_cnt[n], o_nl[n, >= cap]), entry
+    by entry in list order, vectorised over chunks of atoms."""
+    n = len(ids)
+    cap = nl.shape[0]
+    slot_of = np.empty(n, np.int64)
+    slot_of[ids] = np.arange(n)
+    assert np.array_equal(cnt[:n][slot_of], o_cnt), "list lengths differ"
+    assert int(o_cnt.max(initial=0)) <= cap
+    col = np.arange(cap)
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        sl = slot_of[a:b]
+        rows = nl[:, sl]
+        m = col[:, None] < cnt[sl][None, :]
+        g = np.where(m, ids[np.clip(rows, 0, n - 1)], -1).T
+        o = np.where(col[None, :] < o_cnt[a:b, None], o_nl[a:b, :cap], -1)
+        assert np.array_equal(g, o), f"list entries or their order differ for ids {a}..{b}"
 
 
 def force_errors(f_gpu, ref):

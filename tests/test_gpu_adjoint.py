@@ -135,16 +135,19 @@ def test_autograd_function_gives_the_same_gradients():
     assert float(gs) == pytest.approx(ref["grad_theta"][1], rel=1e-8)
 
 
-def test_full_size_differentiable_run_matches_the_oracle():
-    # 32000 atoms (20^3 FCC, rho 0.8, T 1), LJ r_c 2.5, dt 0.004, 200 steps,
-    # checkpoints every 20, 50 g(r) bins on [0, 2.5)
+@pytest.mark.parametrize("eps,sigma", [(1.0, 1.0), (1.05, 0.98)])
+def test_full_size_differentiable_run_matches_the_oracle(eps, sigma):
+    # 32000 atoms (20^3 FCC, rho 0.8, T 1), LJ r_c 2.5 sigma, dt 0.004, 200
+    # steps, checkpoints every 20, 50 g(r) bins on [0, 2.5); (1.05, 0.98) is the
+    # parameter point of the target run whose g(r) the loss compares against
     L, pos, vel = state(32000, 0.8, 5)
-    sim = md.Simulation(pos, vel, L, r_cut=2.5, dt=0.004, skin=0.3, reorder=False)
+    sim = md.Simulation(pos, vel, L, r_cut=2.5 * sigma, dt=0.004, skin=0.3, eps=eps,
+                        sigma=sigma, reorder=False)
     rng = np.random.default_rng(500)
     gobs = np.concatenate([[1.0], 0.1 * rng.standard_normal(50)])
     tp = dict(n_steps=200, checkpoint_every=20, n_bins=50, gr_rmax=2.5, gr_width=0.05)
     obs, gx, gv, gth = run_gpu(sim, tp, gobs)
-    s = oracle.make_sys(32000, L, r_cut=2.5, skin=0.3, dt=0.004)
+    s = oracle.make_sys(32000, L, r_cut=2.5 * sigma, skin=0.3, dt=0.004, eps=eps, sigma=sigma)
     ref = oracle.traj_adjoint(s, oracle.gr_spec(50, 2.5, 0.05), 200, pos, vel, gobs[0], gobs[1:])
     assert abs(obs[0] - ref["ubar"]) <= 1e-10 * abs(ref["ubar"])
     assert np.abs(obs[1:] - ref["g"]).max() <= 1e-9 * np.abs(ref["g"]).max()
@@ -153,6 +156,34 @@ def test_full_size_differentiable_run_matches_the_oracle():
     assert np.allclose(gth, ref["grad_theta"], rtol=1e-7, atol=0)
     # any size: the loss does not change under a uniform translation
     assert np.abs(gx.sum(0)).max() <= 1e-9 * np.abs(gx).sum()
+
+
+@pytest.mark.parametrize("eps,sigma,mass", [(1.05, 0.98, 1.0), (1.3, 0.9, 2.0)])
+def test_gradients_match_the_oracle_away_from_unit_parameters(eps, sigma, mass):
+    # the pair derivatives scale with eps and sigma, the kicks of the reverse
+    # pass with 1/m; at eps = sigma = m = 1 a wrong factor would cancel
+    n, steps, k, bins, dt = 4000, 40, 10, 50, 0.004
+    rng = np.random.default_rng(71)
+    from paper_2003_14061_amd import inputs
+
+    L = inputs.box_length(n, 0.8 / sigma ** 3)
+    pos = inputs.jitter(inputs.fcc_positions(n, L, rng), L, 0.05 * sigma, rng)
+    vel = inputs.thermal_velocities(n, eps, rng, mass=mass)
+    rmax, width = 2.5 * sigma, 0.05
+    sim = md.Simulation(pos, vel, L, r_cut=2.5 * sigma, dt=dt, skin=0.3, eps=eps, sigma=sigma,
+                        mass=mass, reorder=False)
+    gobs = np.concatenate([[1.0], 0.1 * rng.standard_normal(bins)])
+    tp = dict(n_steps=steps, checkpoint_every=k, n_bins=bins, gr_rmax=rmax, gr_width=width)
+    obs, gx, gv, gth = run_gpu(sim, tp, gobs)
+    s = oracle.make_sys(n, L, r_cut=2.5 * sigma, skin=0.3, dt=dt, eps=eps, sigma=sigma,
+                        mass=mass)
+    ref = oracle.traj_adjoint(s, oracle.gr_spec(bins, rmax, width), steps, pos, vel, gobs[0],
+                              gobs[1:])
+    assert abs(obs[0] - ref["ubar"]) <= 1e-10 * abs(ref["ubar"])
+    assert np.abs(obs[1:] - ref["g"]).max() <= 1e-9 * max(1.0, np.abs(ref["g"]).max())
+    assert rel(gx, ref["grad_x0"]) <= 1e-8
+    assert rel(gv, ref["grad_v0"]) <= 1e-8
+    assert np.allclose(gth, ref["grad_theta"], rtol=1e-8, atol=0)
 
 
 def test_reverse_mode_arguments_are_checked():

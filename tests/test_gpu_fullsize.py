@@ -2,8 +2,8 @@
 times (default tuning, or the autotuner's pick for the ensemble):
 
   * the 2.048M-atom LJ system and the 256 000-atom WCA system after a stretch
-    of steps: cells bit-exact over all atoms, list lengths of all atoms, list
-    entries and brute-force forces of a sample of atoms, total energy and
+    of steps: cells bit-exact over all atoms, every list entry of every atom
+    in list order, brute-force forces of a sample of atoms, total energy and
     virial against the oracle's full-list sums, kinetic energy and momentum;
   * the 64-replica ensemble, every replica against its own oracle run;
   * the 4000-atom cells-only WCA system over its full 1000 steps: momentum
@@ -19,7 +19,7 @@ import oracle
 from paper_2003_14061_amd import inputs
 from paper_2003_14061_amd import md
 
-from gpu_helpers import check_cells, force_errors, min_image
+from gpu_helpers import check_cells, compare_lists, force_errors, min_image
 
 pytestmark = pytest.mark.gpu
 
@@ -50,19 +50,12 @@ def test_full_size_state_matches_the_oracle_on_samples(name, precision):
     assert longest <= sim.grid.nl_capacity
     cnt, nl = sim.neighbor_list()
     ids = sim.ids()
-    cnt_id = np.empty(n, np.int32)
-    cnt_id[ids] = cnt[:n]
-    assert np.array_equal(cnt_id, o_cnt), "list lengths differ"
+    # every list of every atom, entry by entry in list order
+    compare_lists(ids, cnt, nl, o_cnt, o_nl)
+    del nl
     assert obs["max_nl"] == int(o_cnt.max())
-    # entries of a sample, in list order
     rng = np.random.default_rng(5)
     idx = np.sort(rng.choice(n, 2000, replace=False)).astype(np.int32)
-    slot_of = np.empty(n, np.int64)
-    slot_of[ids] = np.arange(n)
-    for i in idx:
-        k = slot_of[i]
-        got = ids[nl[: cnt[k], k]]
-        assert np.array_equal(got, o_nl[i, : o_cnt[i]]), i
     # forces of the sample against brute force over all atoms
     ref = oracle.forces_sample(s, pos, idx)
     per_atom, normwise = force_errors(st["f"][idx], ref)

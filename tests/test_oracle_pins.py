@@ -465,3 +465,22 @@ def test_half_list_holds_every_pair_once_in_canonical_order():
     assert np.abs(h["f"] - f["f"]).max() <= 1e-12 * f["s"].max()
     assert abs(h["u"].sum() - f["u"].sum()) <= 1e-12 * np.abs(f["u"]).sum()
     assert abs(h["w"].sum() - f["w"].sum()) <= 1e-12 * np.abs(f["w"]).sum()
+
+
+def test_kinetic_energy_and_momentum_carry_the_mass():
+    # hand values: K = (m/2) sum |v|^2, P = m sum v, at m = 2 and m = 0.5
+    v = np.array([[1.0, 2.0, 3.0], [-1.0, 0.0, 2.0], [0.5, -0.25, 0.0]])
+    sq = (1 + 4 + 9) + (1 + 0 + 4) + (0.25 + 0.0625 + 0)  # 19.3125
+    for m in (2.0, 0.5):
+        s = oracle.make_sys(3, 5.0, r_cut=1.0, mass=m)
+        assert oracle.kinetic(s, v) == 0.5 * m * sq
+        assert np.array_equal(oracle.momentum(s, v), m * np.array([0.5, 1.75, 5.0]))
+    # the temperature the oracle's run reports for a box of resting atoms but
+    # one moving at speed c: K = m c^2 / 2 exactly
+    s = oracle.make_sys(2, 10.0, r_cut=1.0, dt=0.01, mass=3.0, use_nl=False)
+    pos = np.array([[1.0, 1.0, 1.0], [6.0, 6.0, 6.0]])
+    vel = np.array([[0.0, 0.0, 0.0], [0.0, 2.0, 0.0]])
+    _, v_end, _, o, _ = oracle.run(s, pos, vel, 3)
+    assert np.array_equal(v_end, vel)
+    assert np.all(o["K"] == 0.5 * 3.0 * 4.0)
+    assert np.all(o["P"][:, 1] == 6.0)
