@@ -407,7 +407,7 @@ def traj_adjoint(s, g, n_steps, pos, vel, gU, gG=None):
 
 # ---------------------------------------------------------------------------
 # Bonded chains (md_oracle_bonded.h): FENE bonds, bond angles, dihedrals of
-# linear chains of consecutive ids, section 4.4 item (2).
+# linear chains of consecutive ids, section 4.3 item (2).
 
 def forces_bonded(s, b, pos):
     """Bonded forces alone: dict f, u (energy booked to each term's first

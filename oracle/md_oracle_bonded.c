@@ -1,6 +1,6 @@
 /*
  * md_oracle_bonded.c -- TEST INFRASTRUCTURE ONLY.  Bonded chain forces
- * (section 4.4, item (2)); the readings are stated in md_oracle_bonded.h.
+ * (section 4.3, item (2)); the readings are stated in md_oracle_bonded.h.
  * Every term is evaluated once, in chain order, and its forces are applied
  * to all of its atoms.
  */

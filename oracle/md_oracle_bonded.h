@@ -2,7 +2,7 @@
  * md_oracle_bonded.h -- TEST INFRASTRUCTURE ONLY.
  *
  * Bonded forces of linear polymer chains, the extension the paper outlines
- * among its further MD studies (section 4.4, item (2)): atoms linked by
+ * among its further MD studies (section 4.3, item (2)): atoms linked by
  * elastic bonds, a bond-angle interaction between adjacent bonds, and an
  * optional dihedral (twist) interaction over three consecutive bonds, on top
  * of the non-bonded pair forces between all atoms.  The paper gives no

@@ -1,4 +1,4 @@
-"""Bonded polymer chains (md_set_bonded, section 4.4 item (2)) on the GPU
+"""Bonded polymer chains (md_set_bonded, section 4.3 item (2)) on the GPU
 against the oracle: the pair forces of the chosen pipeline plus FENE bonds,
 bond angles and dihedrals.
 

@@ -1,4 +1,4 @@
-"""Pins of the oracle's bonded chain forces (section 4.4, item (2); readings
+"""Pins of the oracle's bonded chain forces (section 4.3, item (2); readings
 in oracle/md_oracle_bonded.h): closed forms of each term, forces as minus
 the gradient of the energy by central differences, zero net force and
 torque per chain, the bond virial as minus the derivative of the energy
