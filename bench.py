@@ -248,7 +248,7 @@ POLYMER_BONDED = dict(fene_k=30.0, fene_r0=1.5, bend_k=1.5)
 
 
 def run_polymer(steps=500, warmup=50):
-    """Bonded chains (section 4.4, item (2)): 4096 chains of 64 atoms (64^3 =
+    """Bonded chains (section 4.3, item (2)): 4096 chains of 64 atoms (64^3 =
     262 144), rho 0.85, T 1, dt 0.005, WCA between all atoms, skin 0.3, FENE
     bonds (k 30, R0 1.5) and bending k_b 1.5, FP64, tiled pipeline.  The same
     system without the bonded terms gives the bonded overhead."""

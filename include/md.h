@@ -189,7 +189,7 @@ enum {
  * width) < 3. */
 md_status md_init(const md_params* params, md_ctx** out);
 
-/* Bonded chains (section 4.4, item (2): polymers as atoms linked by elastic
+/* Bonded chains (section 4.3, item (2): polymers as atoms linked by elastic
  * bonds, with a bond-angle and an optional dihedral interaction, on top of
  * the pair forces between all atoms).  The paper gives no functional forms;
  * these are used:

@@ -1,4 +1,4 @@
-// md_bonded.hip -- bonded forces of linear polymer chains (section 4.4,
+// md_bonded.hip -- bonded forces of linear polymer chains (section 4.3,
 // item (2)): elastic bonds, a bond-angle term between adjacent bonds and a
 // dihedral term over three consecutive bonds, added to the pair forces.
 //

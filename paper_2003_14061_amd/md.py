@@ -61,7 +61,7 @@ class Buffers(C.Structure):
 
 class Bonded(C.Structure):
     """md_bonded: linear chains of consecutive ids, FENE bonds, bond angles,
-    dihedrals (section 4.4, item (2))."""
+    dihedrals (section 4.3, item (2))."""
     _fields_ = [("chain_length", C.c_int32), ("pad", C.c_int32), ("fene_k", C.c_double),
                 ("fene_r0", C.c_double), ("bend_k", C.c_double), ("tors_c", C.c_double * 4)]
 

@@ -46,8 +46,13 @@ CASES = {
 }
 
 
-def system(name, seed=31):
+def system(name, seed=31, run=False):
     n, rho_s3, rc, shifted, nl, jit = CASES[name]
+    if run and jit is not None:
+        # Gaussian jitter of 0.08 sigma over 13 500 atoms leaves pairs at
+        # 0.55 sigma, whose forces make a 40-step run blow up (in the oracle
+        # as well); runs start from at most 0.05 sigma
+        jit = min(jit, 0.05)
     rng = np.random.default_rng(seed)
     L = inputs.box_length(n, rho_s3 / SIGMA ** 3)
     if jit is None:
@@ -110,7 +115,12 @@ def test_cells_list_forces_and_observables_fp64(name):
         pairs = sum(int(np.count_nonzero(
             (lambda d: (d * d).sum(1))(min_image(pos[o_nl[i, :o_cnt[i]]] - pos[i], L))
             < s.r_cut ** 2)) for i in range(s.n)) // 2
-        assert obs["U"] - sh["u"].sum() == pytest.approx(pairs * oracle.shift(s_sh), rel=1e-9)
+        # both totals carry rounding of order tol * sum |u_i|; with random
+        # positions close pairs make that scale large, so the difference is
+        # compared at that scale rather than relative to itself
+        scale = np.abs(sh["u"]).sum() + abs(pairs * oracle.shift(s_sh))
+        assert abs(obs["U"] - sh["u"].sum() - pairs * oracle.shift(s_sh)) <= max(
+            1e-9 * abs(pairs * oracle.shift(s_sh)), 2 * TOL["fp64"] * scale)
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -126,7 +136,7 @@ def test_forces_and_observables_fp32_mixed(name):
 
 
 def run_pair(name, precision, steps=40):
-    L, pos, vel, kw = system(name, seed=37)
+    L, pos, vel, kw = system(name, seed=37, run=True)
     sim, s = pair(pos, vel, L, precision=precision, **kw)
     sim.prepare()
     sim.step(steps, record_every=1)
