@@ -54,9 +54,15 @@ typedef enum {
     MD_ERR_LAYER_OVERFLOW = -8, /* a cell held more atoms than the layer matrix has layers
                                    (MD_PIPE_LAYERS) */
     MD_ERR_BOND_BROKEN = -9,    /* a bonded pair reached the FENE limit R0 (md_set_bonded) */
-    MD_ERR_TOPOLOGY = -10       /* the permanent ids are not a permutation of 0 .. N-1, so
+    MD_ERR_TOPOLOGY = -10,      /* the permanent ids are not a permutation of 0 .. N-1, so
                                    the chains of md_set_bonded are undefined */
+    MD_ERR_WORKSPACE_TOO_LARGE = -11 /* md_bind_static: the context needs more workspace than
+                                        MD_STATIC_WORKSPACE_BYTES */
 } md_status;
+
+/* Size of the library's own device workspace array used by md_bind_static
+ * (one per GPU, held until the process ends). */
+#define MD_STATIC_WORKSPACE_BYTES (64u << 20)
 
 enum { MD_LJ_SHIFTED = 0, MD_LJ_TRUNC = 1 };      /* potential */
 enum { MD_FP64 = 0, MD_FP32_MIXED = 1 };          /* precision */
@@ -235,6 +241,24 @@ md_status md_layout(const md_ctx* ctx, int32_t which, size_t* offset, size_t* co
  * the null stream).  Clears the device counters and flags (enqueued).  The
  * buffers must stay valid until the context is destroyed or bound again. */
 md_status md_bind(md_ctx* ctx, const md_buffers* bufs, void* hip_stream);
+
+/* md_bind_static: md_bind for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The caller still passes the state arrays; bufs->workspace must
+ * be NULL.  The workspace is taken from a static device array of
+ * MD_STATIC_WORKSPACE_BYTES (64 MiB; about 130 000 atoms of the dense LJ
+ * state, 250 000 of soft spheres) that the library holds on each GPU until
+ * the process ends; its used part is cleared on the stream (a fill kernel),
+ * then the device counters, as md_bind does.  Returns
+ * MD_ERR_WORKSPACE_TOO_LARGE, enqueuing nothing, when md_workspace_bytes(ctx)
+ * exceeds the array.  Neither this call nor any later call on the context
+ * allocates device memory (md_set_timing's events aside).  Every context
+ * bound this way on one GPU shares that GPU's array, which keeps the last
+ * call's contents: binding another context there overwrites the earlier
+ * one's cells, list and counters (rebind it before using it again), and
+ * calls of two such contexts that overlap in time race.  md_layout offsets
+ * are relative to the array, which the caller cannot address. */
+md_status md_bind_static(md_ctx* ctx, const md_buffers* bufs, void* hip_stream);
 
 /* md_build_cells (N1-N4, and the reorder): assign every atom to its cell,
  * group the slots by cell with ascending id inside a cell, and, with reorder

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <initializer_list>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -35,6 +36,8 @@ extern "C" const char* md_status_str(int32_t st)
         case MD_ERR_LAYER_OVERFLOW: return "layer matrix overflow: a cell held more atoms than layers";
         case MD_ERR_BOND_BROKEN: return "a bond reached the FENE limit R0";
         case MD_ERR_TOPOLOGY: return "atom ids are not a permutation of 0..N-1 (chains undefined)";
+        case MD_ERR_WORKSPACE_TOO_LARGE:
+            return "workspace larger than the library's static array (md_bind_static)";
         default: return "unknown status";
     }
 }
@@ -356,15 +359,18 @@ extern "C" md_status md_layout(const md_ctx* c, int32_t which, size_t* offset, s
     return MD_OK;
 }
 
-extern "C" md_status md_bind(md_ctx* c, const md_buffers* bf, void* stream)
+static bool state_buffers_ok(const md_buffers* bf)
 {
-    if (!c || !bf) return MD_ERR_ARG;
-    if (!bf->x || !bf->y || !bf->z || !bf->vx || !bf->vy || !bf->vz || !bf->fx || !bf->fy ||
-        !bf->fz || !bf->id || !bf->workspace)
-        return MD_ERR_ARG;
-    if (((uintptr_t)bf->workspace) % kAlign != 0) return MD_ERR_ARG;
+    return bf->x && bf->y && bf->z && bf->vx && bf->vy && bf->vz && bf->fx && bf->fy &&
+           bf->fz && bf->id;
+}
+
+// Points the kernel parameters at the caller's state arrays and at the
+// workspace regions inside ws, binds the stream, plans the tiles and
+// enqueues the clearing of the device counters.
+static md_status bind_to(md_ctx* c, const md_buffers* bf, char* ws, void* stream)
+{
     KParams& k = c->kp;
-    char* ws = static_cast<char*>(bf->workspace);
     auto at = [&](int r) -> void* { return c->bytes[r] ? ws + c->off[r] : nullptr; };
     k.x = bf->x; k.y = bf->y; k.z = bf->z;
     k.vx = bf->vx; k.vy = bf->vy; k.vz = bf->vz;
@@ -412,6 +418,63 @@ extern "C" md_status md_bind(md_ctx* c, const md_buffers* bf, void* stream)
     c->cells_ok = c->nl_ok = c->forces_ok = false;
     launch_clear(k, c->stream);
     return launched();
+}
+
+extern "C" md_status md_bind(md_ctx* c, const md_buffers* bf, void* stream)
+{
+    if (!c || !bf) return MD_ERR_ARG;
+    if (!state_buffers_ok(bf) || !bf->workspace) return MD_ERR_ARG;
+    if (((uintptr_t)bf->workspace) % kAlign != 0) return MD_ERR_ARG;
+    return bind_to(c, bf, static_cast<char*>(bf->workspace), stream);
+}
+
+// ---- binding to the library's own workspace (no allocation) ----
+//
+// One static device array per GPU holds the workspace of contexts bound
+// with md_bind_static.  In host code the array's name stands for a host
+// shadow, not for device memory, so its device address is looked up once
+// per device (with that device current) and only that address is used.
+
+static __device__ __align__(256) unsigned char scratch[MD_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // device address of scratch on each device
+}  // namespace
+
+static md_status static_workspace(void** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MD_ERR_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return MD_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return MD_ERR_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MD_OK;
+}
+
+extern "C" md_status md_bind_static(md_ctx* c, const md_buffers* bf, void* stream)
+{
+    if (!c || !bf) return MD_ERR_ARG;
+    if (!state_buffers_ok(bf) || bf->workspace) return MD_ERR_ARG;
+    if (c->ws_bytes > (size_t)MD_STATIC_WORKSPACE_BYTES) return MD_ERR_WORKSPACE_TOO_LARGE;
+    void* ws = nullptr;
+    md_status st = static_workspace(&ws);
+    if (st != MD_OK) return st;
+    // a caller-supplied workspace starts zeroed; so does this one, whatever
+    // an earlier binding left in it (a fill kernel, not a memset node, so the
+    // call may sit in a captured graph)
+    launch_fill(static_cast<double*>(ws), c->ws_bytes / sizeof(double), 0.0,
+                static_cast<hipStream_t>(stream));
+    st = launched();
+    if (st != MD_OK) return st;
+    return bind_to(c, bf, static_cast<char*>(ws), stream);
 }
 
 // The stages of either pipeline.

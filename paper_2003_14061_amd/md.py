@@ -29,6 +29,7 @@ MD_PIPE_TILED, MD_PIPE_LAYERS, MD_PIPE_ALLPAIRS = 0, 1, 2
  MD_ARR_LAYERS, MD_ARR_LAYER_COUNT) = range(8)
 
 EXPORTS = ("md_init", "md_workspace_bytes", "md_geometry", "md_layout", "md_bind",
+           "md_bind_static",
            "md_build_cells", "md_build_neighbors", "md_forces", "md_step", "md_reduce",
            "md_history", "md_set_tuning", "md_get_tuning", "md_set_timing", "md_get_timing",
            "md_export_neighbors", "md_traj_workspace_bytes", "md_traj_forward",
@@ -116,6 +117,7 @@ def lib():
         "md_geometry": (C.c_int, [P, C.POINTER(Grid)]),
         "md_layout": (C.c_int, [P, C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
         "md_bind": (C.c_int, [P, C.POINTER(Buffers), P]),
+        "md_bind_static": (C.c_int, [P, C.POINTER(Buffers), P]),
         "md_build_cells": (C.c_int, [P]),
         "md_build_neighbors": (C.c_int, [P]),
         "md_forces": (C.c_int, [P]),
@@ -202,6 +204,12 @@ def md_layout(ctx, which):
 
 def md_bind(ctx, bufs: Buffers, stream_handle: int):
     _check(lib().md_bind(ctx, C.byref(bufs), C.c_void_p(stream_handle)), "md_bind")
+
+
+def md_bind_static(ctx, bufs: Buffers, stream_handle: int):
+    """md_bind onto the library's own static workspace (bufs.workspace None)."""
+    _check(lib().md_bind_static(ctx, C.byref(bufs), C.c_void_p(stream_handle)),
+           "md_bind_static")
 
 
 def md_build_cells(ctx):
@@ -305,7 +313,7 @@ class Simulation:
     def __init__(self, pos, vel, L, *, r_cut, dt, skin=0.3, eps=1.0, sigma=1.0, mass=1.0,
                  shifted=True, precision="fp64", neighbor_list=True, reorder=None,
                  newton3=False, nl_capacity=0, block=256, pipeline="tiled", bonded=None,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, static_workspace=False):
         import torch
 
         if not torch.cuda.is_available():
@@ -347,14 +355,22 @@ class Simulation:
         self.fx, self.fy, self.fz = (torch.zeros(n, dtype=fdt, device=self.device)
                                      for _ in range(3))
         self.id = torch.arange(n, dtype=torch.int32, device=self.device)
+        state = [v.data_ptr() for v in (self.x, self.y, self.z, self.vx, self.vy, self.vz,
+                                         self.fx, self.fy, self.fz, self.id)]
+        self.static_workspace = bool(static_workspace)
+        if self.static_workspace:
+            # the library's own workspace array: nothing allocated for it here
+            self.workspace = None
+            self._ws_shift = 0
+            torch.cuda.synchronize(self.device)
+            md_bind_static(self.ctx, Buffers(*state, None), self.stream.cuda_stream)
+            return
         nbytes = md_workspace_bytes(self.ctx)
         # 256-byte alignment: torch's caching allocator returns 512-byte aligned blocks
         self.workspace = torch.zeros(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
         self._ws_shift = (-base) % 256
-        bufs = Buffers(*[v.data_ptr() for v in (self.x, self.y, self.z, self.vx, self.vy,
-                                                 self.vz, self.fx, self.fy, self.fz, self.id)],
-                       base + self._ws_shift)
+        bufs = Buffers(*state, base + self._ws_shift)
         torch.cuda.synchronize(self.device)
         md_bind(self.ctx, bufs, self.stream.cuda_stream)
 
@@ -466,6 +482,8 @@ class Simulation:
     def ws_array(self, which, dtype):
         import torch
 
+        if self.workspace is None:
+            raise RuntimeError("the workspace of a static binding is not addressable")
         off, cnt = md_layout(self.ctx, which)
         es = torch.empty((), dtype=dtype).element_size()
         start = self._ws_shift + off
