@@ -24,11 +24,14 @@ sys.path.insert(0, ROOT)
 METRIC = "atom-steps/sec at N=2.05M LJ (FP64 vs FP32-mixed); adjoint/forward time ratio"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6   # MI355X dense FP64 vector
-FP32_PEAK_TFS = 157.3  # MI355X FP32 vector
+# FP32 vector: the published 157.3 TFLOP/s counts packed FP32 (two lanes per
+# instruction), which this build switches off, so plain FP32 issues at the
+# FP64 rate
+FP32_PEAK_TFS = 78.6
 FORCE_SOURCES = ("paper_2003_14061_amd/csrc/md_forces.hip", "paper_2003_14061_amd/csrc/md_tiles.h",
                  "paper_2003_14061_amd/csrc/md_pair.h",
                  "paper_2003_14061_amd/csrc/md_device.h", "paper_2003_14061_amd/csrc/md_internal.h")
-TRAFFIC_FILE = "profiles/k_forces_tiles_lj_2048k_traffic.txt"
+PROFILES = "profiles"
 
 
 def parse():
@@ -38,7 +41,16 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="lj_2048k")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=24,
+                    help="steps of the CPU oracle sample (from the melted FP64 GPU state; "
+                         "the list is rebuilt about every 11 steps there)")
+    ap.add_argument("--drift-steps", type=int, default=1000,
+                    help="untimed steps after the timed ones, energy recorded every 10, "
+                         "for the energy-drift slope")
+    ap.add_argument("--batch-steps", type=int, default=500,
+                    help="steps of the batched ensemble's timed graph launch")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 4000-atom cells-only and 256 000-atom WCA lines")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-mixed measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--no-newton3", action="store_true",
@@ -80,29 +92,57 @@ def force_sources_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n_atoms, precision):
-    """HBM bytes per force-pass launch from the committed rocprofv3 counter
-    summary, or None when it is missing, for another workload or precision,
-    or taken on other kernel sources."""
-    path = os.path.join(ROOT, TRAFFIC_FILE)
-    if not os.path.exists(path):
+def measured_traffic(n_atoms, precision, kernel="k_forces_tiles"):
+    """HBM bytes per force-pass launch from a committed rocprofv3 counter
+    summary (profiles/*_traffic.txt) for this kernel, atom count and
+    precision, taken on the current kernel sources; None when there is none."""
+    d = os.path.join(ROOT, PROFILES)
+    if not os.path.isdir(d):
         return None
-    kv = {}
-    with open(path) as fh:
-        for line in fh:
-            if ":" in line and not line.startswith("#"):
-                k, v = line.split(":", 1)
-                kv[k.strip()] = v.strip()
-    try:
-        if (kv.get("sources_sha256") != force_sources_hash() or
-                int(kv.get("n_atoms", -1)) != n_atoms or kv.get("precision") != precision):
-            return None
-        return float(kv["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    h = force_sources_hash()
+    for name in sorted(os.listdir(d)):
+        if not name.endswith("_traffic.txt"):
+            continue
+        kv = {}
+        with open(os.path.join(d, name)) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        try:
+            if (kv.get("sources_sha256") == h and int(kv.get("n_atoms", -1)) == n_atoms and
+                    kv.get("precision") == precision and
+                    kv.get("kernel", "").split("<")[0].endswith(kernel)):
+                return float(kv["hbm_bytes_per_launch"])
+        except (KeyError, ValueError):
+            continue
+    return None
 
 
-def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled", detail=True):
+def energy_drift(sim, w, steps, every=10):
+    """Total energy per atom over `steps` further steps, recorded every
+    `every`: least-squares slope per unit time, RMS about the line, and the
+    change end to start."""
+    import numpy as np
+
+    if steps <= 0:
+        return None
+    sim.step(steps, record_every=every)
+    h = sim.history()
+    if len(h) < 3:
+        return None
+    t = h["step"].astype(np.float64) * w.dt
+    e = (h["U"] + h["K"]) / w.n
+    slope, icpt = np.polyfit(t - t[0], e, 1)
+    resid = e - (icpt + slope * (t - t[0]))
+    return {"steps": int(steps), "records": int(len(h)), "every": every,
+            "slope_per_atom_per_time": float(slope),
+            "rms_about_fit_per_atom": float(np.sqrt(np.mean(resid ** 2))),
+            "change_per_atom": float(e[-1] - e[0]), "e_per_atom_start": float(e[0])}
+
+
+def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled", detail=True,
+            drift_steps=0, keep_state=False):
     import torch
 
     from paper_2003_14061_amd import md
@@ -129,6 +169,7 @@ def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled", detail
         res = {"value": w.n * steps / wall, "ms_per_step": 1e3 * wall / steps,
                "force_ms_avg": f_ms / max(f_launches, 1), "energy_drift_per_atom": e1 - e0,
                "rebuilds": int(o1["n_rebuilds"] - o0["n_rebuilds"])}
+        res["energy_drift"] = energy_drift(sim, w, drift_steps)
         del sim
         torch.cuda.synchronize()
         return res
@@ -161,33 +202,44 @@ def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled", detail
                                "flops_per_atom": round(force_flops_per_atom(mean_nl,
                                                                             mean_in_range), 1)}}
     res["mean_in_range"] = mean_in_range
-    res["final_pos"] = sim.state()["pos"]
+    st = sim.state()
+    res["final_pos"] = st["pos"]
+    if keep_state:
+        res["final_vel"] = st["vel"]
+    res["energy_drift"] = energy_drift(sim, w, drift_steps)
     del sim
     torch.cuda.synchronize()
     return res
 
 
-def force_error_fp32(w, pos):
-    """Per-step force error of the FP32-mixed path: its forces against the FP64
-    path's on the same positions (the state the FP64 run ended in), per atom
-    relative to the largest FP64 force and normwise."""
+def error_fp32(w, pos, vel):
+    """Per-step error of the FP32-mixed path, observable by observable: its
+    forces, U, W, K, T and pressure against the FP64 path's on the same state
+    (the state the FP64 run ended in).  The FP64 path itself matches the FP64
+    oracle to 1e-12 (the parity tests, also at this size); forces per atom
+    relative to the largest FP64 force and normwise, the scalars relative."""
     import numpy as np
     import torch
 
     from paper_2003_14061_amd import md
 
-    f = {}
+    f, o = {}, {}
     for prec in ("fp64", "fp32"):
-        sim = md.Simulation(pos, np.zeros_like(pos), w.L, r_cut=w.r_cut, skin=w.skin, dt=w.dt,
+        sim = md.Simulation(pos, vel, w.L, r_cut=w.r_cut, skin=w.skin, dt=w.dt,
                             shifted=w.shifted, precision=prec)
         sim.prepare()
         f[prec] = sim.state()["f"]
+        o[prec] = sim.reduce()
         del sim
         torch.cuda.synchronize()
     d = np.linalg.norm(f["fp32"] - f["fp64"], axis=1)
     scale = float(np.linalg.norm(f["fp64"], axis=1).max())
-    return {"max_per_atom_rel_to_max_force": float(d.max() / scale),
-            "normwise": float(np.linalg.norm(f["fp32"] - f["fp64"]) / np.linalg.norm(f["fp64"]))}
+    out = {"F_max_per_atom_rel_to_max_force": float(d.max() / scale),
+           "F_normwise": float(np.linalg.norm(f["fp32"] - f["fp64"]) /
+                               np.linalg.norm(f["fp64"]))}
+    for k in ("U", "W", "K", "T", "pressure"):
+        out[k + "_rel"] = float(abs(o["fp32"][k] - o["fp64"][k]) / abs(o["fp64"][k]))
+    return out
 
 
 # FP64 lane operations the all-pairs test needs per ordered pair: three
@@ -242,6 +294,39 @@ def run_allpairs():
               file=sys.stderr, flush=True)
     return {"workload": "WCA (LJ cut and shifted at r_c=2^(1/6) sigma), FCC, rho=0.8, T=1, "
                         "dt=0.005; list pipelines with skin 0.3", "by_n": out}
+
+
+def run_small(drift_steps):
+    """The two smaller workloads.  wca_4000: soft spheres (WCA), N=4000
+    (10^3 FCC), rho 0.8, T 1, dt 0.005, cells only, 1000 steps, FP64: the
+    whole state fits in L2, so the step time is launch latency.  wca_256k:
+    WCA, N=256 000 (40^3 FCC), rho 0.8, T 1, dt 0.005, skin 0.3, 2000 steps,
+    FP64 and FP32-mixed; the analogue of the soft-sphere rows of the paper's
+    Table 1."""
+    from paper_2003_14061_amd import inputs
+
+    w1 = inputs.preset("wca_4000").materialize()
+    c1 = run_gpu(w1, "fp64", 1000, 100, detail=False, drift_steps=drift_steps)
+    c1 = {"workload": "wca_4000: WCA (LJ cut and shifted at 2^(1/6) sigma), N=4000 FCC, "
+                      "rho=0.8, T=1, dt=0.005, cells only, FP64, 1000 steps",
+          "value": round(c1["value"], 1), "us_per_step": round(1e3 * c1["ms_per_step"], 3),
+          "force_us_avg": round(1e3 * c1["force_ms_avg"], 3),
+          "energy_drift": c1["energy_drift"]}
+    print(f"[bench] wca_4000 done: {c1['value']:.3e} atom-steps/s", file=sys.stderr, flush=True)
+    w2 = inputs.preset("wca_256k").materialize()
+    c2 = {"workload": "wca_256k: WCA, N=256000 FCC, rho=0.8, T=1, dt=0.005, skin 0.3, "
+                      "2000 steps"}
+    for prec in ("fp64", "fp32"):
+        r = run_gpu(w2, prec, 2000, 100, drift_steps=drift_steps)
+        c2[prec if prec == "fp64" else "fp32_mixed"] = {
+            "value": round(r["value"], 1), "us_per_step": round(1e3 * r["ms_per_step"], 3),
+            "force_us_avg": round(1e3 * r["force_ms_avg"], 3), "rebuilds": r["rebuilds"],
+            "mean_nl": round(r["mean_nl"], 2), "roofline": r["roofline"],
+            "energy_drift": r["energy_drift"]}
+    c2["fp32_speedup"] = round(c2["fp32_mixed"]["value"] / c2["fp64"]["value"], 3)
+    print(f"[bench] wca_256k done: {c2['fp64']['value']:.3e} atom-steps/s", file=sys.stderr,
+          flush=True)
+    return c1, c2
 
 
 POLYMER_BONDED = dict(fene_k=30.0, fene_r0=1.5, bend_k=1.5)
@@ -416,23 +501,45 @@ def in_range_pairs(sim, w, sample=20000):
     return tot / len(idx)
 
 
-def run_cpu(w, steps):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def run_cpu(w, steps, pos=None, vel=None):
+    """The oracle on the host cores: `steps` steps of the same system from
+    the given state (the melted state of the FP64 GPU run, else the FCC
+    start), timed minus its initial cell/list/force build."""
     import oracle
 
+    import numpy as np
+
+    start = "the melted state the FP64 GPU run ended in"
+    if pos is None:
+        pos, vel, start = w.pos, w.vel, "the FCC start"
+    pos = np.mod(pos, w.L)  # between list builds positions may sit outside [0, L)
+    pos[pos >= w.L] = 0.0
     s = oracle.make_sys(w.n, w.L, r_cut=w.r_cut, skin=w.skin, dt=w.dt,
                         potential=oracle.LJ_SHIFTED if w.shifted else oracle.LJ_TRUNC,
                         use_nl=w.use_nl)
     t = time.perf_counter()
-    oracle.run(s, w.pos, w.vel, 0)
+    oracle.run(s, pos, vel, 0)
     t_build = time.perf_counter() - t
     t = time.perf_counter()
-    oracle.run(s, w.pos, w.vel, steps)
+    nreb = oracle.run(s, pos, vel, steps)[4]
     t_run = time.perf_counter() - t
     per = max(t_run - t_build, 1e-9)
     return {"value": w.n * steps / per, "unit": "atom-steps/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"{w.name}: full N={w.n}, {steps} steps from the FCC start; time of "
-                      f"the run minus the time of its initial cell/list/force build"}
+            "kind": "oracle", "cpu_model": cpu_model(), "rebuilds": int(nreb),
+            "sample": f"{w.name}: full N={w.n}, {steps} steps from {start}, {nreb} list "
+                      f"rebuilds inside; time of the run minus the time of its initial "
+                      f"cell/list/force build"}
 
 
 def copy_probe(mib):
@@ -462,12 +569,13 @@ def main():
     w = inputs.preset(args.workload).materialize()
     fp64 = None
     if not args.no_main:
-        fp64 = run_gpu(w, "fp64", args.steps, args.warmup)
+        fp64 = run_gpu(w, "fp64", args.steps, args.warmup, drift_steps=args.drift_steps,
+                       keep_state=True)
         print(f"[bench] fp64 done: {fp64['value']:.3e} atom-steps/s", file=sys.stderr,
               flush=True)
     mixed = None
     if not args.no_mixed:
-        mixed = run_gpu(w, "fp32", args.steps, args.warmup)
+        mixed = run_gpu(w, "fp32", args.steps, args.warmup, drift_steps=args.drift_steps)
         print(f"[bench] fp32-mixed done: {mixed['value']:.3e} atom-steps/s", file=sys.stderr,
               flush=True)
     lay = None
@@ -484,7 +592,8 @@ def main():
         copy_probe(args.copy_probe_mib)
     cpu = None
     if not args.no_cpu:
-        cpu = run_cpu(w, args.cpu_steps)
+        cpu = run_cpu(w, args.cpu_steps, *((fp64["final_pos"], fp64["final_vel"])
+                                           if fp64 is not None else (None, None)))
         print(f"[bench] cpu oracle done: {cpu['value']:.3e} atom-steps/s", file=sys.stderr,
               flush=True)
     if fp64 is None:  # a profiling run of the other legs: no headline figure
@@ -515,12 +624,15 @@ def main():
         "mean_nl": round(fp64["mean_nl"], 2),
         "mean_in_range": round(fp64["mean_in_range"], 2),
         "energy_drift_per_atom": fp64["energy_drift_per_atom"],
+        "energy_drift": fp64.get("energy_drift"),
         "force_ms_avg": round(fp64["force_ms_avg"], 5),
     }
     if mixed is not None:
-        ferr = force_error_fp32(w, fp64["final_pos"]) if "final_pos" in fp64 else None
+        ferr = (error_fp32(w, fp64["final_pos"], fp64["final_vel"])
+                if "final_vel" in fp64 else None)
         out["fp32_mixed"] = {"value": round(mixed["value"], 1),
-                             "force_error_vs_fp64": ferr,
+                             "error_vs_fp64": ferr,
+                             "energy_drift": mixed["energy_drift"],
                              "ms_per_step": round(mixed["ms_per_step"], 5),
                              "roofline": mixed["roofline"], "rebuilds": mixed["rebuilds"],
                              "energy_drift_per_atom": mixed["energy_drift_per_atom"],
@@ -543,12 +655,14 @@ def main():
                                "energy_drift_per_atom": n3["energy_drift_per_atom"],
                                "speedup_vs_full_list": round(n3["value"] / fp64["value"], 3),
                                "kernels": "k_zero_forces + k_forces_half"}
+    if not args.no_small:
+        out["wca_4000_cells"], out["wca_256k"] = run_small(args.drift_steps)
     if not args.no_batch:
-        bt = run_batch()
+        bt = run_batch(steps=args.batch_steps)
         print(f"[bench] batch done: {bt['value']:.3e} atom-steps/s", file=sys.stderr, flush=True)
         out["batched_ensemble"] = dict(bt, workload="64 WCA replicas, N~U[500,32000], "
                                        "rho~U[0.6,0.9], T=1, dt=0.005, skin 0.3, FP32-mixed, "
-                                       "one HIP graph launch per 500 steps")
+                                       f"one HIP graph launch per {args.batch_steps} steps")
     if not args.no_allpairs:
         out["paper_allpairs"] = run_allpairs()
     if not args.no_polymer:

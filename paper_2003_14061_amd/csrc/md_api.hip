@@ -245,6 +245,7 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
     }
     k.half_shift = 0.5 * shift;
     k.ushift = k.half_shift / k.eps2;
+    k.ushift2 = 2.0 * k.ushift;
     k.hdt = (0.5 * p.dt) / p.mass;
     k.dt = p.dt;
     k.disp_thr2 = (0.5 * p.skin) * (0.5 * p.skin);

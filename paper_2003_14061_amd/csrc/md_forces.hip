@@ -191,13 +191,13 @@ __global__ __attribute__((amdgpu_waves_per_eu(6))) void k_forces_tiles(B b)
     double e[2] = {0.0, 0.0};
     for (int hb = 0; hb < nh; hb += per_pass) {
         const int h = hb + threadIdx.x / LANES;
-        Acc a;
+        LeanOf<F> a;
         int slot_i = 0;
         if (h < nh) {
             slot_i = atom_at(p, slot0 + h);
             double xi, yi, zi;
             home_position(p, s, h0, h, slot_i, xi, yi, zi);
-            ForceOp<Acc> op{p, a};
+            ForceOp<LeanOf<F>> op{p, a};
             // the lane's list-row offset is formed here for each pass: hoisted out
             // of the pass loop it is a 64-bit value live across the whole kernel
             // (the empty asm hides that sub is the same in every pass)
@@ -209,18 +209,19 @@ __global__ __attribute__((amdgpu_waves_per_eu(6))) void k_forces_tiles(B b)
             a.fx = lane_group_sum<LANES>(a.fx);
             a.fy = lane_group_sum<LANES>(a.fy);
             a.fz = lane_group_sum<LANES>(a.fz);
-            a.u = lane_group_sum<LANES>(a.u);
-            a.w = lane_group_sum<LANES>(a.w);
+            a.q = lane_group_sum<LANES>(a.q);
+            a.s6 = lane_group_sum<LANES>(a.s6);
         }
         if (h < nh && sub == 0) {
-            static_cast<F*>(p.fx)[slot_i] = a.fx;
-            static_cast<F*>(p.fy)[slot_i] = a.fy;
-            static_cast<F*>(p.fz)[slot_i] = a.fz;
-            // per-atom energy: half of each pair's 4 eps (sr12 - sr6) - shift
-            const double ui = p.eps2 * (double)a.u;
+            F fx, fy, fz;
+            double ui, wi;
+            lean_finish(p, a, fx, fy, fz, ui, wi);
+            static_cast<F*>(p.fx)[slot_i] = fx;
+            static_cast<F*>(p.fy)[slot_i] = fy;
+            static_cast<F*>(p.fz)[slot_i] = fz;
             e[0] += ui;
-            e[1] += 0.5 * (double)a.w;
-            if (!isfinite(ui + (double)a.fx + (double)a.fy + (double)a.fz))
+            e[1] += wi;
+            if (!isfinite(ui + (double)fx + (double)fy + (double)fz))
                 atomicOr(&p.dev->flags, (int)MD_FLAG_NONFINITE);
         }
     }
@@ -276,7 +277,7 @@ __global__ void k_forces_cells(B b)
     if (!b.fetch(G_TILES, wg, p)) return;
     __shared__ double red[(1024 / kWave) * 2];
     const int i = xcd_tile(wg.id, wg.n) * blockDim.x + threadIdx.x;
-    Acc a;
+    LeanOf<F> a;
     if (i < p.n) {
         const int c = p.cell_of[i], nc = p.nc;
         const int cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
@@ -286,15 +287,17 @@ __global__ void k_forces_cells(B b)
             walk_cells<true>(p, i, a);
         else
             walk_cells<false>(p, i, a);
-        static_cast<F*>(p.fx)[i] = a.fx;
-        static_cast<F*>(p.fy)[i] = a.fy;
-        static_cast<F*>(p.fz)[i] = a.fz;
     }
-    double e[2];
-    e[0] = i < p.n ? p.eps2 * (double)a.u : 0.0;
-    e[1] = i < p.n ? 0.5 * (double)a.w : 0.0;
-    if (i < p.n && !isfinite(e[0] + (double)a.fx + (double)a.fy + (double)a.fz))
-        atomicOr(&p.dev->flags, (int)MD_FLAG_NONFINITE);
+    double e[2] = {0.0, 0.0};
+    if (i < p.n) {
+        F fx, fy, fz;
+        lean_finish(p, a, fx, fy, fz, e[0], e[1]);
+        static_cast<F*>(p.fx)[i] = fx;
+        static_cast<F*>(p.fy)[i] = fy;
+        static_cast<F*>(p.fz)[i] = fz;
+        if (!isfinite(e[0] + (double)fx + (double)fy + (double)fz))
+            atomicOr(&p.dev->flags, (int)MD_FLAG_NONFINITE);
+    }
     block_sum<2>(e, red);
     if (threadIdx.x == 0) {
         p.fpart[2 * wg.id] = e[0];

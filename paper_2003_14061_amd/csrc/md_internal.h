@@ -42,6 +42,7 @@ struct KParams {
     // constants (all formed once on the host)
     double L, invL, inv_w, rc2, rl2, sig2, eps2, eps48, half_shift, hdt, dt, disp_thr2, mass;
     double ushift;          // half_shift / eps2: the shift in the units of the u sums
+    double ushift2;         // 2 ushift = shift / (2 eps): the constant of the lean sums
     double eps, sigma;
     double inner_lo, inner_hi;  // atoms with every coordinate in [lo, hi] need no minimum image
     // state (caller-owned)

@@ -106,3 +106,46 @@ def test_cells_only_wca_4000_conserves_over_1000_steps():
     s = oracle.make_sys(w.n, w.L, r_cut=w.r_cut, dt=w.dt, use_nl=False)
     _, _, _, o_ref, _ = oracle.run(s, w.pos, w.vel, 10)
     assert h["U"][0] == pytest.approx(o_ref["U"][9], rel=1e-10, abs=1e-10)
+
+
+def test_fp32_mixed_error_per_observable_on_the_lj_2048k_state(capsys):
+    # The state of a 30-step FP64 run of the 2.048M-atom LJ system; the
+    # FP32-mixed force pass on it against the FP64 oracle over every atom:
+    # forces (per atom against S_i, and normwise), U, W, K, T and pressure.
+    w = inputs.preset("lj_2048k").materialize()
+    run = md.Simulation(w.pos, w.vel, w.L, r_cut=w.r_cut, skin=w.skin, dt=w.dt)
+    run.prepare()
+    run.step(STEPS["lj_2048k"])
+    st = run.state()
+    del run
+    pos = np.mod(st["pos"], w.L)
+    pos[pos >= w.L] = 0.0
+    vel = st["vel"]
+    sim = md.Simulation(pos, vel, w.L, r_cut=w.r_cut, skin=w.skin, dt=w.dt, precision="fp32")
+    sim.prepare()
+    obs = sim.reduce()
+    f32 = sim.state()["f"]
+    s = oracle.make_sys(w.n, w.L, r_cut=w.r_cut, skin=w.skin, dt=w.dt,
+                        nl_cap=sim.grid.nl_capacity)
+    del sim
+    nc = oracle.cells_per_side(w.L, w.r_cut + w.skin)
+    cells = oracle.build_cells(s, nc, pos)
+    cnt, nl, _ = oracle.build_nl(s, nc, pos, cells)
+    ref = oracle.forces_nl(s, pos, cnt, nl)
+    per_atom, normwise = force_errors(f32, ref)
+    U, W = ref["u"].sum(), ref["w"].sum()
+    K = oracle.kinetic(s, vel)
+    V = w.L ** 3
+    T = 2.0 * K / (3.0 * (w.n - 1))
+    P = (2.0 * K + W) / (3.0 * V)
+    err = {"F_per_atom": per_atom, "F_normwise": normwise,
+           "U": abs(obs["U"] - U) / abs(U), "W": abs(obs["W"] - W) / abs(W),
+           "K": abs(obs["K"] - K) / K, "T": abs(obs["T"] - T) / T,
+           # relative to the scale of its two terms (P itself can be near 0)
+           "pressure": abs(obs["pressure"] - P) / ((2.0 * K + abs(W)) / (3.0 * V))}
+    with capsys.disabled():
+        print("\nFP32-mixed vs FP64 oracle, lj_2048k state after 30 steps: " +
+              ", ".join(f"{k} {v:.2e}" for k, v in err.items()), flush=True)
+    for k, v in err.items():
+        assert v <= TOL["fp32"], (k, v)
+    assert err["K"] <= 1e-13 and err["T"] <= 1e-13  # integration and K stay FP64
