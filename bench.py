@@ -151,22 +151,33 @@ def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled", detail
                         shifted=w.shifted, precision=precision, neighbor_list=w.use_nl,
                         newton3=newton3, pipeline=pipeline)
     sim.prepare()
-    sim.step(warmup)
+    sim.step(warmup)  # more than 32 steps: md_step captures its graph here
     o0 = sim.reduce()
     e0 = (o0["U"] + o0["K"]) / w.n
-    sim.set_timing(True)
+    # the timed run: md_step as it runs by default (graph replays)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    f_ms, f_launches = sim.get_timing()
-    sim.set_timing(False)
     o1 = sim.reduce()
     e1 = (o1["U"] + o1["K"]) / w.n
+    # the same number of steps with every force launch bracketed by HIP events
+    # on the bound stream (direct launches of the same kernels): the force
+    # kernel's average duration, and the step rate without the graph
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    f_ms, f_launches = sim.get_timing()
+    sim.set_timing(False)
+    direct = w.n * steps / (t3 - t2)
     if not detail:
         wall = t1 - t0
         res = {"value": w.n * steps / wall, "ms_per_step": 1e3 * wall / steps,
+               "value_direct_launches": direct,
                "force_ms_avg": f_ms / max(f_launches, 1), "energy_drift_per_atom": e1 - e0,
                "rebuilds": int(o1["n_rebuilds"] - o0["n_rebuilds"])}
         res["energy_drift"] = energy_drift(sim, w, drift_steps)
@@ -180,6 +191,7 @@ def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled", detail
     res = {
         "value": w.n * steps / wall,
         "ms_per_step": 1e3 * wall / steps,
+        "value_direct_launches": direct,
         "force_ms_avg": f_ms / max(f_launches, 1),
         "force_launches": f_launches,
         "mean_nl": mean_nl,
@@ -310,6 +322,7 @@ def run_small(drift_steps):
     c1 = {"workload": "wca_4000: WCA (LJ cut and shifted at 2^(1/6) sigma), N=4000 FCC, "
                       "rho=0.8, T=1, dt=0.005, cells only, FP64, 1000 steps",
           "value": round(c1["value"], 1), "us_per_step": round(1e3 * c1["ms_per_step"], 3),
+          "value_direct_launches": round(c1["value_direct_launches"], 1),
           "force_us_avg": round(1e3 * c1["force_ms_avg"], 3),
           "energy_drift": c1["energy_drift"]}
     print(f"[bench] wca_4000 done: {c1['value']:.3e} atom-steps/s", file=sys.stderr, flush=True)
@@ -320,6 +333,7 @@ def run_small(drift_steps):
         r = run_gpu(w2, prec, 2000, 100, drift_steps=drift_steps)
         c2[prec if prec == "fp64" else "fp32_mixed"] = {
             "value": round(r["value"], 1), "us_per_step": round(1e3 * r["ms_per_step"], 3),
+            "value_direct_launches": round(r["value_direct_launches"], 1),
             "force_us_avg": round(1e3 * r["force_ms_avg"], 3), "rebuilds": r["rebuilds"],
             "mean_nl": round(r["mean_nl"], 2), "roofline": r["roofline"],
             "energy_drift": r["energy_drift"]}
@@ -626,6 +640,8 @@ def main():
         "energy_drift_per_atom": fp64["energy_drift_per_atom"],
         "energy_drift": fp64.get("energy_drift"),
         "force_ms_avg": round(fp64["force_ms_avg"], 5),
+        "value_direct_launches": (round(fp64["value_direct_launches"], 1)
+                                  if "value_direct_launches" in fp64 else None),
     }
     if mixed is not None:
         ferr = (error_fp32(w, fp64["final_pos"], fp64["final_vel"])

@@ -298,6 +298,19 @@ md_status md_forces(md_ctx* ctx);
  * overwritten).  Enqueued. */
 md_status md_step(md_ctx* ctx, int32_t n_steps, int32_t record_every);
 
+/* md_set_graph: with enable != 0 md_step replays runs of 32 steps from a HIP
+ * graph captured at its first use (recaptured after md_bind, md_set_tuning or
+ * a different record_every); the first step of a call and the remainder are
+ * launched directly.  The default is on for systems of at most 131 072 atoms,
+ * whose steps are bound by launch latency, and off above (measured on
+ * MI355X: graph replays pay less per idle kernel but slightly more between
+ * long ones).  When the bound stream is the
+ * null stream the graph runs on a stream of the context's own, ordered after
+ * the bound stream's earlier work and before its later work by events.
+ * enable = 0 launches every kernel directly.  Results are identical either
+ * way; md_set_timing also selects the direct launches. */
+md_status md_set_graph(md_ctx* ctx, int32_t enable);
+
 /* md_reduce (F2): finish the reductions on the device (kinetic energy,
  * momentum, the potential energy and virial of the last force pass) and
  * copy them to *out.  Synchronizes the stream.  Returns the latched device

@@ -117,6 +117,9 @@ static void relayout(md_ctx* c)
 
 static md_status launched() { return hip_ok(hipGetLastError()); }
 
+static void drop_graph(md_ctx* c);  // md_step's captured graph (below)
+constexpr int kGraphAtoms = 131072;  // md_step graph on by default up to this size
+
 extern "C" md_status md_init(const md_params* in, md_ctx** out)
 {
     if (!in || !out) return MD_ERR_ARG;
@@ -154,6 +157,7 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
     md_ctx* c = new (std::nothrow) md_ctx();
     if (!c) return MD_ERR_ARG;
     c->prm = p;
+    c->graph_on = p.n_atoms <= kGraphAtoms;
     const int64_t n = p.n_atoms;
     const int npad = (int)((n + 63) / 64 * 64);
     int cap = 0;
@@ -372,6 +376,7 @@ static bool state_buffers_ok(const md_buffers* bf)
 static md_status bind_to(md_ctx* c, const md_buffers* bf, char* ws, void* stream)
 {
     KParams& k = c->kp;
+    drop_graph(c);  // the pointers are baked into it
     auto at = [&](int r) -> void* { return c->bytes[r] ? ws + c->off[r] : nullptr; };
     k.x = bf->x; k.y = bf->y; k.z = bf->z;
     k.vx = bf->vx; k.vy = bf->vy; k.vz = bf->vz;
@@ -593,26 +598,127 @@ extern "C" md_status md_forces(md_ctx* c)
     return launched();
 }
 
+// ---- md_step ----
+//
+// A step is a fixed launch sequence (integrate, the rebuild-gated cell and
+// list kernels, forces), so runs of kGraphSteps steps can be captured once
+// into a HIP graph and replayed.  Measured on MI355X: an idle kernel costs
+// about 1.6 us from a graph against 2.7 us launched on a stream, and the
+// 4000-atom cells-only system steps 8% faster from the graph; with kernels of
+// tens of microseconds and more the graph is 1.5-2% slower (256 000 and 2.048M
+// atoms), so the graph is on by default up to kGraphAtoms atoms
+// (md_set_graph overrides).  The first step of a call (its integrate kernel
+// only kicks and drifts) and the remainder are launched directly.  Timing
+// (md_set_timing) brackets each force launch with events and uses the direct
+// path throughout.
+
+constexpr int kGraphSteps = 32;
+
+static void drop_graph(md_ctx* c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->g_record = -1;
+    c->g_run = nullptr;
+}
+
+// Launches of n steps; first: the first of them is the first step of the run.
+static md_status step_launches(md_ctx* c, hipStream_t s, bool first, int32_t n,
+                               int32_t record_every)
+{
+    const KParams& k = c->kp;
+    const bool nl = c->prm.mode == MD_NEIGHBOR_LIST;
+    for (int32_t i = 0; i < n; ++i) {
+        launch_integrate(k, first && i == 0 ? 0 : 1, record_every, s);
+        cells_any(k, 0, s);
+        if (nl) neighbors_any(k, 0, s);
+        if (s == c->stream) {
+            timed_forces(c);
+            if (c->timing && c->ev_pending.size() >= 8192) {
+                md_status st = fold_timing(c);
+                if (st != MD_OK) return st;
+            }
+        } else {
+            forces_any(k, s);
+        }
+    }
+    return MD_OK;
+}
+
+// n_graphs replays of the kGraphSteps-step graph, captured first if needed.
+// The null stream cannot be captured: then the graph runs on the context's own
+// stream, ordered after and before the bound stream's work by events.
+static md_status step_graphs(md_ctx* c, int32_t n_graphs, int32_t record_every)
+{
+    hipStream_t run = c->stream;
+    const bool own = run == nullptr;
+    if (own) {
+        if (!c->gstream &&
+            hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess)
+            return MD_ERR_HIP;
+        for (int e = 0; e < 2; ++e)
+            if (!c->gev[e] &&
+                hipEventCreateWithFlags(&c->gev[e], hipEventDisableTiming) != hipSuccess)
+                return MD_ERR_HIP;
+        run = c->gstream;
+    }
+    if (!(c->gexec && c->g_record == record_every && c->g_run == run)) {
+        drop_graph(c);
+        if (hipStreamBeginCapture(run, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return MD_ERR_HIP;
+        const md_status st = step_launches(c, run, false, kGraphSteps, record_every);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(run, &g);
+        if (st != MD_OK) return st;
+        if (ec != hipSuccess || !g) return MD_ERR_HIP;
+        c->graph = g;
+        if (hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0) != hipSuccess) {
+            drop_graph(c);
+            return MD_ERR_HIP;
+        }
+        c->g_record = record_every;
+        c->g_run = run;
+    }
+    if (own && (hipEventRecord(c->gev[0], c->stream) != hipSuccess ||
+                hipStreamWaitEvent(run, c->gev[0], 0) != hipSuccess))
+        return MD_ERR_HIP;
+    for (int32_t g = 0; g < n_graphs; ++g)
+        if (hipGraphLaunch(c->gexec, run) != hipSuccess) return MD_ERR_HIP;
+    if (own && (hipEventRecord(c->gev[1], run) != hipSuccess ||
+                hipStreamWaitEvent(c->stream, c->gev[1], 0) != hipSuccess))
+        return MD_ERR_HIP;
+    return MD_OK;
+}
+
 extern "C" md_status md_step(md_ctx* c, int32_t n_steps, int32_t record_every)
 {
     if (!c || n_steps < 0 || record_every < 0) return MD_ERR_ARG;
     if (!c->bound) return MD_ERR_NOT_BOUND;
     if (!c->forces_ok) return MD_ERR_STATE;
     if (n_steps == 0) return MD_OK;
-    const KParams& k = c->kp;
-    const bool nl = c->prm.mode == MD_NEIGHBOR_LIST;
-    for (int32_t s = 0; s < n_steps; ++s) {
-        launch_integrate(k, s == 0 ? 0 : 1, record_every, c->stream);
-        cells_any(k, 0, c->stream);
-        if (nl) neighbors_any(k, 0, c->stream);
-        timed_forces(c);
-        if (c->timing && c->ev_pending.size() >= 8192) {
-            md_status st = fold_timing(c);
-            if (st != MD_OK) return st;
-        }
+    md_status st;
+    if (c->timing || !c->graph_on || n_steps <= kGraphSteps) {
+        st = step_launches(c, c->stream, true, n_steps, record_every);
+    } else {
+        const int32_t rest = n_steps - 1, n_graphs = rest / kGraphSteps;
+        st = step_launches(c, c->stream, true, 1, record_every);
+        if (st == MD_OK) st = step_graphs(c, n_graphs, record_every);
+        if (st == MD_OK)
+            st = step_launches(c, c->stream, false, rest - n_graphs * kGraphSteps, record_every);
     }
-    launch_integrate(k, 2, record_every, c->stream);
+    if (st != MD_OK) return st;
+    launch_integrate(c->kp, 2, record_every, c->stream);
     return launched();
+}
+
+extern "C" md_status md_set_graph(md_ctx* c, int32_t enable)
+{
+    if (!c) return MD_ERR_ARG;
+    c->graph_on = enable != 0;
+    if (!c->graph_on) drop_graph(c);
+    return MD_OK;
 }
 
 extern "C" md_status md_reduce(md_ctx* c, md_observables* out)
@@ -943,6 +1049,7 @@ extern "C" md_status md_set_tuning(md_ctx* c, const md_tuning* t)
         !one_of(t->nl_method, {MD_NL_AUTO, MD_NL_LANES, MD_NL_CELL_WAVES}))
         return MD_ERR_ARG;
     KParams& k = c->kp;
+    drop_graph(c);  // launch shapes and parameters are baked into it
     const int old_tiles = k.n_tiles, old_cells = c->tile_cells;
     k.force_lanes = t->force_lanes;
     k.force_block = t->force_block;
@@ -993,7 +1100,12 @@ extern "C" md_status md_get_timing(md_ctx* c, double* total_ms, int64_t* launche
 extern "C" void md_destroy(md_ctx* c)
 {
     if (!c) return;
-    if (!c->ev_pending.empty()) (void)hipStreamSynchronize(c->stream);
+    if (!c->ev_pending.empty() || c->gexec) (void)hipStreamSynchronize(c->stream);
+    if (c->gstream) (void)hipStreamSynchronize(c->gstream);
+    drop_graph(c);
+    for (int e = 0; e < 2; ++e)
+        if (c->gev[e]) (void)hipEventDestroy(c->gev[e]);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
     for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_pending) (void)hipEventDestroy(e);
     delete c;

@@ -51,7 +51,8 @@ int integrate_share(int R)
 int64_t max_workgroups(const md_ctx* c)
 {
     const int64_t n = c->prm.n_atoms, ncell = c->geo.n_cells, b = c->kp.block;
-    return (n + b - 1) / b + 1 + kIntegrateGridMax + max_force_blocks(n, ncell) + 8 * G_KINDS;
+    return (n + b - 1) / b + 1 + kIntegrateGridMax + 2 * max_force_blocks(n, ncell) +
+           8 * G_KINDS;
 }
 
 size_t table_bytes(const md_batch* b)

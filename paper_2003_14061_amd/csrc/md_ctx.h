@@ -40,4 +40,12 @@ struct md_ctx {
     size_t lds_limit = 160 * 1024;  // per-workgroup LDS; refreshed from the device at bind
     int tile_cells = 0;
     int stage_cap = 0;              // requested staged-atom capacity (0: from density)
+    // md_step's graph of kGraphSteps steps (see md_api.hip)
+    bool graph_on = false;  // set by md_init from the system size
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int g_record = -1;                     // record_every the graph was captured with
+    hipStream_t g_run = nullptr;           // stream it was captured on
+    hipStream_t gstream = nullptr;         // own stream, when the bound one is the null stream
+    hipEvent_t gev[2] = {nullptr, nullptr};
 };

@@ -233,39 +233,26 @@ __global__ __attribute__((amdgpu_waves_per_eu(6))) void k_forces_tiles(B b)
 }
 
 // ---- cells-only mode ----
+//
+// kCellLanes lanes per atom: lane c < 27 walks neighbor cell c of the atom's
+// 27 (dz, dy, dx each -1, 0, +1, dz slowest) straight from the cell arrays,
+// with the full minimum image; the lanes' sums are then added across the
+// group.  At about one atom per cell a lane has one or two partners, so the
+// pass is as deep as a few dependent loads rather than the 27 cells in turn.
 
-template <bool kInterior, typename Acc>
-__device__ __forceinline__ void visit(const KParams& p, double xi, double yi, double zi,
-                                      double xj, double yj, double zj, bool valid, Acc& a)
+template <typename Acc>
+__device__ __forceinline__ void walk_cell(const KParams& p, int i, double xi, double yi,
+                                          double zi, int c2, Acc& a)
 {
-    double dx = xi - xj, dy = yi - yj, dz = zi - zj;
-    if (!kInterior) {
-        dx = minimg(dx, p.L, p.invL);
-        dy = minimg(dy, p.L, p.invL);
-        dz = minimg(dz, p.L, p.invL);
-    }
-    const double r2 = dist2(dx, dy, dz);
-    if (valid && r2 < p.rc2) pair_acc(p, dx, dy, dz, r2, a);
-}
-
-template <bool kInterior, typename Acc>
-__device__ __forceinline__ void walk_cells(const KParams& p, int i, Acc& a)
-{
-    const double xi = p.x[i], yi = p.y[i], zi = p.z[i];
-    const int nc = p.nc, c = p.cell_of[i];
-    const int cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
-    for (int dz = -1; dz <= 1; ++dz) {
-        const int zz = wrap_cell(cz + dz, nc);
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int yy = wrap_cell(cy + dy, nc);
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int c2 = (zz * nc + yy) * nc + wrap_cell(cx + dx, nc);
-                for (int k = p.cell_start[c2]; k < p.cell_start[c2 + 1]; ++k) {
-                    const int j = p.order[k];
-                    visit<kInterior>(p, xi, yi, zi, p.x[j], p.y[j], p.z[j], j != i, a);
-                }
-            }
-        }
+    const int k1 = p.cell_start[c2 + 1];
+    for (int k = p.cell_start[c2]; k < k1; ++k) {
+        const int j = atom_at(p, k);
+        if (j == i) continue;
+        const double dx = minimg(xi - p.x[j], p.L, p.invL);
+        const double dy = minimg(yi - p.y[j], p.L, p.invL);
+        const double dz = minimg(zi - p.z[j], p.L, p.invL);
+        const double r2 = dist2(dx, dy, dz);
+        if (r2 < p.rc2) pair_acc(p, dx, dy, dz, r2, a);
     }
 }
 
@@ -276,20 +263,24 @@ __global__ void k_forces_cells(B b)
     KParams p;
     if (!b.fetch(G_TILES, wg, p)) return;
     __shared__ double red[(1024 / kWave) * 2];
-    const int i = xcd_tile(wg.id, wg.n) * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)xcd_tile(wg.id, wg.n) * blockDim.x + threadIdx.x;
+    const int i = (int)(t / kCellLanes), sub = (int)(t % kCellLanes);
     LeanOf<F> a;
-    if (i < p.n) {
+    if (i < p.n && sub < 27) {
         const int c = p.cell_of[i], nc = p.nc;
         const int cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
-        const bool inner = nc >= 5 && cx >= 1 && cx <= nc - 2 && cy >= 1 && cy <= nc - 2 &&
-                           cz >= 1 && cz <= nc - 2;
-        if (__all(inner))
-            walk_cells<true>(p, i, a);
-        else
-            walk_cells<false>(p, i, a);
+        const int dz = sub / 9 - 1, dy = (sub / 3) % 3 - 1, dx = sub % 3 - 1;
+        const int c2 = (wrap_cell(cz + dz, nc) * nc + wrap_cell(cy + dy, nc)) * nc +
+                       wrap_cell(cx + dx, nc);
+        walk_cell(p, i, p.x[i], p.y[i], p.z[i], c2, a);
     }
+    a.fx = lane_group_sum<kCellLanes>(a.fx);
+    a.fy = lane_group_sum<kCellLanes>(a.fy);
+    a.fz = lane_group_sum<kCellLanes>(a.fz);
+    a.q = lane_group_sum<kCellLanes>(a.q);
+    a.s6 = lane_group_sum<kCellLanes>(a.s6);
     double e[2] = {0.0, 0.0};
-    if (i < p.n) {
+    if (i < p.n && sub == 0) {
         F fx, fy, fz;
         lean_finish(p, a, fx, fy, fz, e[0], e[1]);
         static_cast<F*>(p.fx)[i] = fx;

@@ -120,9 +120,10 @@ struct Wg {
 
 // The grid rules of the launches; a batched launch concatenates, per rule,
 // the workgroups of every replica.
-enum GridKind { G_ATOMS, G_ONE, G_INTEGRATE, G_TILES, G_KINDS };
+enum GridKind { G_ATOMS, G_ONE, G_INTEGRATE, G_TILES, G_NL, G_KINDS };
 
 constexpr int kScanThreads = 1024;  // the one workgroup of the cell-offset scan
+constexpr int kCellLanes = 32;      // lanes per atom of the cells-only force pass
 constexpr int kScanPer = 4;
 
 __host__ __device__ inline int grid_of(const KParams& p, GridKind k)
@@ -138,7 +139,10 @@ __host__ __device__ inline int grid_of(const KParams& p, GridKind k)
             const int g = up(p.n, kIntThreads);
             return g < p.int_grid ? (g > 0 ? g : 1) : p.int_grid;
         }
-        case G_TILES: return p.mode == MD_NEIGHBOR_LIST ? p.n_tiles : up(p.n, p.block);
+        case G_TILES:
+            return p.mode == MD_NEIGHBOR_LIST ? p.n_tiles : up((int64_t)kCellLanes * p.n, p.block);
+        case G_NL:  // the list build: one workgroup per tile
+            return p.mode == MD_NEIGHBOR_LIST ? p.n_tiles : 1;
         default: return 1;
     }
 }
@@ -233,10 +237,11 @@ struct LaunchShape {
 
 LaunchShape shape_of(const KParams& p);
 
-// Largest number of force-pass workgroups any tuning can ask for.
+// Largest number of force-pass workgroups any tuning can ask for (the
+// cells-only pass takes kCellLanes lanes per atom, workgroups of at least 64).
 inline int64_t max_force_blocks(int64_t n, int64_t ncell)
 {
-    const int64_t a = (n + 63) / 64 + 1;
+    const int64_t a = (kCellLanes * n + 63) / 64 + 1;
     return a > ncell + 1 ? a : ncell + 1;
 }
 

@@ -274,15 +274,10 @@ __device__ __forceinline__ void nl_lanes(const KParams& p, const Stage& s, int k
     }
 }
 
-template <class B, int kMethod, bool kHalf>
-__global__ void k_nl_tiles(B b, int force)
+// One tile's lists (every thread of the workgroup calls it).
+template <int kMethod, bool kHalf>
+__device__ __forceinline__ void nl_tile(const KParams& p, int t, char* smem)
 {
-    Wg wg;
-    KParams p;
-    if (!b.fetch(G_TILES, wg, p)) return;
-    if (!force && !p.dev->rebuild) return;
-    extern __shared__ __attribute__((aligned(16))) char smem[];
-    const int t = xcd_tile(wg.id, wg.n);
     const Tile g = tile_of(p, t);
     Stage s = stage_layout(p, smem);
     stage_tables(p, g, s);
@@ -330,6 +325,26 @@ __global__ void k_nl_tiles(B b, int force)
     }
 }
 
+// The list build, gated by the rebuild flag.  Workgroups take tiles
+// v = id, id + n, ... (grid rule G_NL, one tile each at present: a capped grid
+// looping over tiles idles less per launch but measured slower per rebuild,
+// from the uneven tile counts of the last wave of workgroups); tile v keeps
+// the XCD-aware order (v mod 8 is the workgroup's XCD when n is a multiple
+// of 8).
+template <class B, int kMethod, bool kHalf>
+__global__ void k_nl_tiles(B b, int force)
+{
+    Wg wg;
+    KParams p;
+    if (!b.fetch(G_NL, wg, p)) return;
+    if (!force && !p.dev->rebuild) return;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    for (int v = wg.id; v < p.n_tiles; v += wg.n) {
+        nl_tile<kMethod, kHalf>(p, xcd_tile(v, p.n_tiles), smem);
+        __syncthreads();  // the next tile reuses the LDS
+    }
+}
+
 // Decode the list into global slots: out[m * n_pad + k] for m < count[k],
 // -1 elsewhere.
 __global__ void k_nl_export(KParams p, int32_t* out)
@@ -356,7 +371,7 @@ __global__ void k_nl_export(KParams p, int32_t* out)
 template <class B, bool kHalf>
 static void neighbors_seq(const B& b, const LaunchShape& sh, int force, hipStream_t s)
 {
-    const dim3 g(sh.grid[G_TILES]), t(sh.nl_block);
+    const dim3 g(sh.grid[G_NL]), t(sh.nl_block);
     if (sh.nl_method == MD_NL_CELL_WAVES)
         hipLaunchKernelGGL((k_nl_tiles<B, MD_NL_CELL_WAVES, kHalf>), g, t, sh.nl_lds, s, b,
                            force);

@@ -455,6 +455,7 @@ __device__ __forceinline__ void home_position(const KParams& p, const Stage& s, 
 constexpr int kDppQuadXor1 = 0xB1;   // quad_perm(1, 0, 3, 2)
 constexpr int kDppQuadXor2 = 0x4E;   // quad_perm(2, 3, 0, 1)
 constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppRowMirror = 0x140;  // lane i of each row of 16 takes lane 15 - i
 
 template <int CTRL, typename T>
 __device__ __forceinline__ T dpp_move(T v)
@@ -473,15 +474,19 @@ __device__ __forceinline__ T dpp_move(T v)
     }
 }
 
-// Sum over aligned groups of LANES lanes (1, 2, 4 or 8); every lane of a
-// group gets the group's sum.  The lane exchanges are DPP moves on the VALU
+// Sum over aligned groups of LANES lanes (1, 2, 4, 8, 16 or 32); every lane
+// of a group gets the group's sum.  The lane exchanges are DPP moves on the VALU
 // (a shuffle would go through LDS, which the pair loops keep busy).  Every
 // lane of the wave must be active.
 template <int LANES, typename T>
 __device__ __forceinline__ T lane_group_sum(T v)
 {
-    static_assert(LANES == 1 || LANES == 2 || LANES == 4 || LANES == 8, "lanes per atom");
-    if constexpr (LANES == 8) v += dpp_move<kDppHalfMirror>(v);
+    static_assert(LANES == 1 || LANES == 2 || LANES == 4 || LANES == 8 || LANES == 16 ||
+                      LANES == 32,
+                  "lanes per atom");
+    if constexpr (LANES == 32) v += __shfl_xor(v, 16, kWave);  // across the two rows
+    if constexpr (LANES >= 16) v += dpp_move<kDppRowMirror>(v);
+    if constexpr (LANES >= 8) v += dpp_move<kDppHalfMirror>(v);
     if constexpr (LANES >= 4) v += dpp_move<kDppQuadXor2>(v);
     if constexpr (LANES >= 2) v += dpp_move<kDppQuadXor1>(v);
     return v;

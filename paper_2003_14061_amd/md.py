@@ -29,7 +29,7 @@ MD_PIPE_TILED, MD_PIPE_LAYERS, MD_PIPE_ALLPAIRS = 0, 1, 2
  MD_ARR_LAYERS, MD_ARR_LAYER_COUNT) = range(8)
 
 EXPORTS = ("md_init", "md_workspace_bytes", "md_geometry", "md_layout", "md_bind",
-           "md_bind_static",
+           "md_bind_static", "md_set_graph",
            "md_build_cells", "md_build_neighbors", "md_forces", "md_step", "md_reduce",
            "md_history", "md_set_tuning", "md_get_tuning", "md_set_timing", "md_get_timing",
            "md_export_neighbors", "md_traj_workspace_bytes", "md_traj_forward",
@@ -122,6 +122,7 @@ def lib():
         "md_build_neighbors": (C.c_int, [P]),
         "md_forces": (C.c_int, [P]),
         "md_step": (C.c_int, [P, C.c_int32, C.c_int32]),
+        "md_set_graph": (C.c_int, [P, C.c_int32]),
         "md_reduce": (C.c_int, [P, C.POINTER(Observables)]),
         "md_history": (C.c_int, [P, C.POINTER(Record), C.c_int32, C.POINTER(C.c_int32)]),
         "md_export_neighbors": (C.c_int, [P, P]),
@@ -474,6 +475,9 @@ class Simulation:
 
     def set_timing(self, enable=True):
         md_set_timing(self.ctx, enable)
+
+    def set_graph(self, enable=True):
+        _check(lib().md_set_graph(self.ctx, int(bool(enable))), "md_set_graph")
 
     def get_timing(self):
         return md_get_timing(self.ctx)
