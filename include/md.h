@@ -330,8 +330,10 @@ typedef struct {
     int32_t nl_block;       /* threads per workgroup of the list build: 64..1024, multiple of 64;
                                0 = automatic (a lane per home atom of a mean tile, or a wave
                                per home cell of the widest tile, at most 16 waves) */
-    int32_t tile_cells;     /* cells per tile along x in neighbor-list mode; 0 = enough for
-                               about 1.25 home atoms per lane group of the force workgroup */
+    int32_t tile_cells;     /* neighbor-list mode: cells per tile (a block of cells) along x;
+                               0 = automatic: the block with the fewest staged cells per home
+                               cell whose staged atoms fit three force workgroups per CU and
+                               whose home atoms fill at most three force passes */
     int32_t stage_cap;      /* atoms a workgroup stages in LDS (0 = 1.15x the mean need plus
                                64); tiles that hold more read positions from global memory
                                instead */
@@ -342,13 +344,15 @@ typedef struct {
                                ones) or MD_NL_AUTO (lanes below 8 atoms per cell); the list
                                is the same either way.  md_get_tuning reports the method
                                in use */
+    int32_t tile_y;         /* cells per tile along y (0 = automatic, as tile_cells) */
+    int32_t tile_z;         /* cells per tile along z (0 = automatic, as tile_cells) */
 } md_tuning;
 
 /* md_set_tuning: change the launch shape (host only; takes effect at the
  * next launch).  The forces must be recomputed (md_forces) before md_step,
- * and a change of tile_cells also needs md_build_neighbors, since list
+ * and a change of the tile size also needs md_build_neighbors, since list
  * entries index the tile's staged atoms.  md_get_tuning: the current shape
- * (tile_cells as resolved). */
+ * (tile_cells, tile_y, tile_z as resolved: the largest block in use). */
 md_status md_set_tuning(md_ctx* ctx, const md_tuning* tuning);
 md_status md_get_tuning(const md_ctx* ctx, md_tuning* tuning);
 

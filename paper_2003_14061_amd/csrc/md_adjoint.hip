@@ -150,7 +150,7 @@ __global__ void k_adj_point(KParams p, AdjArgs q)
     const Tile g = tile_of(p, xcd_tile(blockIdx.x, gridDim.x));
     Stage s = stage_layout(p, smem, q.cap, true);
     stage_tables(p, g, s);
-    const int nh = home_count(s), h0 = home_first_lds(s), slot0 = home_first_slot(s);
+    const int nh = home_count(s);
     const int mode = staged_image_mode(p, s, tile_interior(p, g));
     stage_atoms<true, true>(p, s, q.vx, q.vy, q.vz);
     __syncthreads();
@@ -164,11 +164,13 @@ __global__ void k_adj_point(KParams p, AdjArgs q)
         int i = 0;
         double vix = 0.0, viy = 0.0, viz = 0.0;
         if (h < nh) {
-            i = atom_at(p, slot0 + h);
+            int eh, pos;
+            home_atom(s, h, eh, pos);
+            i = atom_at(p, pos);
             double xi, yi, zi;
-            home_position(p, s, h0, h, i, xi, yi, zi);
+            home_position(p, s, eh, i, xi, yi, zi);
             if (s.fits) {
-                lds_xyz(s.a3, h0 + h, vix, viy, viz);
+                lds_xyz(s.a3, eh, vix, viy, viz);
             } else {
                 vix = q.vx[i];
                 viy = q.vy[i];
@@ -286,16 +288,18 @@ __global__ void k_gr_hist(KParams p, GrArgs g, int cap)
     const Tile t = tile_of(p, xcd_tile(blockIdx.x, gridDim.x));
     Stage s = stage_layout(p, smem, cap, false);
     stage_tables(p, t, s);
-    const int nh = home_count(s), h0 = home_first_lds(s), slot0 = home_first_slot(s);
+    const int nh = home_count(s);
     const int mode = staged_image_mode(p, s, tile_interior(p, t));
     stage_positions_imaged(p, s);
     __syncthreads();
     const double reach = g.rmax + 3.0 * g.width;
     GrOp op{g, lh, reach * reach};
     for (int h = threadIdx.x; h < nh; h += blockDim.x) {
-        const int i = atom_at(p, slot0 + h);
+        int eh, pos;
+        home_atom(s, h, eh, pos);
+        const int i = atom_at(p, pos);
         double xi, yi, zi;
-        home_position(p, s, h0, h, i, xi, yi, zi);
+        home_position(p, s, eh, i, xi, yi, zi);
         walk_home<1>(p, s, mode, i, 0, p.nl_count[i], xi, yi, zi, op);
     }
     __syncthreads();
@@ -347,15 +351,17 @@ __global__ void k_gr_grad(KParams p, GrArgs g, int cap)
     const Tile t = tile_of(p, xcd_tile(blockIdx.x, gridDim.x));
     Stage s = stage_layout(p, smem, cap, false);
     stage_tables(p, t, s);
-    const int nh = home_count(s), h0 = home_first_lds(s), slot0 = home_first_slot(s);
+    const int nh = home_count(s);
     const int mode = staged_image_mode(p, s, tile_interior(p, t));
     stage_positions_imaged(p, s);
     __syncthreads();
     const double reach = g.rmax + 3.0 * g.width;
     for (int h = threadIdx.x; h < nh; h += blockDim.x) {
-        const int i = atom_at(p, slot0 + h);
+        int eh, pos;
+        home_atom(s, h, eh, pos);
+        const int i = atom_at(p, pos);
         double xi, yi, zi;
-        home_position(p, s, h0, h, i, xi, yi, zi);
+        home_position(p, s, eh, i, xi, yi, zi);
         GrGradOp op{g, wn, reach * reach};
         walk_home<1>(p, s, mode, i, 0, p.nl_count[i], xi, yi, zi, op);
         g.lx[i] = op.ax;
@@ -407,7 +413,7 @@ template <typename T>
 static void launch_adj_t(const KParams& p, const AdjArgs& a, hipStream_t s)
 {
     const dim3 g(p.n_tiles), t(p.force_block);
-    const size_t lds = stage_bytes(a.cap, p.kx_max, true);
+    const size_t lds = stage_bytes(p, a.cap, true);
     switch (p.force_lanes) {
         case 8: hipLaunchKernelGGL((k_adj_point<T, 8>), g, t, lds, s, p, a); break;
         case 4: hipLaunchKernelGGL((k_adj_point<T, 4>), g, t, lds, s, p, a); break;
@@ -429,7 +435,7 @@ void launch_gr(const KParams& p, const GrArgs& g, hipStream_t s)
     const int cap = gr_stage_cap(p);
     hipLaunchKernelGGL(k_gr_clear, dim3(1), dim3(256), 0, s, g);
     hipLaunchKernelGGL(k_gr_hist, dim3(p.n_tiles), dim3(p.force_block),
-                       stage_bytes(cap, p.kx_max), s, p, g, cap);
+                       stage_bytes(p, cap), s, p, g, cap);
     hipLaunchKernelGGL(k_gr_finish, dim3(1), dim3(256), 0, s, p, g);
 }
 
@@ -437,7 +443,7 @@ void launch_gr_grad(const KParams& p, const GrArgs& g, hipStream_t s)
 {
     const int cap = gr_stage_cap(p);
     hipLaunchKernelGGL(k_gr_grad, dim3(p.n_tiles), dim3(p.force_block),
-                       stage_bytes(cap, p.kx_max), s, p, g, cap);
+                       stage_bytes(p, cap), s, p, g, cap);
 }
 
 void launch_traj_ubar(const KParams& p, int32_t n_steps, double* out, hipStream_t s)

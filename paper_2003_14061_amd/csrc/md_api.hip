@@ -42,33 +42,71 @@ extern "C" const char* md_status_str(int32_t st)
     }
 }
 
-// Tiling of the neighbor-list mode: each row of nc cells is cut into
-// tiles_per_row tiles of about `cells` cells (0: enough cells for about 1.25
-// home atoms per lane group of the force workgroup at the mean occupancy;
-// the staging of a tile's neighborhood is then shared by more home atoms
-// than one pass of the workgroup holds).  The LDS capacity allows 1.15x the
-// mean staged count plus 64, so that three force workgroups share a CU at
-// the dense LJ state; a tile that does not fit takes its partners from
-// global memory.
-static void plan_tiles(md_ctx* c, int cells)
+// Tiling of the neighbor-list mode: the grid is cut into near-equal blocks of
+// about kx x ky x kz cells (a requested size of 0 is chosen here).  The
+// choice minimizes the staged cells per home cell, (kx+2)(ky+2)(kz+2) over
+// kx ky kz, among blocks whose expected staged atoms (1.15x the mean plus 64)
+// fit the LDS share that lets three force workgroups share a CU, whose
+// expected home atoms fill at most three passes of the force workgroup and,
+// for a system alone, that give at least one tile per CU (ties: the longer
+// block along x, whose slot runs are longer).  The LDS
+// capacity then allows 1.15x the mean staged count plus 64 of the largest
+// block; a tile that does not fit takes its partners from global memory.
+static void plan_tiles(md_ctx* c)
 {
     KParams& k = c->kp;
     const int nc = k.nc;
     const double occ = (double)k.n / ((double)nc * nc * nc);
-    if (cells <= 0) {
-        // about 1.25 x force_block / 4 home atoms per tile, whatever the lanes
-        // per atom: at 2 lanes the same tile size measured best as well
-        const double home = 1.25 * k.force_block / 4.0;
-        cells = (int)floor(home / (occ > 1e-9 ? occ : 1e-9));
-    }
-    const int kx_cap = nc < 128 ? nc : 128;
-    cells = cells < 1 ? 1 : (cells > kx_cap ? kx_cap : cells);
-    k.tiles_per_row = (nc + cells - 1) / cells;
-    k.kx_max = (nc + k.tiles_per_row - 1) / k.tiles_per_row;
-    k.n_tiles = nc * nc * k.tiles_per_row;
-    const double s_mean = 9.0 * (k.kx_max + 2) * occ;
+    const double lds_share = 160.0 * 1024.0 / 3.0 - 2048.0;  // bytes, three per CU
+    const double home_max = 3.0 * k.force_block / k.force_lanes;
+    // a system alone keeps a workgroup per CU at least (replicas of a batch share
+    // the machine)
+    const int64_t ncell = (int64_t)nc * nc * nc;
+    const int64_t min_tiles = c->min_tiles < ncell ? c->min_tiles : ncell;
+    auto maxsize = [nc](int req) {
+        const int parts = (nc + req - 1) / req;
+        return (nc + parts - 1) / parts;
+    };
+    int best[3] = {1, 1, 1};
+    double best_ratio = 1e300;
+    const int kx_hi = nc < 64 ? nc : 64, kyz_hi = nc < 4 ? nc : 4;
+    for (int kz = 1; kz <= kyz_hi; ++kz)
+        for (int ky = kz; ky <= kyz_hi; ++ky)
+            for (int kx = 1; kx <= kx_hi; ++kx) {
+                const int ax = c->tile_cells > 0 ? c->tile_cells : kx;
+                const int ay = c->tile_y > 0 ? c->tile_y : ky;
+                const int az = c->tile_z > 0 ? c->tile_z : kz;
+                const int mx = maxsize(ax), my = maxsize(ay), mz = maxsize(az);
+                const double staged = (double)(mx + 2) * (my + 2) * (mz + 2) * occ;
+                const double home = (double)mx * my * mz * occ;
+                const int64_t tiles = (int64_t)((nc + ax - 1) / ax) * ((nc + ay - 1) / ay) *
+                                      ((nc + az - 1) / az);
+                const bool ok = (1.15 * staged + 64.0) * 3.0 * sizeof(double) <= lds_share &&
+                                home <= home_max && tiles >= min_tiles;
+                const double ratio = (double)(mx + 2) * (my + 2) * (mz + 2) / ((double)mx * my * mz);
+                // a block that breaks the limits is taken only while nothing fits
+                const double score = ok ? ratio : 1e200 + ratio;
+                if (score < best_ratio - 1e-9 ||
+                    (fabs(score - best_ratio) <= 1e-9 && mx > best[0])) {
+                    best_ratio = score;
+                    best[0] = ax;
+                    best[1] = ay;
+                    best[2] = az;
+                }
+            }
+    k.tiles_x = (nc + best[0] - 1) / best[0];
+    k.tiles_y = (nc + best[1] - 1) / best[1];
+    k.tiles_z = (nc + best[2] - 1) / best[2];
+    k.kx_max = (nc + k.tiles_x - 1) / k.tiles_x;
+    k.ky_max = (nc + k.tiles_y - 1) / k.tiles_y;
+    k.kz_max = (nc + k.tiles_z - 1) / k.tiles_z;
+    k.n_tiles = k.tiles_x * k.tiles_y * k.tiles_z;
+    c->tile_cells_res = k.kx_max;
+    c->tile_y_res = k.ky_max;
+    c->tile_z_res = k.kz_max;
+    const double s_mean = (double)(k.kx_max + 2) * (k.ky_max + 2) * (k.kz_max + 2) * occ;
     // tables and static LDS
-    const size_t tables = stage_bytes(0, k.kx_max) + 2048;
+    const size_t tables = stage_bytes(k, 0) + 2048;
     const size_t room = c->lds_limit > tables ? c->lds_limit - tables : 0;
     int scap = c->stage_cap > 0 ? c->stage_cap : (int)(1.15 * s_mean + 64.0);
     const int scap_max = (int)(room / (3 * sizeof(double)));
@@ -79,28 +117,32 @@ static void plan_tiles(md_ctx* c, int cells)
     int aux = (int)(room / (6 * sizeof(double)));
     aux = (aux < k.scap ? aux : k.scap) / 64 * 64;
     k.scap_aux = aux < 64 ? 64 : aux;
-    c->tile_cells = cells;
     if (k.pipeline == MD_PIPE_LAYERS)
         k.nblk_force = (k.n + k.block - 1) / k.block;
     else if (k.pipeline == MD_PIPE_ALLPAIRS)
         k.nblk_force = allpairs_home_blocks(k.n) * k.ap_split;
     else
         k.nblk_force = force_blocks(k);
-    // list build: a lane per home atom of a mean tile (25% spare), or a
-    // wave per home cell of the widest tile (at most 16 waves, each then
-    // taking several cells)
+    // list build: a lane per home atom of a mean tile (25% spare), or waves
+    // taking the home cells in turn: 8 waves from 8 home cells on, else 4 (a
+    // multiple of the CU's four SIMDs measured best: 6 or 12 waves for 12
+    // cells were 28-35% slower than 8 or 4)
     k.nl_method = c->nl_method_req != MD_NL_AUTO ? c->nl_method_req
                                                  : (occ < 8.0 ? MD_NL_LANES : MD_NL_CELL_WAVES);
+    const int home_cells = k.kx_max * k.ky_max * k.kz_max;
     int waves;
     if (k.nl_method == MD_NL_LANES) {
-        waves = (int)ceil(1.25 * k.kx_max * occ / kWave);
+        waves = (int)ceil(1.25 * home_cells * occ / kWave);
+        waves = waves > 16 ? 16 : waves;
     } else {
-        waves = k.kx_max < 16 ? k.kx_max : 16;
+        waves = home_cells >= 8 ? 8 : (home_cells >= 4 ? 4 : home_cells);
     }
     waves = waves < 1 ? 1 : waves;
     const int nlb = c->nl_block_req > 0 ? c->nl_block_req : kWave * waves;
     k.nl_block = nlb < kWave ? kWave : (nlb > 1024 ? 1024 : nlb);
 }
+
+void replan_tiles(md_ctx* c) { plan_tiles(c); }
 
 static md_status hip_ok(hipError_t e) { return e == hipSuccess ? MD_OK : MD_ERR_HIP; }
 
@@ -271,7 +313,7 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
     c->nl_block_req = 0;
     k.int_grid = kIntegrateGridDefault;
     k.gate_grid = kGateGridDefault;
-    plan_tiles(c, 0);
+    plan_tiles(c);
     *out = c;
     return MD_OK;
 }
@@ -419,7 +461,7 @@ static md_status bind_to(md_ctx* c, const md_buffers* bf, char* ws, void* stream
         hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         return MD_ERR_HIP;
     c->lds_limit = (size_t)lds;
-    plan_tiles(c, c->tile_cells);
+    plan_tiles(c);
     c->bound = true;
     c->cells_ok = c->nl_ok = c->forces_ok = false;
     launch_clear(k, c->stream);
@@ -1044,22 +1086,27 @@ extern "C" md_status md_set_tuning(md_ctx* c, const md_tuning* t)
     if (!c || !t) return MD_ERR_ARG;
     if (!one_of(t->force_lanes, {1, 2, 4, 8}) || t->force_block % 64 != 0 ||
         t->force_block < 64 || t->force_block > 1024 || t->nl_block % 64 != 0 ||
-        t->nl_block < 0 || t->nl_block > 1024 || t->tile_cells < 0 || t->stage_cap < 0 ||
+        t->nl_block < 0 || t->nl_block > 1024 || t->tile_cells < 0 || t->tile_y < 0 ||
+        t->tile_z < 0 || t->stage_cap < 0 ||
         t->integrate_grid < 0 || t->integrate_grid > kIntegrateGridMax ||
         !one_of(t->nl_method, {MD_NL_AUTO, MD_NL_LANES, MD_NL_CELL_WAVES}))
         return MD_ERR_ARG;
     KParams& k = c->kp;
     drop_graph(c);  // launch shapes and parameters are baked into it
-    const int old_tiles = k.n_tiles, old_cells = c->tile_cells;
+    const int old[4] = {k.n_tiles, k.kx_max, k.ky_max, k.kz_max};
     k.force_lanes = t->force_lanes;
     k.force_block = t->force_block;
     c->nl_block_req = t->nl_block;
     c->nl_method_req = t->nl_method;
     k.int_grid = t->integrate_grid > 0 ? t->integrate_grid : kIntegrateGridDefault;
     c->stage_cap = t->stage_cap;
-    plan_tiles(c, t->tile_cells);
+    c->tile_cells = t->tile_cells;
+    c->tile_y = t->tile_y;
+    c->tile_z = t->tile_z;
+    plan_tiles(c);
     // the list encoding depends on the tiling
-    if (k.n_tiles != old_tiles || c->tile_cells != old_cells) c->nl_ok = false;
+    if (k.n_tiles != old[0] || k.kx_max != old[1] || k.ky_max != old[2] || k.kz_max != old[3])
+        c->nl_ok = false;
     // the partials of the last force pass are laid out for the old grid
     c->forces_ok = false;
     return MD_OK;
@@ -1073,7 +1120,9 @@ extern "C" md_status md_get_tuning(const md_ctx* c, md_tuning* t)
     t->nl_block = c->kp.nl_block;
     t->integrate_grid = c->kp.int_grid;
     t->nl_method = c->kp.nl_method;
-    t->tile_cells = c->tile_cells;
+    t->tile_cells = c->tile_cells_res;
+    t->tile_y = c->tile_y_res;
+    t->tile_z = c->tile_z_res;
     t->stage_cap = c->kp.scap;
     return MD_OK;
 }

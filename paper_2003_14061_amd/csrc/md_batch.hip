@@ -208,6 +208,8 @@ extern "C" md_status md_batch_init(const md_params* params, int32_t n_replicas, 
         // the machine among the replicas
         c->kp.gate_grid = gate_share(n_replicas);
         c->kp.int_grid = integrate_share(n_replicas);
+        c->min_tiles = 0;  // the replicas together fill the machine
+        replan_tiles(c);
         b->rep.push_back(c);
         b->rep_off.push_back(off);
         off += align_up(c->ws_bytes);

@@ -22,6 +22,9 @@ enum Region {
 
 }  // namespace md
 
+struct md_ctx;
+void replan_tiles(md_ctx* c);  // the tiling again, after a change of min_tiles
+
 struct md_ctx {
     md_params prm;
     md_grid geo;
@@ -38,8 +41,10 @@ struct md_ctx {
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
     size_t lds_limit = 160 * 1024;  // per-workgroup LDS; refreshed from the device at bind
-    int tile_cells = 0;
+    int tile_cells = 0, tile_y = 0, tile_z = 0;  // requested block size (0: automatic)
+    int tile_cells_res = 0, tile_y_res = 0, tile_z_res = 0;  // largest block in use
     int stage_cap = 0;              // requested staged-atom capacity (0: from density)
+    int min_tiles = 256;            // automatic tiling: at least this many tiles (one per CU)
     // md_step's graph of kGraphSteps steps (see md_api.hip)
     bool graph_on = false;  // set by md_init from the system size
     hipGraph_t graph = nullptr;

@@ -85,7 +85,7 @@ __global__ void k_forces_half(B b)
     const Tile g = tile_of(p, xcd_tile(wg.id, wg.n));
     Stage s = stage_layout(p, smem, p.scap_aux, true);
     stage_tables(p, g, s);
-    const int nh = home_count(s), h0 = home_first_lds(s), slot0 = home_first_slot(s);
+    const int nh = home_count(s);
     const int mode = staged_image_mode(p, s, tile_interior(p, g));
     stage_positions_imaged(p, s);
     // the accumulators, in the aux region (F-typed, interleaved)
@@ -100,11 +100,13 @@ __global__ void k_forces_half(B b)
     for (int hb = 0; hb < nh; hb += per_pass) {
         const int h = hb + threadIdx.x / LANES;
         Acc a;
-        int slot_i = 0;
+        int slot_i = 0, eh = 0;
         if (h < nh) {
-            slot_i = atom_at(p, slot0 + h);
+            int pos;
+            home_atom(s, h, eh, pos);
+            slot_i = atom_at(p, pos);
             double xi, yi, zi;
-            home_position(p, s, h0, h, slot_i, xi, yi, zi);
+            home_position(p, s, eh, slot_i, xi, yi, zi);
             HalfOp<F, Acc> op{p, a, r};
             walk_home<LANES>(p, s, mode, slot_i, sub, p.nl_count[slot_i], xi, yi, zi, op);
         }
@@ -117,9 +119,9 @@ __global__ void k_forces_half(B b)
         }
         if (h < nh && sub == 0) {
             if (s.fits) {
-                lds_add(r + 3 * (h0 + h), a.fx);
-                lds_add(r + 3 * (h0 + h) + 1, a.fy);
-                lds_add(r + 3 * (h0 + h) + 2, a.fz);
+                lds_add(r + 3 * eh, a.fx);
+                lds_add(r + 3 * eh + 1, a.fy);
+                lds_add(r + 3 * eh + 2, a.fz);
             } else {
                 global_add(static_cast<F*>(p.fx) + slot_i, a.fx);
                 global_add(static_cast<F*>(p.fy) + slot_i, a.fy);
@@ -182,7 +184,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(6))) void k_forces_tiles(B b)
     const Tile g = tile_of(p, xcd_tile(wg.id, wg.n));
     Stage s = stage_layout(p, smem);
     stage_tables(p, g, s);
-    const int nh = home_count(s), h0 = home_first_lds(s), slot0 = home_first_slot(s);
+    const int nh = home_count(s);
     const int mode = staged_image_mode(p, s, tile_interior(p, g));
     stage_positions_imaged(p, s);
     __syncthreads();
@@ -194,9 +196,11 @@ __global__ __attribute__((amdgpu_waves_per_eu(6))) void k_forces_tiles(B b)
         LeanOf<F> a;
         int slot_i = 0;
         if (h < nh) {
-            slot_i = atom_at(p, slot0 + h);
+            int eh, pos;
+            home_atom(s, h, eh, pos);
+            slot_i = atom_at(p, pos);
             double xi, yi, zi;
-            home_position(p, s, h0, h, slot_i, xi, yi, zi);
+            home_position(p, s, eh, slot_i, xi, yi, zi);
             ForceOp<LeanOf<F>> op{p, a};
             // the lane's list-row offset is formed here for each pass: hoisted out
             // of the pass loop it is a 64-bit value live across the whole kernel
@@ -349,7 +353,7 @@ int force_blocks(const KParams& p) { return grid_of(p, G_TILES); }
 size_t force_lds_bytes(const KParams& p)
 {
     if (p.mode != MD_NEIGHBOR_LIST) return 0;
-    return p.newton3 ? stage_bytes(p.scap_aux, p.kx_max, true) : stage_bytes(p.scap, p.kx_max);
+    return p.newton3 ? stage_bytes(p, p.scap_aux, true) : stage_bytes(p, p.scap);
 }
 
 LaunchShape shape_of(const KParams& p)

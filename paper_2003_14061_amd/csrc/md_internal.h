@@ -71,8 +71,10 @@ struct KParams {
     int32_t int_grid;       // workgroups of the grid-stride per-atom kernels
     int32_t gate_grid;      // most workgroups of a rebuild-gated per-atom or per-cell kernel
     int32_t nl_method;      // MD_NL_LANES or MD_NL_CELL_WAVES
-    // tiling of the neighbor-list mode: rows of nc cells cut into tiles_per_row tiles
-    int32_t tiles_per_row, kx_max, n_tiles;
+    // tiling of the neighbor-list mode: blocks of cells, the grid cut into
+    // tiles_x x tiles_y x tiles_z near-equal blocks of at most kx_max x ky_max x
+    // kz_max cells
+    int32_t tiles_x, tiles_y, tiles_z, kx_max, ky_max, kz_max, n_tiles;
     int32_t scap;           // staged atoms a workgroup's LDS holds
     int32_t scap_aux;       // the same with a second 3-vector staged per atom
     int32_t ap_split, ap_chunk;  // all-pairs: partner chunks per home block, atoms per chunk

@@ -2,9 +2,9 @@
 //
 // One workgroup per tile (md_tiles.h) stages the tile's 27-cell
 // neighborhoods in LDS.  A home atom's candidates are the three cells
-// dx = -1, 0, +1 of each of the 9 staged rows (dz, dy each -1, 0, +1, dz
-// slowest), every cell in ascending permanent id; its list keeps them in
-// that canonical order.  An entry is kept when the minimum-image squared
+// dx = -1, 0, +1 of each of the 9 staged rows next to its cell (dz, dy each
+// -1, 0, +1, dz slowest), every cell in ascending permanent id; its list
+// keeps them in that canonical order.  An entry is kept when the minimum-image squared
 // separation is below (r_cut + skin)^2 (dx*dx, then two fused
 // multiply-adds) and it is not the atom itself.  Two ways to walk them:
 //
@@ -18,8 +18,8 @@
 // The half list (for the Newton's-third-law force pass) keeps a candidate
 // only if it comes after the home atom in cell order (cell index, then
 // permanent id).  That order is the order of the cell-ordered slots:
-// candidate e of staged cell t sits at slot[t] + (e - off[t]), the home atom
-// h at home_first_slot + h, so the test is one integer comparison, and a
+// candidate e of staged cell t sits at slot[t] + (e - off[t]), and so does the
+// home atom, so the test is one integer comparison, and a
 // staged cell whose last slot is not past the home atom's is skipped whole.
 //
 // Storage follows the paper's W (section 2.3): row m holds the m-th
@@ -41,10 +41,10 @@ __device__ __forceinline__ double readlane_f64(double v, int lane)
 }
 
 // LDS bytes of the list build: the staged tile.
-size_t nl_lds_bytes(const KParams& p) { return stage_bytes(p.scap, p.kx_max); }
+size_t nl_lds_bytes(const KParams& p) { return stage_bytes(p, p.scap); }
 
-// One home cell q of the tile, by one wave.  The candidates (the 9 windows
-// of cells q-1..q+1 of every staged row, concatenated, in canonical order)
+// One home cell hc of the tile, by one wave.  The candidates (the 9 windows
+// of three cells next to it, concatenated, in canonical order)
 // are taken kNlRounds x 64 at a time: lane l holds candidate k0 + 64 r + l
 // (position, wrap bits, encoded entry) in registers.  Each home atom hh in
 // turn is broadcast from lane hh (readlane) and tested against the block;
@@ -53,20 +53,36 @@ size_t nl_lds_bytes(const KParams& p) { return stage_bytes(p.scap, p.kx_max); }
 // length, kept in a scalar register while hh is tested and in lane hh of a
 // vector register between blocks.  Lanes past the candidates read the home
 // cell's first atom (e = hb) and never hit.
+// Staged cell of column a - 1 in the row (dz, dy) = (sg / 3 - 1, sg % 3 - 1)
+// next to home cell home_t (at column a): the first cell of window sg.
+__device__ __forceinline__ int window_cell(const Stage& s, int home_t, int sg)
+{
+    const int dz = (sg >= 3 ? 1 : 0) + (sg >= 6 ? 1 : 0) - 1, dy = sg - 3 * (dz + 1) - 1;
+    return home_t - 1 + (dz * s.rows_y + dy) * s.stride;
+}
+
+// Staged cell of home cell hc (0 .. kx ky kz - 1, x fastest).
+__device__ __forceinline__ int home_cell(const Stage& s, int hc)
+{
+    const int a = 1 + hc % s.kx, r = hc / s.kx;
+    return home_row_cell(s, r) + (a - 1);
+}
+
 template <int kImage, bool kHalf, bool kFits>
-__device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, int q)
+__device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, int hc)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int home_t = 4 * s.stride + q;
+    const int home_t = home_cell(s, hc);
     // table values are the same in every lane: keep them in scalar registers
     const int hb = uniform(s.off[home_t]), he = uniform(s.off[home_t + 1]);
     const int hslot0 = uniform(s.slot[home_t]);
-    int wa[9], wp[10];
+    int wa[9], wp[10], wt[9];
     wp[0] = 0;
 #pragma unroll
     for (int sg = 0; sg < 9; ++sg) {
-        wa[sg] = uniform(s.off[sg * s.stride + q - 1]);
-        wp[sg + 1] = wp[sg] + (uniform(s.off[sg * s.stride + q + 2]) - wa[sg]);
+        wt[sg] = window_cell(s, home_t, sg);
+        wa[sg] = uniform(s.off[wt[sg]]);
+        wp[sg + 1] = wp[sg] + (uniform(s.off[wt[sg] + 3]) - wa[sg]);
     }
     const int ncand = wp[9];
     const int cap = p.cap;  // a multiple of 4
@@ -100,14 +116,14 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
                 int sg = 0;
 #pragma unroll
                 for (int j = 1; j < 9; ++j) sg += k >= wp[j] ? 1 : 0;
-                int a = wa[0], pre = wp[0];
+                int a = wa[0], pre = wp[0], t0 = wt[0];
 #pragma unroll
                 for (int j = 1; j < 9; ++j) {
                     a = sg == j ? wa[j] : a;
                     pre = sg == j ? wp[j] : pre;
+                    t0 = sg == j ? wt[j] : t0;
                 }
                 const int e = cval[r] ? a + (k - pre) : hb;
-                const int t0 = sg * s.stride + q - 1;
                 const int w = (e >= s.off[t0 + 1] ? 1 : 0) + (e >= s.off[t0 + 2] ? 1 : 0);
                 const int t = cval[r] ? t0 + w : home_t;
                 ce[r] = e;
@@ -176,27 +192,28 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
     }
 }
 
-// Home cell (column 1..kx of the middle row) holding staged entry e.
-__device__ __forceinline__ int home_column(const Stage& s, int kx, int e)
+// Home cell of row cell t1 (column 1 of its home row) holding staged entry e.
+__device__ __forceinline__ int home_column_cell(const Stage& s, int t1, int e)
 {
-    int lo = 1, hi = kx;
+    int lo = 0, hi = s.kx - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (s.off[4 * s.stride + mid] <= e)
+        if (s.off[t1 + mid] <= e)
             lo = mid;
         else
             hi = mid - 1;
     }
-    return lo;
+    return t1 + lo;
 }
 
-// The list of home atom h (staged entry e_self, home column q), by one lane.
-// Returns the number of entries found (beyond the capacity: overflow).
+// The list of home atom h, by one lane.  Returns the number of entries found
+// (beyond the capacity: overflow).
 template <int kImage, bool kFits, bool kHalf>
-__device__ __forceinline__ int nl_home_atom(const KParams& p, const Stage& s, int h, int q)
+__device__ __forceinline__ int nl_home_atom(const KParams& p, const Stage& s, int h)
 {
-    const int e_self = home_first_lds(s) + h;
-    const int pos_i = home_first_slot(s) + h;
+    int e_self, pos_i, t1;
+    home_atom(s, h, e_self, pos_i, t1);
+    const int home_t = home_column_cell(s, t1, e_self);
     const int slot_i = atom_at(p, pos_i);
     double xi, yi, zi;
     if (kFits) {
@@ -211,9 +228,10 @@ __device__ __forceinline__ int nl_home_atom(const KParams& p, const Stage& s, in
     uint64_t chunk = 0;
     uint32_t m = 0;
     for (int sg = 0; sg < 9; ++sg) {
+        const int tw = window_cell(s, home_t, sg);
 #pragma unroll
         for (int w = 0; w < 3; ++w) {
-            const int t = sg * s.stride + q - 1 + w;
+            const int t = tw + w;
             const int eb = s.off[t], ee = s.off[t + 1];
             const int fl = s.flag[t];
             const int tslot = kFits && !kHalf ? 0 : s.slot[t];
@@ -259,12 +277,12 @@ __device__ __forceinline__ int nl_home_atom(const KParams& p, const Stage& s, in
 }
 
 template <int kImage, bool kFits, bool kHalf>
-__device__ __forceinline__ void nl_lanes(const KParams& p, const Stage& s, int kx)
+__device__ __forceinline__ void nl_lanes(const KParams& p, const Stage& s)
 {
-    const int nh = home_count(s), h0 = home_first_lds(s);
+    const int nh = home_count(s);
     int mmax = 0;
     for (int h = threadIdx.x; h < nh; h += blockDim.x) {
-        const int m = nl_home_atom<kImage, kFits, kHalf>(p, s, h, home_column(s, kx, h0 + h));
+        const int m = nl_home_atom<kImage, kFits, kHalf>(p, s, h);
         mmax = m > mmax ? m : mmax;
     }
     mmax = wave_max(mmax);
@@ -285,8 +303,11 @@ __device__ __forceinline__ void nl_tile(const KParams& p, int t, char* smem)
         // the 13-bit entry cannot address this tile (and its sentinel): report it
         // as an overflow
         const int nh = home_count(s);
-        for (int h = threadIdx.x; h < nh; h += blockDim.x)
-            p.nl_count[atom_at(p, home_first_slot(s) + h)] = 0;
+        for (int h = threadIdx.x; h < nh; h += blockDim.x) {
+            int e, pos;
+            home_atom(s, h, e, pos);
+            p.nl_count[atom_at(p, pos)] = 0;
+        }
         if (threadIdx.x == 0) atomicOr(&p.dev->flags, (int)MD_FLAG_NL_OVERFLOW);
         return;
     }
@@ -296,31 +317,32 @@ __device__ __forceinline__ void nl_tile(const KParams& p, int t, char* smem)
     if (kMethod == MD_NL_LANES) {
         if (!s.fits) {
             if (mode == 2)
-                nl_lanes<2, false, kHalf>(p, s, g.kx);
+                nl_lanes<2, false, kHalf>(p, s);
             else
-                nl_lanes<1, false, kHalf>(p, s, g.kx);
+                nl_lanes<1, false, kHalf>(p, s);
         } else if (mode == 0) {
-            nl_lanes<0, true, kHalf>(p, s, g.kx);
+            nl_lanes<0, true, kHalf>(p, s);
         } else if (mode == 1) {
-            nl_lanes<1, true, kHalf>(p, s, g.kx);
+            nl_lanes<1, true, kHalf>(p, s);
         } else {
-            nl_lanes<2, true, kHalf>(p, s, g.kx);
+            nl_lanes<2, true, kHalf>(p, s);
         }
         return;
     }
     const int wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    for (int q = 1 + wid; q <= g.kx; q += nw) {
+    const int ncells = g.kx * g.ky * g.kz;
+    for (int hc = wid; hc < ncells; hc += nw) {
         if (!s.fits) {
             if (mode == 2)
-                nl_home_cell<2, kHalf, false>(p, s, q);
+                nl_home_cell<2, kHalf, false>(p, s, hc);
             else
-                nl_home_cell<1, kHalf, false>(p, s, q);
+                nl_home_cell<1, kHalf, false>(p, s, hc);
         } else if (mode == 0) {
-            nl_home_cell<0, kHalf, true>(p, s, q);
+            nl_home_cell<0, kHalf, true>(p, s, hc);
         } else if (mode == 1) {
-            nl_home_cell<1, kHalf, true>(p, s, q);
+            nl_home_cell<1, kHalf, true>(p, s, hc);
         } else {
-            nl_home_cell<2, kHalf, true>(p, s, q);
+            nl_home_cell<2, kHalf, true>(p, s, hc);
         }
     }
 }
@@ -353,9 +375,11 @@ __global__ void k_nl_export(KParams p, int32_t* out)
     const Tile g = tile_of(p, xcd_tile(blockIdx.x, gridDim.x));
     Stage s = stage_layout(p, smem);
     stage_tables(p, g, s);
-    const int nh = home_count(s), slot0 = home_first_slot(s);
+    const int nh = home_count(s);
     for (int h = threadIdx.x; h < nh; h += blockDim.x) {
-        const int k = atom_at(p, slot0 + h), cnt = p.nl_count[k];
+        int e, pos;
+        home_atom(s, h, e, pos);
+        const int k = atom_at(p, pos), cnt = p.nl_count[k];
         for (int m = 0; m < p.cap; ++m) {
             int v = -1;
             if (m < cnt) {
@@ -401,7 +425,7 @@ void launch_neighbors(const Batch& b, const LaunchShape& sh, int force, hipStrea
 void launch_nl_export(const KParams& p, int32_t* out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_nl_export, dim3(p.n_tiles), dim3(p.nl_block),
-                       stage_bytes(p.scap, p.kx_max), s, p, out);
+                       nl_lds_bytes(p), s, p, out);
 }
 
 }  // namespace md

@@ -1,15 +1,20 @@
 // md_tiles.h -- LDS-staged cell tiles shared by the list build and the
 // force pass.
 //
-// A tile is a run of `kx` consecutive cells along x in one (cy, cz) row of
-// cells.  Its workgroup stages, for each of the 9 rows (cz+dz, cy+dy),
-// dz, dy in {-1, 0, 1} (dz slowest), the kx+2 cells cx0-1 .. cx0+kx in that
-// order, taken modulo nc (a cell can appear twice when kx+2 > nc).  Staged
-// cell (s, q), s = 3(dz+1) + (dy+1), q = 0..kx+1, occupies LDS entries
-// [off[s(kx+2)+q], off[s(kx+2)+q+1]), in the cell's slot order (ascending
-// permanent id).  So for a home cell at q the three cells dx = -1, 0, +1 are
-// q-1, q, q+1 of every staged row: the paper's 27-cell neighborhood, walked
-// in the canonical order (section 2.3, step N5).
+// A tile is a block of kx x ky x kz home cells, x fastest: cells
+// cx0 .. cx0+kx-1, cy0 .. cy0+ky-1, cz0 .. cz0+kz-1.  Its workgroup stages
+// the (kx+2)(ky+2)(kz+2) cells around the block, taken modulo nc (a cell
+// can appear twice on small grids): staged row (b, c), b = 0..ky+1,
+// c = 0..kz+1, is the line of cells y = cy0-1+b, z = cz0-1+c; row index
+// s = c (ky+2) + b; along a row, column q = 0..kx+1 is the cell
+// x = cx0-1+q.  Staged cell t = s (kx+2) + q occupies LDS entries
+// [off[t], off[t+1]) in the cell's slot order (ascending permanent id).  For
+// home cell (a, b, c) (1 <= a <= kx, 1 <= b <= ky, 1 <= c <= kz) the 27-cell
+// neighborhood in the canonical order (dz, dy, dx each -1, 0, +1, dz
+// slowest; section 2.3, step N5) is, for each (dz, dy), the three
+// consecutive staged cells q = a-1, a, a+1 of row (c+dz)(ky+2) + (b+dy).
+// A block stages fewer cells per home cell than a single row of cells
+// (9 (kx+2) / kx): at 3 x 2 x 2 cells it is 6.7 against 11.25 at 8 x 1 x 1.
 //
 // Each staged cell carries wrap bits (1: x, 2: y, 4: z) telling which
 // coordinates of a pair that reaches it cross the periodic boundary, the
@@ -51,7 +56,7 @@ constexpr int kMaxStaged = 1 << kEntryBits;  // virtual layout limit
 constexpr int kChunk = 4;                    // entries per 8-byte list chunk
 
 struct Tile {
-    int cz, cy, cx0, kx;
+    int cx0, cy0, cz0, kx, ky, kz;
 };
 
 // Atom stored at position k of the cell-ordered list (the identity once the
@@ -61,15 +66,24 @@ __device__ __forceinline__ int atom_at(const KParams& p, int k)
     return p.reorder ? k : p.order[k];
 }
 
+// Cells c0 .. c0+k-1 of part i of nc cells cut into `parts` near-equal parts.
+__device__ __forceinline__ void split_cells(int nc, int parts, int i, int& c0, int& k)
+{
+    const int base = nc / parts, rem = nc % parts;
+    c0 = i * base + (i < rem ? i : rem);
+    k = base + (i < rem ? 1 : 0);
+}
+
+// Tile t, x fastest, then y, then z: consecutive tiles are neighbors, so the
+// contiguous tile ranges of the XCD-aware order are compact slabs.
 __device__ __forceinline__ Tile tile_of(const KParams& p, int t)
 {
-    const int row = t / p.tiles_per_row, seg = t % p.tiles_per_row;
-    const int base = p.nc / p.tiles_per_row, rem = p.nc % p.tiles_per_row;
+    const int tx = t % p.tiles_x, r = t / p.tiles_x;
+    const int ty = r % p.tiles_y, tz = r / p.tiles_y;
     Tile g;
-    g.cz = row / p.nc;
-    g.cy = row % p.nc;
-    g.cx0 = seg * base + (seg < rem ? seg : rem);
-    g.kx = base + (seg < rem ? 1 : 0);
+    split_cells(p.nc, p.tiles_x, tx, g.cx0, g.kx);
+    split_cells(p.nc, p.tiles_y, ty, g.cy0, g.ky);
+    split_cells(p.nc, p.tiles_z, tz, g.cz0, g.kz);
     return g;
 }
 
@@ -88,7 +102,8 @@ struct Stage {
     MD_LDS int* flag;             // [ntab] wrap bits
     MD_LDS int* scan;             // [kWave] scratch of the scan; afterwards [0], [1]: the
                                   // columns where the staged x index wraps to 0 (or stride)
-    int ntab, stride, total, cap;
+    MD_LDS int* hp;               // [nhr + 1] home atoms before each home row (prefix)
+    int ntab, stride, rows_y, nrows, kx, ky, nhr, total, cap;
     bool fits;                    // total + 1 <= cap: positions (and sentinel) staged
 };
 
@@ -104,19 +119,25 @@ __device__ __forceinline__ void lds_xyz(const MD_LDS double* a, int e, double& x
     z = q[2];
 }
 
-// Ints of the table region, rounded up to 16 bytes.
-__host__ __device__ __forceinline__ int stage_table_ints(int kx_max)
+// Staged cells of the largest tile.
+__host__ __device__ __forceinline__ int stage_cells_max(const KParams& p)
 {
-    const int ntab = 9 * (kx_max + 2);
-    return (3 * ntab + 1 + kWave + 3) / 4 * 4;
+    return (p.kx_max + 2) * (p.ky_max + 2) * (p.kz_max + 2);
+}
+
+// Ints of the table region, rounded up to 16 bytes.
+__host__ __device__ __forceinline__ int stage_table_ints(const KParams& p)
+{
+    const int ntab = stage_cells_max(p), nhr = p.ky_max * p.kz_max;
+    return (3 * ntab + 1 + kWave + nhr + 1 + 3) / 4 * 4;
 }
 
 // Dynamic LDS bytes of the staged tile: positions (and with `aux` a second
 // 3-vector) of cap atoms, then the cell tables.
-inline size_t stage_bytes(int cap, int kx_max, bool aux = false)
+inline size_t stage_bytes(const KParams& p, int cap, bool aux = false)
 {
     return sizeof(double) * (aux ? 6 : 3) * (size_t)cap +
-           sizeof(int) * (size_t)stage_table_ints(kx_max);
+           sizeof(int) * (size_t)stage_table_ints(p);
 }
 
 // Candidate rounds (of 64) held in registers by the cell-wave list build.
@@ -128,11 +149,12 @@ __device__ __forceinline__ Stage stage_layout(const KParams& p, char* smem, int 
     s.cap = cap;
     s.p3 = (MD_LDS double*)smem;
     s.a3 = aux ? s.p3 + 3 * cap : nullptr;
-    const int ntab_max = 9 * (p.kx_max + 2);
+    const int ntab_max = stage_cells_max(p);
     s.off = (MD_LDS int*)(s.p3 + (aux ? 6 : 3) * cap);
     s.slot = s.off + ntab_max + 1;
     s.flag = s.slot + ntab_max;
     s.scan = s.flag + ntab_max;
+    s.hp = s.scan + kWave;
     return s;
 }
 
@@ -142,25 +164,32 @@ __device__ __forceinline__ Stage stage_layout(const KParams& p, char* smem)
 }
 
 // Cell tables of tile g: slots, wrap bits and LDS offsets of the staged
-// cells (one round of global loads, then a workgroup scan).  Every thread of
-// the workgroup must call it.
+// cells (one round of global loads, then a workgroup scan), and the prefix
+// of home atoms over the home rows.  Every thread of the workgroup must call
+// it.
 __device__ __forceinline__ void stage_tables(const KParams& p, const Tile& g, Stage& s)
 {
     const int nc = p.nc;
+    s.kx = g.kx;
+    s.ky = g.ky;
     s.stride = g.kx + 2;
-    s.ntab = 9 * s.stride;
+    s.rows_y = g.ky + 2;
+    s.nrows = s.rows_y * (g.kz + 2);
+    s.ntab = s.nrows * s.stride;
+    s.nhr = g.ky * g.kz;
     int carry = 0;
     for (int base = 0; base < s.ntab; base += blockDim.x) {
         const int t = base + threadIdx.x;
         int cnt = 0;
         if (t < s.ntab) {
-            const int sg = t / s.stride, q = t % s.stride;
-            const int zz = g.cz + sg / 3 - 1, yy = g.cy + sg % 3 - 1, xx = g.cx0 - 1 + q;
+            const int row = t / s.stride, q = t - row * s.stride;
+            const int c = row / s.rows_y, b = row - c * s.rows_y;
+            const int zz = g.cz0 - 1 + c, yy = g.cy0 - 1 + b, xx = g.cx0 - 1 + q;
             const int fl = ((xx < 0 || xx >= nc) ? 1 : 0) | ((yy < 0 || yy >= nc) ? 2 : 0) |
                            ((zz < 0 || zz >= nc) ? 4 : 0);
-            const int c = (wrap_cell(zz, nc) * nc + wrap_cell(yy, nc)) * nc + wrap_cell(xx, nc);
-            const int a = p.cell_start[c];
-            cnt = p.cell_start[c + 1] - a;
+            const int cell = (wrap_cell(zz, nc) * nc + wrap_cell(yy, nc)) * nc + wrap_cell(xx, nc);
+            const int a = p.cell_start[cell];
+            cnt = p.cell_start[cell + 1] - a;
             s.slot[t] = a;
             s.flag[t] = fl;
         }
@@ -196,19 +225,44 @@ __device__ __forceinline__ void stage_tables(const KParams& p, const Tile& g, St
     s.total = carry;
     s.fits = carry < s.cap;
     __syncthreads();
+    // home rows r = (c - 1) ky + (b - 1): the prefix of their home atoms (one wave,
+    // a row per lane, at most 64 rows)
+    if (threadIdx.x < kWave) {
+        const int r = threadIdx.x;
+        int cnt = 0;
+        if (r < s.nhr) {
+            const int b = 1 + r % g.ky, c = 1 + r / g.ky;
+            const int t0 = (c * s.rows_y + b) * s.stride;
+            cnt = s.off[t0 + g.kx + 1] - s.off[t0 + 1];
+        }
+        int inc = cnt;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int v = __shfl_up(inc, o, kWave);
+            if (r >= o) inc += v;
+        }
+        if (r < s.nhr) s.hp[r + 1] = inc;
+        if (r == 0) s.hp[0] = 0;
+    }
+    __syncthreads();
 }
 
 // First staged cell t of the run of slot-contiguous cells holding staged
-// entry k (k < total): its staged row from the 9 row starts (off of each
-// row's first cell; independent LDS reads, the same address in every lane),
-// then the wrap break(s) of that row.  The slot of entry k is then
-// s.slot[t] + (k - s.off[t]).
+// entry k (k < total): its staged row by a binary search over the row starts
+// (off of each row's first cell, monotone; an empty row shares its start with
+// the next one and is passed over), then the wrap break(s) of that row.  The
+// slot of entry k is then s.slot[t] + (k - s.off[t]).
 __device__ __forceinline__ int staged_run(const Stage& s, int k)
 {
-    int sg = 0;
-#pragma unroll
-    for (int r = 1; r < 9; ++r) sg += k >= s.off[r * s.stride] ? 1 : 0;
-    const int t0 = sg * s.stride, qb0 = s.scan[0], qb1 = s.scan[1];
+    int lo = 0, hi = s.nrows - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (k >= s.off[mid * s.stride])
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int t0 = lo * s.stride, qb0 = s.scan[0], qb1 = s.scan[1];
     int t = t0;
     if (k >= s.off[t0 + qb0]) t = t0 + qb0;
     if (k >= s.off[t0 + qb1]) t = t0 + qb1;
@@ -223,7 +277,7 @@ __device__ __forceinline__ int staged_run(const Stage& s, int k)
 //
 // kShift (grids of at least 5 cells per side): every staged cell that wraps
 // is staged as its periodic image next to the tile, shifted by -L on the low
-// side of an axis (staged column 0, row y or z index -1) and +L on the high
+// side of an axis (staged column 0, row b = 0 or c = 0) and +L on the high
 // side, so that the raw difference of a home atom and any staged partner is
 // already the minimum image and the pair loop needs no image rule.
 template <bool kAux, bool kShift = false>
@@ -246,10 +300,11 @@ __device__ __forceinline__ void stage_atoms(const KParams& p, const Stage& s, co
                 pz[u] = p.z[j];
                 const int fl = shift ? s.flag[t] : 0;
                 if (fl) {
-                    const int sg = t / s.stride, q = t - sg * s.stride;
+                    const int row = t / s.stride, q = t - row * s.stride;
+                    const int c = row / s.rows_y, b = row - c * s.rows_y;
                     if (fl & 1) px[u] += q == 0 ? -p.L : p.L;
-                    if (fl & 2) py[u] += sg % 3 == 0 ? -p.L : p.L;
-                    if (fl & 4) pz[u] += sg / 3 == 0 ? -p.L : p.L;
+                    if (fl & 2) py[u] += b == 0 ? -p.L : p.L;
+                    if (fl & 4) pz[u] += c == 0 ? -p.L : p.L;
                 }
                 if (kAux) {
                     qx[u] = vx[j];
@@ -341,21 +396,48 @@ __device__ __forceinline__ int staged_image_mode(const KParams& p, const Stage& 
     return image_mode(p, interior || s.fits);
 }
 
-// Home atoms of a tile: the kx cells q = 1..kx of the middle row (s = 4),
-// contiguous in LDS and in the cell-ordered list (home atom h is
-// atom_at(home_first_slot + h)).
-__device__ __forceinline__ int home_first_lds(const Stage& s) { return s.off[4 * s.stride + 1]; }
-__device__ __forceinline__ int home_count(const Stage& s)
+// Home atoms of a tile: the kx cells a = 1..kx of every home row (b, c),
+// 1 <= b <= ky, 1 <= c <= kz, numbered h = 0 .. home_count - 1 row by row
+// (home row r = (c - 1) ky + (b - 1)); each row's atoms are contiguous in LDS
+// and in the cell-ordered slots.
+__device__ __forceinline__ int home_count(const Stage& s) { return s.hp[s.nhr]; }
+
+// Staged cell (column 1) of home row r.
+__device__ __forceinline__ int home_row_cell(const Stage& s, int r)
 {
-    return s.off[4 * s.stride + s.stride - 1] - s.off[4 * s.stride + 1];
+    const int b = 1 + r % s.ky, c = 1 + r / s.ky;
+    return (c * s.rows_y + b) * s.stride + 1;
 }
-__device__ __forceinline__ int home_first_slot(const Stage& s) { return s.slot[4 * s.stride + 1]; }
+
+// Home atom h: its LDS entry e, its cell-ordered slot position pos (the
+// atom is atom_at(p, pos)) and the staged cell of column 1 of its row.
+__device__ __forceinline__ void home_atom(const Stage& s, int h, int& e, int& pos, int& t1)
+{
+    int lo = 0, hi = s.nhr - 1;
+    while (lo < hi) {  // the last row whose prefix is <= h (empty rows passed over)
+        const int mid = (lo + hi + 1) >> 1;
+        if (h >= s.hp[mid])
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    t1 = home_row_cell(s, lo);
+    const int d = h - s.hp[lo];
+    e = s.off[t1] + d;
+    pos = s.slot[t1] + d;
+}
+
+__device__ __forceinline__ void home_atom(const Stage& s, int h, int& e, int& pos)
+{
+    int t1;
+    home_atom(s, h, e, pos, t1);
+}
 
 // True when no staged cell of the tile wraps (and the grid has >= 5 cells).
 __device__ __forceinline__ bool tile_interior(const KParams& p, const Tile& g)
 {
-    return p.nc >= 5 && g.cx0 >= 1 && g.cx0 + g.kx <= p.nc - 1 && g.cy >= 1 &&
-           g.cy <= p.nc - 2 && g.cz >= 1 && g.cz <= p.nc - 2;
+    return p.nc >= 5 && g.cx0 >= 1 && g.cx0 + g.kx <= p.nc - 1 && g.cy0 >= 1 &&
+           g.cy0 + g.ky <= p.nc - 1 && g.cz0 >= 1 && g.cz0 + g.kz <= p.nc - 1;
 }
 
 // ---- walking one home atom's list ----
@@ -437,12 +519,13 @@ __device__ __forceinline__ void walk_home(const KParams& p, const Stage& s, int 
     }
 }
 
-// Position of home atom h (LDS when staged).
-__device__ __forceinline__ void home_position(const KParams& p, const Stage& s, int h0, int h,
+// Position of the home atom at LDS entry e and storage slot slot_i (LDS when
+// staged).
+__device__ __forceinline__ void home_position(const KParams& p, const Stage& s, int e,
                                               int slot_i, double& xi, double& yi, double& zi)
 {
     if (s.fits) {
-        lds_xyz(s.p3, h0 + h, xi, yi, zi);
+        lds_xyz(s.p3, e, xi, yi, zi);
     } else {
         xi = p.x[slot_i];
         yi = p.y[slot_i];

@@ -76,7 +76,8 @@ class Grid(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("force_lanes", C.c_int32), ("force_block", C.c_int32),
                 ("nl_block", C.c_int32), ("tile_cells", C.c_int32), ("stage_cap", C.c_int32),
-                ("integrate_grid", C.c_int32), ("nl_method", C.c_int32)]
+                ("integrate_grid", C.c_int32), ("nl_method", C.c_int32),
+                ("tile_y", C.c_int32), ("tile_z", C.c_int32)]
 
 
 class TrajParams(C.Structure):
@@ -273,9 +274,9 @@ def md_traj_backward(ctx, tp: TrajParams, ws_ptr: int, gobs_ptr: int, gx_ptr: in
 
 
 def md_set_tuning(ctx, force_lanes=4, force_block=512, nl_block=0, tile_cells=0, stage_cap=0,
-                  integrate_grid=0, nl_method=MD_NL_AUTO):
+                  integrate_grid=0, nl_method=MD_NL_AUTO, tile_y=0, tile_z=0):
     t = Tuning(int(force_lanes), int(force_block), int(nl_block), int(tile_cells), int(stage_cap),
-               int(integrate_grid), int(nl_method))
+               int(integrate_grid), int(nl_method), int(tile_y), int(tile_z))
     _check(lib().md_set_tuning(ctx, C.byref(t)), "md_set_tuning")
 
 
@@ -459,12 +460,12 @@ class Simulation:
 
     def set_tuning(self, **kw):
         """Change some launch-shape settings; the others keep their last
-        requested values (nl_block, tile_cells, stage_cap and integrate_grid
-        start automatic, 0)."""
+        requested values (nl_block, tile_cells, tile_y, tile_z, stage_cap and
+        integrate_grid start automatic, 0)."""
         if self._tuning is None:
             self._tuning = md_get_tuning(self.ctx)
             self._tuning.update(nl_block=0, tile_cells=0, stage_cap=0, integrate_grid=0,
-                                nl_method=MD_NL_AUTO)
+                                nl_method=MD_NL_AUTO, tile_y=0, tile_z=0)
         req = dict(self._tuning)
         req.update(kw)
         md_set_tuning(self.ctx, **req)
@@ -570,7 +571,8 @@ def _tuning_tuple(t: dict):
     return Tuning(int(t.get("force_lanes", 4)), int(t.get("force_block", 512)),
                   int(t.get("nl_block", 0)), int(t.get("tile_cells", 0)),
                   int(t.get("stage_cap", 0)), int(t.get("integrate_grid", 0)),
-                  int(t.get("nl_method", MD_NL_AUTO)))
+                  int(t.get("nl_method", MD_NL_AUTO)), int(t.get("tile_y", 0)),
+                  int(t.get("tile_z", 0)))
 
 
 class Batch:
@@ -674,7 +676,7 @@ class Batch:
         if self._tuning is None:
             self._tuning = self.get_tuning()
             self._tuning.update(nl_block=0, tile_cells=0, stage_cap=0, integrate_grid=0,
-                                nl_method=MD_NL_AUTO)
+                                nl_method=MD_NL_AUTO, tile_y=0, tile_z=0)
         req = dict(self._tuning)
         req.update(kw)
         t = _tuning_tuple(req)

@@ -26,11 +26,14 @@ def systems(n_replicas=6, n_lo=500, n_hi=6000, jitter=0.03, seed=4):
 def single(sy, precision, batch=None, r=0):
     """The same system alone; with the batch's integration grid for replica r
     (a batch gives each replica a smaller share), so that the kinetic-energy
-    and momentum sums add in the same order."""
+    and momentum sums add in the same order, and its tiling (a system alone
+    prefers at least a tile per CU), so that the per-tile energy partials do."""
     s = md.Simulation(sy["pos"], sy["vel"], sy["L"], r_cut=sy["r_cut"], dt=sy["dt"],
                       skin=sy["skin"], precision=precision)
     if batch is not None:
-        s.set_tuning(integrate_grid=md.md_get_tuning(batch.replicas[r])["integrate_grid"])
+        t = md.md_get_tuning(batch.replicas[r])
+        s.set_tuning(integrate_grid=t["integrate_grid"], tile_cells=t["tile_cells"],
+                     tile_y=t["tile_y"], tile_z=t["tile_z"])
     return s
 
 

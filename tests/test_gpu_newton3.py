@@ -82,7 +82,8 @@ def test_half_forces_fp32_mixed(name):
 
 TUNINGS = ([dict(force_lanes=l, force_block=b) for l in (1, 2, 4, 8) for b in (256, 1024)] +
            [dict(stage_cap=64), dict(stage_cap=64, force_lanes=4, tile_cells=2),
-            dict(tile_cells=1, force_block=64), dict(tile_cells=1000, force_block=512)])
+            dict(tile_cells=1, force_block=64), dict(tile_cells=1000, force_block=512),
+            dict(tile_cells=2, tile_y=3, tile_z=2), dict(tile_y=2, tile_z=2, stage_cap=64)])
 
 
 @pytest.mark.parametrize("name", ["lj32000", "wca108_nc3", "lj4000_noreorder"])
@@ -96,7 +97,7 @@ def test_every_tuning_matches_the_oracle(name):
     ref = oracle.forces_half(s, pos, o_cnt, o_nl)
     base = sim.get_tuning()
     for tu in TUNINGS:
-        kw = dict(base, tile_cells=0, stage_cap=0)
+        kw = dict(base, tile_cells=0, tile_y=0, tile_z=0, stage_cap=0)
         kw.update(tu)
         sim.set_tuning(**kw)
         sim.build_neighbors()

@@ -255,7 +255,13 @@ TUNINGS = ([dict(force_lanes=l, force_block=b) for l in (1, 2, 4, 8) for b in (2
            [dict(nl_method=md.MD_NL_CELL_WAVES, tile_cells=c, stage_cap=cap)
             for c, cap in ((0, 0), (2, 0), (3, 64))] +
            [dict(nl_method=md.MD_NL_LANES, nl_block=b, tile_cells=c)
-            for b, c in ((64, 1), (1024, 0), (128, 6))])
+            for b, c in ((64, 1), (1024, 0), (128, 6))] +
+           # blocks of cells in y and z as well (rows of one cell: tile_y = tile_z = 1)
+           [dict(tile_cells=c, tile_y=y, tile_z=z, nl_method=m)
+            for c, y, z, m in ((8, 1, 1, md.MD_NL_AUTO), (2, 3, 2, md.MD_NL_CELL_WAVES),
+                               (1, 1, 4, md.MD_NL_LANES), (3, 4, 1, md.MD_NL_CELL_WAVES),
+                               (5, 2, 3, md.MD_NL_LANES))] +
+           [dict(tile_y=2, tile_z=2, stage_cap=64), dict(tile_cells=1, tile_y=1, tile_z=1)])
 
 
 @pytest.mark.parametrize("name", ["lj32000_nl", "wca13500_nl", "lj5000_random", "wca108_nc3",
@@ -268,7 +274,7 @@ def test_every_tuning_matches_the_oracle(name):
     ref = oracle.forces_nl(s, pos, o_cnt, o_nl)
     base = sim.get_tuning()
     for tu in TUNINGS:
-        kw = dict(base, tile_cells=0, stage_cap=0)
+        kw = dict(base, tile_cells=0, tile_y=0, tile_z=0, stage_cap=0)
         kw.update(tu)
         sim.set_tuning(**kw)
         sim.build_neighbors()
@@ -284,6 +290,7 @@ def test_tuning_is_validated():
     sim, s, pos, vel = setup("wca108_nc3")
     for bad in (dict(force_lanes=3), dict(force_lanes=16), dict(force_block=96),
                 dict(force_block=2048), dict(nl_block=32), dict(tile_cells=-1),
+                dict(tile_y=-1), dict(tile_z=-2),
                 dict(stage_cap=-5), dict(integrate_grid=-1), dict(integrate_grid=4097),
                 dict(nl_method=3)):
         with pytest.raises(md.MDError):
@@ -294,7 +301,8 @@ def test_tuning_is_validated():
         sim.step(1)
     sim.forces()
     sim.step(1)
-    sim.set_tuning(tile_cells=1)
+    kx = sim.get_tuning()["tile_cells"]
+    sim.set_tuning(tile_cells=1 if kx > 1 else 3)
     with pytest.raises(md.MDError):  # a new tiling needs a new list
         sim.forces()
     sim.build_neighbors()
