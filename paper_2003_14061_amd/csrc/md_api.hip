@@ -242,7 +242,10 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
     b[R_CELL_START] = sizeof(int32_t) * (ncell + 1);
     b[R_CELL_OF] = b[R_SLOT] = b[R_ORDER] = b[R_TMP] = sizeof(int32_t) * n;
     const bool layers = p.pipeline == MD_PIPE_LAYERS;
-    b[R_NL] = layers ? 0 : sizeof(uint16_t) * (size_t)cap * npad;
+    // plus one chunk row past the list: the cell-wave build writes entries
+    // beyond the capacity there instead of testing each store (overflow is
+    // counted and latched all the same)
+    b[R_NL] = layers ? 0 : sizeof(uint16_t) * (size_t)(cap + kChunk) * npad;
     b[R_LAYERS] = sizeof(int32_t) * (size_t)ncell * n_layers;
     b[R_W32] = layers ? sizeof(int32_t) * (size_t)cap * npad : 0;
     b[R_NL_COUNT] = sizeof(int32_t) * npad;

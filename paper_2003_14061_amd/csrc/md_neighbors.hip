@@ -68,7 +68,7 @@ __device__ __forceinline__ int home_cell(const Stage& s, int hc)
     return home_row_cell(s, r) + (a - 1);
 }
 
-template <int kImage, bool kHalf, bool kFits>
+template <int kImage, bool kHalf, bool kFits, bool kSmall>
 __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, int hc)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -76,19 +76,17 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
     // table values are the same in every lane: keep them in scalar registers
     const int hb = uniform(s.off[home_t]), he = uniform(s.off[home_t + 1]);
     const int hslot0 = uniform(s.slot[home_t]);
-    int wa[9], wp[10], wt[9];
+    int wp[10];  // candidates before each window (the windows' own cells follow per lane)
     wp[0] = 0;
 #pragma unroll
     for (int sg = 0; sg < 9; ++sg) {
-        wt[sg] = window_cell(s, home_t, sg);
-        wa[sg] = uniform(s.off[wt[sg]]);
-        wp[sg + 1] = wp[sg] + (uniform(s.off[wt[sg] + 3]) - wa[sg]);
+        const int tw = window_cell(s, home_t, sg);
+        wp[sg + 1] = wp[sg] + (uniform(s.off[tw + 3]) - uniform(s.off[tw]));
     }
     const int ncand = wp[9];
-    const int cap = p.cap;  // a multiple of 4
+    const uint32_t cap = (uint32_t)p.cap;  // a multiple of 4
     uint16_t* nl16 = reinterpret_cast<uint16_t*>(p.nl64);
     const uint32_t npad4 = 4u * (uint32_t)p.npad;  // 16-bit entries per chunk row
-    const bool small = npad4 < (1u << 24);         // row offsets by 24-bit multiply
     for (int h0 = hb; h0 < he; h0 += kWave) {
         const int nhs = he - h0 < kWave ? he - h0 : kWave;
         const bool home_lane = lane < nhs;
@@ -108,25 +106,23 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
             double cx[kNlRounds], cy[kNlRounds], cz[kNlRounds];
             int ce[kNlRounds], cfl[kNlRounds], cpos[kNlRounds];
             uint16_t cenc[kNlRounds];
-            bool cval[kNlRounds];
 #pragma unroll
             for (int r = 0; r < kNlRounds; ++r) {
                 const int k = k0 + r * kWave + lane;
-                cval[r] = k < ncand;
-                int sg = 0;
-#pragma unroll
-                for (int j = 1; j < 9; ++j) sg += k >= wp[j] ? 1 : 0;
-                int a = wa[0], pre = wp[0], t0 = wt[0];
+                const bool valid = k < ncand;
+                int sg = 0, pre = 0;
 #pragma unroll
                 for (int j = 1; j < 9; ++j) {
-                    a = sg == j ? wa[j] : a;
-                    pre = sg == j ? wp[j] : pre;
-                    t0 = sg == j ? wt[j] : t0;
+                    sg += k >= wp[j] ? 1 : 0;
+                    pre = k >= wp[j] ? wp[j] : pre;
                 }
-                const int e = cval[r] ? a + (k - pre) : hb;
+                const int t0 = window_cell(s, home_t, sg);
+                const int e = valid ? s.off[t0] + (k - pre) : hb;
                 const int w = (e >= s.off[t0 + 1] ? 1 : 0) + (e >= s.off[t0 + 2] ? 1 : 0);
-                const int t = cval[r] ? t0 + w : home_t;
-                ce[r] = e;
+                const int t = valid ? t0 + w : home_t;
+                // lanes past the candidates: index -1 (never the home atom) and a
+                // NaN position (never near, under any image rule)
+                ce[r] = valid ? e : -1;
                 cfl[r] = s.flag[t];
                 cpos[r] = s.slot[t] + (e - s.off[t]);
                 cenc[r] = (uint16_t)((uint32_t)e | ((uint32_t)cfl[r] << kEntryBits));
@@ -138,44 +134,57 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
                     cy[r] = p.y[j];
                     cz[r] = p.z[j];
                 }
+                if (!valid) cx[r] = __builtin_nan("");
             }
             for (int hh = 0; hh < nhs; ++hh) {
                 const int eh = h0 + hh;
                 const int pos_i = hslot0 + (eh - hb);
                 const double xi = readlane_f64(hx, hh), yi = readlane_f64(hy, hh),
                              zi = readlane_f64(hz, hh);
-                const int slot_h = __builtin_amdgcn_readlane(slot_l, hh);
-                int m_h = __builtin_amdgcn_readlane(mreg, hh);
-                uint16_t* base = nl16 + (int64_t)slot_h * kChunk;
+                const uint32_t slot4 = 4u * (uint32_t)__builtin_amdgcn_readlane(slot_l, hh);
+                uint32_t m_h = (uint32_t)__builtin_amdgcn_readlane(mreg, hh);
+                // the tests of all rounds first (independent), then the stores
+                bool hit[kNlRounds];
+                uint64_t mk[kNlRounds];
 #pragma unroll
                 for (int r = 0; r < kNlRounds; ++r) {
-                    if (r < nr) {
-                        double dx = xi - cx[r], dy = yi - cy[r], dz = zi - cz[r];
-                        image<kImage>(p, cfl[r], dx, dy, dz);
-                        const bool later = !kHalf || cpos[r] > pos_i;
-                        const bool hit = cval[r] & later & (dist2(dx, dy, dz) < p.rl2) &
-                                         (ce[r] != eh);
-                        const uint64_t mask = __builtin_amdgcn_ballot_w64(hit);
-                        if (hit) {
-                            const uint32_t m = (uint32_t)m_h + __builtin_amdgcn_mbcnt_hi(
-                                (uint32_t)(mask >> 32),
-                                __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                            if (m < (uint32_t)cap) {
-                                const uint32_t row = m / kChunk;
-                                const uint32_t idx = (small ? __umul24(row, npad4)
-                                                            : row * npad4) + m % kChunk;
-                                base[idx] = cenc[r];
-                            }
-                        }
-                        m_h += (int)__popcll(mask);
-                    }
+                    double dx = xi - cx[r], dy = yi - cy[r], dz = zi - cz[r];
+                    image<kImage>(p, cfl[r], dx, dy, dz);
+                    // each condition balloted on its own (the compare results are
+                    // the lane masks; a ballot of their conjunction would turn
+                    // them into a vector and back)
+                    const bool near = dist2(dx, dy, dz) < p.rl2;
+                    const bool other = ce[r] != eh;
+                    const bool later = !kHalf || cpos[r] > pos_i;
+                    mk[r] = __builtin_amdgcn_ballot_w64(near) & __builtin_amdgcn_ballot_w64(other);
+                    if (kHalf) mk[r] &= __builtin_amdgcn_ballot_w64(later);
+                    hit[r] = near & other & later;
                 }
-                mreg = lane == hh ? m_h : mreg;
+#pragma unroll
+                for (int r = 0; r < kNlRounds; ++r) {
+                    if (hit[r]) {
+                        // position m_h plus the hits of lower lanes; past the
+                        // capacity into the spare chunk row (counted, not kept)
+                        uint32_t m = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(mk[r] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk[r], m_h));
+                        m = m < cap ? m : cap;
+                        const uint32_t col = (m & 3u) | slot4;
+                        if (kSmall) {
+                            uint32_t idx = __umul24(m >> 2, npad4) + col;
+                            asm volatile("" : "+v"(idx));  // keep the 32-bit index
+                            nl16[idx] = cenc[r];
+                        } else {
+                            nl16[(size_t)(m >> 2) * npad4 + col] = cenc[r];
+                        }
+                    }
+                    m_h += (uint32_t)__popcll(mk[r]);
+                }
+                mreg = lane == hh ? (int)m_h : mreg;
             }
         }
         // lengths, sentinel padding of the last chunk, displacement references
         if (home_lane) {
-            const int stored = mreg < cap ? mreg : cap;
+            const int stored = mreg < (int)cap ? mreg : (int)cap;
             p.nl_count[slot_l] = stored;
             uint16_t* base = nl16 + (int64_t)slot_l * kChunk;
             for (int mm = stored; mm % kChunk != 0; ++mm)
@@ -331,18 +340,26 @@ __device__ __forceinline__ void nl_tile(const KParams& p, int t, char* smem)
     }
     const int wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const int ncells = g.kx * g.ky * g.kz;
+    // list rows by 24-bit products while 4 n_pad < 2^24
+    const bool small = 4u * (uint32_t)p.npad < (1u << 24);
     for (int hc = wid; hc < ncells; hc += nw) {
         if (!s.fits) {
             if (mode == 2)
-                nl_home_cell<2, kHalf, false>(p, s, hc);
+                nl_home_cell<2, kHalf, false, false>(p, s, hc);
             else
-                nl_home_cell<1, kHalf, false>(p, s, hc);
+                nl_home_cell<1, kHalf, false, false>(p, s, hc);
         } else if (mode == 0) {
-            nl_home_cell<0, kHalf, true>(p, s, hc);
+            if (small)
+                nl_home_cell<0, kHalf, true, true>(p, s, hc);
+            else
+                nl_home_cell<0, kHalf, true, false>(p, s, hc);
         } else if (mode == 1) {
-            nl_home_cell<1, kHalf, true>(p, s, hc);
+            if (small)
+                nl_home_cell<1, kHalf, true, true>(p, s, hc);
+            else
+                nl_home_cell<1, kHalf, true, false>(p, s, hc);
         } else {
-            nl_home_cell<2, kHalf, true>(p, s, hc);
+            nl_home_cell<2, kHalf, true, false>(p, s, hc);
         }
     }
 }

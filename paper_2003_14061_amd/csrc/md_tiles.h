@@ -140,8 +140,10 @@ inline size_t stage_bytes(const KParams& p, int cap, bool aux = false)
            sizeof(int) * (size_t)stage_table_ints(p);
 }
 
-// Candidate rounds (of 64) held in registers by the cell-wave list build.
-constexpr int kNlRounds = 4;
+// Candidate rounds (of 64) held in registers by the cell-wave list build
+// (blocks of 192: the 533 candidates of the dense LJ state take three blocks
+// either way, and three rounds hold fewer registers than four).
+constexpr int kNlRounds = 3;
 
 __device__ __forceinline__ Stage stage_layout(const KParams& p, char* smem, int cap, bool aux)
 {
