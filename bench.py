@@ -53,6 +53,10 @@ def parse():
                     help="skip the 4000-atom cells-only and 256 000-atom WCA lines")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-mixed measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
+    ap.add_argument("--tune-cache",
+                    default=os.path.join(os.path.expanduser("~"), ".cache",
+                                         "paper_2003_14061_amd", "tuning.json"),
+                    help="JSON file of autotuned launch shapes ('' for none)")
     ap.add_argument("--no-newton3", action="store_true",
                     help="skip the third-law (half list, atomic) variant")
     ap.add_argument("--no-layers", action="store_true",
@@ -432,10 +436,11 @@ def run_adjoint(precision, repeats=3):
             "grad_eps": float(gth[0]), "grad_sigma": float(gth[1])}
 
 
-def run_batch(steps=500, warmup=20):
+def run_batch(steps=500, warmup=20, tune_cache=None):
     """The batched ensemble: 64 WCA replicas, N uniform on [500, 32000] and
     rho on [0.6, 0.9] (seeded), T 1, dt 0.005, skin 0.3, FP32-mixed, launch
-    shape from the autotuner, all replicas advanced `steps` steps by one HIP
+    shape (tile block, lanes per atom, workgroup size) from the autotuner or
+    from its cache file tune_cache, all replicas advanced `steps` steps by one HIP
     graph launch.  Throughput = total atoms x steps / wall time; the force
     roofline fraction uses the mean list length over all replicas and the
     batched force pass timed alone with HIP events."""
@@ -449,8 +454,13 @@ def run_batch(steps=500, warmup=20):
                for w in reps]
     n_tot = sum(w.n for w in reps)
     b = md.Batch(systems, precision="fp32")
-    cands = [dict(force_lanes=l, force_block=fb) for l in (2, 4, 8) for fb in (256, 512)]
-    best, costs = b.autotune(cands, reps=3)
+    shapes = [{}, dict(tile_cells=4, tile_y=4, tile_z=4), dict(tile_cells=4, tile_y=2, tile_z=2),
+              dict(tile_cells=8, tile_y=2, tile_z=2)]
+    cands = [dict(force_lanes=l, force_block=fb, **t) for t in shapes for l in (2, 4, 8)
+             for fb in (256, 512)]
+    if tune_cache:
+        os.makedirs(os.path.dirname(os.path.abspath(tune_cache)), exist_ok=True)
+    best, costs = b.autotune(cands, reps=3, cache_path=tune_cache or None)
     b.run(warmup, graph=True)  # builds the warm-up graph
     b.synchronize()
     b.run(steps, graph=True)  # capture and instantiate the timed graph once
@@ -474,7 +484,9 @@ def run_batch(steps=500, warmup=20):
     flags = max(b.reduce(r)["flags"] for r in range(len(reps)))
     return {"value": n_tot * steps / wall, "ms_per_step": 1e3 * wall / steps,
             "n_atoms": n_tot, "replicas": len(reps), "steps": steps,
-            "autotune": {"best": cands[best], "costs_ms": [round(c, 4) for c in costs]},
+            "autotune": {"best": cands[best] if best >= 0 else b.get_tuning(),
+                         "cache": tune_cache or None, "cache_hit": all(c < 0 for c in costs),
+                         "costs_ms": [round(c, 4) for c in costs]},
             "force_ms_avg": round(f_ms, 5), "mean_nl": round(mean_nl, 2),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -674,7 +686,7 @@ def main():
     if not args.no_small:
         out["wca_4000_cells"], out["wca_256k"] = run_small(args.drift_steps)
     if not args.no_batch:
-        bt = run_batch(steps=args.batch_steps)
+        bt = run_batch(steps=args.batch_steps, tune_cache=args.tune_cache)
         print(f"[bench] batch done: {bt['value']:.3e} atom-steps/s", file=sys.stderr, flush=True)
         out["batched_ensemble"] = dict(bt, workload="64 WCA replicas, N~U[500,32000], "
                                        "rho~U[0.6,0.9], T=1, dt=0.005, skin 0.3, FP32-mixed, "

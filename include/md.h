@@ -356,6 +356,17 @@ typedef struct {
 md_status md_set_tuning(md_ctx* ctx, const md_tuning* tuning);
 md_status md_get_tuning(const md_ctx* ctx, md_tuning* tuning);
 
+/* md_autotune: the autotuner of md_batch_autotune for one system (tiled
+ * pipeline, neighbor-list mode): each candidate builds the cells once, then
+ * `reps` lists and force passes on the current state are timed; the cost is
+ * the mean force pass plus a tenth of the mean list build.  Leaves the
+ * cheapest shape set, with cells, list and forces rebuilt for it (md_step
+ * may follow).  ms_out[n], *best and cache_path (keyed by the system, the
+ * candidate list and the device) as for md_batch_autotune.  Synchronizes the
+ * stream. */
+md_status md_autotune(md_ctx* ctx, const md_tuning* candidates, int32_t n, int32_t reps,
+                      const char* cache_path, double* ms_out, int32_t* best);
+
 /* md_set_timing: when enable != 0, bracket every force-pass launch with HIP
  * events on the bound stream; md_get_timing returns the summed elapsed time
  * (ms) and the number of timed launches since timing was enabled, and
@@ -488,9 +499,13 @@ md_status md_batch_get_tuning(const md_batch* b, md_tuning* tuning);
  * pass plus a tenth of the mean list build (a rebuild every ~10 steps).
  * Writes the costs (ms) to ms_out[n] and the index of the cheapest to *best,
  * and leaves the batch set to it and prepared.  Synchronizes the stream.
- * Positions are only folded into the box and, with reorder, permuted. */
+ * Positions are only folded into the box and, with reorder, permuted.
+ * cache_path (NULL: none) names a JSON file of earlier results, keyed by
+ * the replicas' sizes and geometry, the candidate list and the device: on a
+ * hit the cached shape is applied without timing (ms_out all -1, *best its
+ * index among the candidates); otherwise the winner is added to the file. */
 md_status md_batch_autotune(md_batch* b, const md_tuning* candidates, int32_t n, int32_t reps,
-                            double* ms_out, int32_t* best);
+                            const char* cache_path, double* ms_out, int32_t* best);
 
 void md_batch_destroy(md_batch* b);
 

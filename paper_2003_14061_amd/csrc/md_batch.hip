@@ -327,10 +327,20 @@ extern "C" md_status md_batch_get_tuning(const md_batch* b, md_tuning* t)
 }
 
 extern "C" md_status md_batch_autotune(md_batch* b, const md_tuning* cand, int32_t n, int32_t reps,
-                                       double* ms_out, int32_t* best)
+                                       const char* cache_path, double* ms_out, int32_t* best)
 {
     if (!b || !cand || n < 1 || reps < 1 || !ms_out || !best) return MD_ERR_ARG;
     if (!b->bound) return MD_ERR_NOT_BOUND;
+    const uint64_t key = tuning_key_batch(b->rep.data(), (int32_t)b->rep.size(), cand, n);
+    md_tuning hit;
+    if (tuning_cache_get(cache_path, key, &hit)) {
+        for (int32_t i = 0; i < n; ++i) ms_out[i] = -1.0;
+        *best = -1;
+        for (int32_t i = 0; i < n; ++i)
+            if (memcmp(&cand[i], &hit, sizeof hit) == 0) *best = i;
+        md_status st = md_batch_set_tuning(b, &hit);
+        return st == MD_OK ? prepare(b) : st;
+    }
     hipEvent_t ev[3];
     for (int k = 0; k < 3; ++k)
         if (hipEventCreate(&ev[k]) != hipSuccess) return MD_ERR_HIP;
@@ -358,7 +368,9 @@ extern "C" md_status md_batch_autotune(md_batch* b, const md_tuning* cand, int32
     if (st != MD_OK) return st;
     *best = arg;
     if ((st = md_batch_set_tuning(b, &cand[arg])) != MD_OK) return st;
-    return prepare(b);
+    if ((st = prepare(b)) != MD_OK) return st;
+    tuning_cache_put(cache_path, key, cand[arg], ms_out[arg]);
+    return MD_OK;
 }
 
 extern "C" void md_batch_destroy(md_batch* b)

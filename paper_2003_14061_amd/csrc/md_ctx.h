@@ -25,6 +25,13 @@ enum Region {
 struct md_ctx;
 void replan_tiles(md_ctx* c);  // the tiling again, after a change of min_tiles
 
+// Tuning cache (md_tune.hip): keys of a system or a batch with a candidate
+// list on this device, and the cached tuning of a key in a cache file.
+uint64_t tuning_key_ctx(const md_ctx* c, const md_tuning* cand, int32_t n);
+uint64_t tuning_key_batch(const md_ctx* const* reps, int32_t r, const md_tuning* cand, int32_t n);
+bool tuning_cache_get(const char* path, uint64_t key, md_tuning* out);
+bool tuning_cache_put(const char* path, uint64_t key, const md_tuning& t, double ms);
+
 struct md_ctx {
     md_params prm;
     md_grid geo;

@@ -36,7 +36,8 @@ EXPORTS = ("md_init", "md_workspace_bytes", "md_geometry", "md_layout", "md_bind
            "md_traj_backward", "md_batch_init", "md_batch_workspace_bytes", "md_batch_replica",
            "md_batch_bind", "md_batch_prepare", "md_batch_forces", "md_batch_layout",
            "md_batch_run", "md_batch_set_tuning",
-           "md_batch_get_tuning", "md_batch_autotune", "md_batch_destroy", "md_destroy",
+           "md_batch_get_tuning", "md_batch_autotune", "md_autotune", "md_batch_destroy",
+           "md_destroy",
            "md_status_str", "md_set_bonded")
 
 
@@ -146,7 +147,10 @@ def lib():
         "md_batch_set_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
         "md_batch_get_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
         "md_batch_autotune": (C.c_int, [P, C.POINTER(Tuning), C.c_int32, C.c_int32,
-                                        C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+                                        C.c_char_p, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_int32)]),
+        "md_autotune": (C.c_int, [P, C.POINTER(Tuning), C.c_int32, C.c_int32, C.c_char_p,
+                                  C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
         "md_batch_destroy": (None, [P]),
         "md_destroy": (None, [P]),
         "md_status_str": (C.c_char_p, [C.c_int32]),
@@ -474,6 +478,21 @@ class Simulation:
     def get_tuning(self):
         return md_get_tuning(self.ctx)
 
+    def autotune(self, candidates, reps=3, cache_path=None):
+        """md_autotune: time each candidate shape (dicts of md_tuning fields)
+        on the current state and keep the cheapest (cells, list and forces
+        rebuilt for it); returns (index, costs in ms).  With cache_path, a
+        cached choice for this system, candidate list and device is taken
+        instead (costs -1) and a new one is stored."""
+        arr = (Tuning * len(candidates))(*[_tuning_tuple(c) for c in candidates])
+        ms = (C.c_double * len(candidates))()
+        best = C.c_int32()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(lib().md_autotune(self.ctx, arr, len(candidates), int(reps), path, ms,
+                                 C.byref(best)), "md_autotune")
+        self._tuning = dict(candidates[best.value]) if best.value >= 0 else None
+        return best.value, list(ms)
+
     def set_timing(self, enable=True):
         md_set_timing(self.ctx, enable)
 
@@ -688,15 +707,18 @@ class Batch:
         _check(lib().md_batch_get_tuning(self.ctx, C.byref(t)), "md_batch_get_tuning")
         return {f: getattr(t, f) for f, _ in Tuning._fields_}
 
-    def autotune(self, candidates, reps=3):
+    def autotune(self, candidates, reps=3, cache_path=None):
         """Time each candidate shape (dicts of md_tuning fields) and keep the
-        cheapest; returns (index, costs in ms)."""
+        cheapest; returns (index, costs in ms).  With cache_path, a cached
+        choice for this batch, candidate list and device is taken instead
+        (costs -1) and a new one is stored."""
         arr = (Tuning * len(candidates))(*[_tuning_tuple(c) for c in candidates])
         ms = (C.c_double * len(candidates))()
         best = C.c_int32()
-        _check(lib().md_batch_autotune(self.ctx, arr, len(candidates), int(reps), ms,
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(lib().md_batch_autotune(self.ctx, arr, len(candidates), int(reps), path, ms,
                                        C.byref(best)), "md_batch_autotune")
-        self._tuning = dict(candidates[best.value])
+        self._tuning = dict(candidates[best.value]) if best.value >= 0 else self.get_tuning()
         return best.value, list(ms)
 
     # -- per replica

@@ -127,9 +127,11 @@ def test_layer_pipeline_geometry_and_arrays():
             for which in (md.MD_ARR_LAYERS, md.MD_ARR_LAYER_COUNT):
                 with pytest.raises(md.MDError):
                     md.md_layout(tiled, which)
-            # the 32-bit matrix is twice the 16-bit one
+            # the 32-bit matrix in place of the 16-bit one, which carries one
+            # spare row of 4-entry chunks past the capacity
             wl = md.md_workspace_bytes(ctx) - md.md_workspace_bytes(tiled)
-            assert wl >= 2 * g.nl_capacity * g.n_pad + 4 * g.n_cells * g.n_layers
+            assert wl >= (4 * g.nl_capacity - 2 * (g.nl_capacity + 4)) * g.n_pad + \
+                4 * g.n_cells * g.n_layers
         finally:
             md.md_destroy(ctx)
             md.md_destroy(tiled)

@@ -104,3 +104,56 @@ def test_batch_arguments_are_checked():
     b = md.Batch(sys_)
     with pytest.raises(md.MDError):  # not prepared yet
         b.run(5)
+
+
+def test_autotune_cache_keeps_and_reuses_the_choice(tmp_path):
+    sys_ = systems(n_replicas=3, seed=12)
+    cache = tmp_path / "tuning.json"
+    cands = [dict(force_lanes=l, force_block=fb) for l in (2, 4) for fb in (256, 512)] + \
+        [dict(force_lanes=2, force_block=256, tile_cells=4, tile_y=2, tile_z=2)]
+    b = md.Batch(sys_, precision="fp32")
+    best, costs = b.autotune(cands, reps=2, cache_path=str(cache))
+    assert costs[best] == min(costs) and min(costs) > 0
+    text = cache.read_text()
+    assert text.startswith("{") and text.rstrip().endswith("}") and text.count('"ms"') == 1
+    # the same batch and candidates again: taken from the file, not timed
+    b2 = md.Batch(sys_, precision="fp32")
+    best2, costs2 = b2.autotune(cands, reps=2, cache_path=str(cache))
+    assert best2 == best and all(c == -1.0 for c in costs2)
+    t = b2.get_tuning()
+    assert t["force_lanes"] == cands[best]["force_lanes"]
+    b2.run(10)
+    assert max(b2.reduce(r)["flags"] for r in range(len(sys_))) == 0
+    # another candidate list is another entry
+    b3 = md.Batch(sys_, precision="fp32")
+    b3.autotune(cands[:2], reps=2, cache_path=str(cache))
+    assert cache.read_text().count('"ms"') == 2
+
+
+def test_single_system_autotune_with_cache(tmp_path):
+    import oracle
+    from gpu_helpers import force_errors, pair, state
+
+    L, pos, vel = state(32000, 0.8442, 13, jitter=0.05)
+    sim, s = pair(pos, vel, L, r_cut=2.5)
+    sim.prepare()
+    cands = [dict(force_lanes=4, force_block=512), dict(force_lanes=2, force_block=512),
+             dict(force_lanes=4, force_block=512, tile_cells=8, tile_y=1, tile_z=1),
+             dict(force_lanes=4, force_block=256, tile_cells=2, tile_y=2, tile_z=2)]
+    cache = tmp_path / "tuning.json"
+    best, costs = sim.autotune(cands, reps=2, cache_path=str(cache))
+    assert costs[best] == min(costs) and min(costs) > 0
+    # forces of the chosen shape are current and match the oracle
+    st = sim.state()
+    nc = oracle.cells_per_side(s.L, s.r_cut + s.skin)
+    p = np.mod(st["pos"], L)
+    cells = oracle.build_cells(s, nc, p)
+    cnt, nl, _ = oracle.build_nl(s, nc, p, cells)
+    per_atom, normwise = force_errors(st["f"], oracle.forces_nl(s, p, cnt, nl))
+    assert per_atom <= 1e-12 and normwise <= 1e-12
+    sim.step(40)
+    assert sim.reduce()["flags"] == 0
+    sim2, _ = pair(pos, vel, L, r_cut=2.5)
+    sim2.prepare()
+    best2, costs2 = sim2.autotune(cands, reps=2, cache_path=str(cache))
+    assert best2 == best and all(c == -1.0 for c in costs2)
