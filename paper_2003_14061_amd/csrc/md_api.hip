@@ -240,7 +240,8 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
     b[R_DEV] = sizeof(DevState);
     b[R_CELL_COUNT] = sizeof(int32_t) * ncell;
     b[R_CELL_START] = sizeof(int32_t) * (ncell + 1);
-    b[R_CELL_OF] = b[R_SLOT] = b[R_ORDER] = b[R_TMP] = sizeof(int32_t) * n;
+    b[R_CELL_OF] = b[R_SLOT] = b[R_ORDER] = sizeof(int32_t) * n;
+    b[R_TMP] = 2 * sizeof(int32_t) * n;  // slot -> atom, then slot -> permanent id
     const bool layers = p.pipeline == MD_PIPE_LAYERS;
     // plus one chunk row past the list: the cell-wave build writes entries
     // beyond the capacity there instead of testing each store (overflow is

@@ -33,18 +33,20 @@ struct md_batch {
 
 namespace {
 
-// Workgroups per replica of the rebuild-gated grid-stride kernels, and of
-// the integration (1024-thread workgroups), in a batch of R.
+// Workgroups per replica of the rebuild-gated grid-stride kernels in a
+// batch of R.
 int gate_share(int R)
 {
     const int g = 4 * kGateGridDefault / R;
     return g > 64 ? g : 64;
 }
 
-int integrate_share(int R)
+// A replica's integration workgroups: one lane per atom (its grid-stride
+// loop runs once), so that large and small replicas finish together.
+int integrate_share(int64_t n)
 {
-    const int g = 2 * kIntegrateGridDefault / R;
-    return g > 8 ? g : 8;
+    const int64_t g = (n + kIntThreads - 1) / kIntThreads;
+    return (int)(g < 1 ? 1 : g > kIntegrateGridDefault ? kIntegrateGridDefault : g);
 }
 
 // Most workgroups replica c can ask of any grid rule, for any tuning.
@@ -94,7 +96,8 @@ md_status upload(md_batch* b)
             first[(size_t)k * (R + 1) + r] = (int32_t)off;
             count[(size_t)k * R + r] = n;
             off += n;
-            if (r + 1 < R) off = (off + 7) / 8 * 8;  // next replica starts on XCD 0
+            // the tile grids start each replica on XCD 0
+            if (r + 1 < R && (k == G_TILES || k == G_NL)) off = (off + 7) / 8 * 8;
         }
         if (off > 0x7fffffff) return MD_ERR_ARG;
         first[(size_t)k * (R + 1) + R] = (int32_t)off;
@@ -207,7 +210,7 @@ extern "C" md_status md_batch_init(const md_params* params, int32_t n_replicas, 
         // the gated per-atom and per-cell kernels and the integration share
         // the machine among the replicas
         c->kp.gate_grid = gate_share(n_replicas);
-        c->kp.int_grid = integrate_share(n_replicas);
+        c->kp.int_grid = integrate_share(p.n_atoms);
         c->min_tiles = 0;  // the replicas together fill the machine
         replan_tiles(c);
         b->rep.push_back(c);
@@ -312,7 +315,7 @@ extern "C" md_status md_batch_set_tuning(md_batch* b, const md_tuning* t)
     for (md_ctx* c : b->rep) {
         md_status st = md_set_tuning(c, t);
         if (st != MD_OK) return st;
-        if (t->integrate_grid == 0) c->kp.int_grid = integrate_share(R);
+        if (t->integrate_grid == 0) c->kp.int_grid = integrate_share(c->prm.n_atoms);
     }
     b->prepared = false;
     set_flags(b, false);

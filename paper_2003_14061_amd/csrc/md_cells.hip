@@ -6,7 +6,8 @@
 //                atom's (unordered) rank in its cell
 //   k_scan_*     N3/N4: exclusive scan of the counts -> cell_start, and the
 //                largest occupancy; clears the counts for the next build
-//   k_scatter    slots grouped by cell (in the order the atomics gave)
+//   k_scatter    slots grouped by cell (in the order the atomics gave), with
+//                each slot's permanent id beside it
 //   k_cellsort   inside each cell, ascending permanent id (the paper leaves
 //                the order open; a fixed order makes the list reproducible):
 //                each atom's place is the number of its cell's members with
@@ -73,21 +74,26 @@ __global__ void k_bin(B b, int force)
             c = cell_of_pos(x, y, z, p);
             p.cell_of[i] = c;
         }
-        // Atoms stored in cell order put a wave's 64 atoms into a few cells:
-        // the lanes of one cell take one atomic together and rank themselves
-        // by their position in the wave (the in-cell order is fixed later).
-        uint64_t todo = __ballot(act);
-        while (todo) {
-            const int leader = __ffsll((unsigned long long)todo) - 1;
-            const int cl = __shfl(c, leader, kWave);
-            const uint64_t same = __ballot(act && c == cl);
-            int base = 0;
-            if (lane == leader) base = atomicAdd(&p.cell_count[cl], (int)__popcll(same));
-            base = __shfl(base, leader, kWave);
-            if (act && c == cl)
-                p.slot[i] = base + (int)__popcll(same & ((1ull << lane) - 1ull));
-            todo &= ~same;
+        // Atoms stored in cell order put a wave's lanes into runs of one
+        // cell: the first lane of each run takes one atomic for the whole run
+        // (all runs of the wave at once) and the others rank themselves by
+        // their distance from it.  A cell met in two runs takes two atomics;
+        // the in-cell order is fixed later, so only distinct slots matter.
+        const int prev = __shfl_up(c, 1, kWave);
+        const bool head = act && (lane == 0 || prev != c);
+        const uint64_t heads = __ballot(head);
+        const int n_act = (int)__popcll(__ballot(act));  // active lanes are a prefix
+        const uint64_t upto = (2ull << lane) - 1ull;     // lanes 0..lane
+        const int h = act ? 63 - (int)__clzll(heads & upto) : lane;
+        int base = 0;
+        if (head) {
+            const uint64_t later = heads & ~upto;
+            int end = later ? (int)__ffsll((unsigned long long)later) - 1 : kWave;
+            end = end < n_act ? end : n_act;
+            base = atomicAdd(&p.cell_count[c], end - lane);
         }
+        base = __shfl(base, h, kWave);
+        if (act) p.slot[i] = base + (lane - h);
     }
 }
 
@@ -190,8 +196,11 @@ __global__ void k_scatter(B b, int force)
     KParams p;
     if (!b.fetch(G_ATOMS, wg, p)) return;
     if (!rebuild_on(p, force)) return;
-    for (int i = wg.id * blockDim.x + threadIdx.x; i < p.n; i += wg.n * blockDim.x)
-        p.tmp[p.cell_start[p.cell_of[i]] + p.slot[i]] = i;
+    for (int i = wg.id * blockDim.x + threadIdx.x; i < p.n; i += wg.n * blockDim.x) {
+        const int q = p.cell_start[p.cell_of[i]] + p.slot[i];
+        p.tmp[q] = i;
+        p.tmp[p.n + q] = p.id[i];  // the ids of a cell side by side, for k_cellsort
+    }
 }
 
 // Canonical order inside each cell: ascending permanent id.  One lane per
@@ -206,13 +215,15 @@ __global__ void k_cellsort(B b, int force)
     KParams p;
     if (!b.fetch(G_ATOMS, wg, p)) return;
     if (!rebuild_on(p, force)) return;
+    const int32_t* ids = p.tmp + p.n;  // ids in slot order (k_scatter)
     for (int q = wg.id * blockDim.x + threadIdx.x; q < p.n; q += wg.n * blockDim.x) {
         const int s = p.tmp[q];
         const int c = p.cell_of[s];
         const int a = p.cell_start[c], cnt = p.cell_start[c + 1] - a;
-        const int key = p.id[s];
+        const int key = ids[q];
         int rank = 0;
-        for (int j = 0; j < cnt; ++j) rank += p.id[p.tmp[a + j]] < key ? 1 : 0;
+#pragma unroll 4
+        for (int j = 0; j < cnt; ++j) rank += ids[a + j] < key ? 1 : 0;
         const int d = a + rank;
         p.order[d] = s;
         if (kPermute) {
