@@ -41,11 +41,12 @@ int gate_share(int R)
     return g > 64 ? g : 64;
 }
 
-// A replica's integration workgroups: one lane per atom (its grid-stride
-// loop runs once), so that large and small replicas finish together.
+// A replica's integration workgroups: one per 8192 atoms (eight per lane),
+// so that large and small replicas finish together; fewer, longer
+// workgroups measured faster than one lane per atom.
 int integrate_share(int64_t n)
 {
-    const int64_t g = (n + kIntThreads - 1) / kIntThreads;
+    const int64_t g = (n + 8 * kIntThreads - 1) / (8 * kIntThreads);
     return (int)(g < 1 ? 1 : g > kIntegrateGridDefault ? kIntegrateGridDefault : g);
 }
 

@@ -11,17 +11,22 @@
 // paper refreshes "at intervals of several time steps", section 2.3, from a
 // bound on the maximal velocity; here the bound is the displacement itself).
 //
-// Reductions (section 2.3, F2 and the completion scheme that follows it):
-// each workgroup writes its partial sums, and the last workgroup to finish,
-// found with an atomic counter and a memory fence, sums all partials in
-// workgroup order and publishes the result on the device.
+// Reductions (section 2.3, F2): each integration workgroup writes its
+// partial sums, and k_int_finish, one workgroup per system launched right
+// after, sums them in workgroup order and publishes the result on the
+// device (the rebuild decision, the step count, the history record).  The
+// paper's completion scheme, where the last workgroup to finish does this,
+// is used by the one-off observables pass (k_observe); per step it would
+// cost every workgroup an agent-scope release, which on this GPU writes
+// back its XCD's L2 and measured several microseconds per launch, more
+// than the extra launch.
 #include "md_device.h"
 
 namespace md {
 
-// Sum partials [nb][stride] (component k) over workgroups in a fixed order.
-// Called only by the last workgroup (see last_block), reading the partials
-// with coherent loads.
+// Sum partials [nb][stride] (component k) over workgroups in a fixed order,
+// by one workgroup (k_int_finish, or the last one of k_observe, see
+// last_block), reading the partials with coherent loads.
 __device__ double finish_sum(const double* part, int nb, int stride, int k, double* red)
 {
     double v[1] = {0.0};
@@ -172,10 +177,23 @@ __global__ __launch_bounds__(kIntThreads) void k_integrate(B b, int phase, int r
         o[3] = acc[3];
         o[4] = dmax2;
     }
-    if (!last_block(p.dev, wg.n)) return;
-    if (phase >= 1) record_step(p, wg.n, record_every, red);
+}
+
+// The end of an integration pass (one workgroup per system): count the
+// step and record it (phase >= 1), and from the largest displacement decide
+// whether the cells and list are rebuilt before the next force pass
+// (phase <= 1).
+template <class B>
+__global__ __launch_bounds__(kFinishThreads) void k_int_finish(B b, int phase, int record_every)
+{
+    Wg wg;
+    KParams p;
+    if (!b.fetch(G_ONE, wg, p)) return;
+    __shared__ double red[(kFinishThreads / kWave) * 5];
+    const int n_wg = grid_of(p, G_INTEGRATE);
+    if (phase >= 1) record_step(p, n_wg, record_every, red);
     if (phase <= 1) {
-        const double m = finish_max(p.ipart, wg.n, 8, 4, red);
+        const double m = finish_max(p.ipart, n_wg, 8, 4, red);
         if (threadIdx.x == 0) {
             DevState* d = p.dev;
             d->dmax2 = m;
@@ -184,7 +202,6 @@ __global__ __launch_bounds__(kIntThreads) void k_integrate(B b, int phase, int r
             if (rb) d->n_rebuilds += 1;
         }
     }
-    if (threadIdx.x == 0) p.dev->blocks_done = 0;
 }
 
 // Observables of the current state: K and P from the velocities, U and W
@@ -237,6 +254,8 @@ static void integrate_seq(const B& b, const LaunchShape& sh, int phase, int reco
         hipLaunchKernelGGL((k_integrate<double, B>), g, t, 0, s, b, phase, record_every);
     else
         hipLaunchKernelGGL((k_integrate<float, B>), g, t, 0, s, b, phase, record_every);
+    hipLaunchKernelGGL(k_int_finish<B>, dim3(sh.grid[G_ONE]), dim3(kFinishThreads), 0, s, b,
+                       phase, record_every);
 }
 
 void launch_integrate(const KParams& p, int phase, int record_every, hipStream_t s)

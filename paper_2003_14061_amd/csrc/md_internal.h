@@ -17,6 +17,7 @@ constexpr int kHistCap = 4096;     // history records kept on the device
 constexpr int kIntegrateGridMax = 4096;  // largest grid of the grid-stride per-atom kernels
 constexpr int kIntegrateGridDefault = 256;
 constexpr int kIntThreads = 1024;        // workgroup of the integration and observables
+constexpr int kFinishThreads = 256;      // workgroup of the per-system end of a pass
 constexpr int kGateGridDefault = 2048;   // per system; a batch divides it among its replicas
 
 // Device-resident control block (first bytes of the workspace).
@@ -205,9 +206,10 @@ struct Single {
 };
 
 // Independent replicas in one launch.  For grid rule k, replica r owns
-// workgroups [first[k][r], first[k][r] + count[k][r]); first is rounded up
-// to a multiple of 8 so that the XCD-aware tile order (workgroup b runs on
-// XCD b mod 8) holds inside every replica.  rep_of maps every workgroup of a
+// workgroups [first[k][r], first[k][r] + count[k][r]); for the tile rules
+// first is rounded up to a multiple of 8 so that the XCD-aware tile order
+// (workgroup b runs on XCD b mod 8) holds inside every replica.  rep_of maps
+// every workgroup of a
 // launch of rule k (from rep_base[k]) to its replica in one load; workgroups
 // in the gaps map to the replica before them and return.
 struct Batch {
