@@ -57,6 +57,9 @@ def parse():
                     default=os.path.join(os.path.expanduser("~"), ".cache",
                                          "paper_2003_14061_amd", "tuning.json"),
                     help="JSON file of autotuned launch shapes ('' for none)")
+    ap.add_argument("--batch-tuning", default="",
+                    help="JSON object of md_tuning fields: the batch runs with this shape "
+                         "instead of autotuning (for profiling)")
     ap.add_argument("--no-newton3", action="store_true",
                     help="skip the third-law (half list, atomic) variant")
     ap.add_argument("--no-layers", action="store_true",
@@ -399,8 +402,9 @@ def run_adjoint(precision, repeats=3):
     20, loss = mean potential energy per atom + sum_b (g_b - g*_b)^2 over 50
     soft g(r) bins on [0, 2.5), g* from a seeded reference run at
     (eps, sigma) = (1.05, 0.98) from the same initial state.  Forward = the
-    checkpointed run with its observables; backward = segment recompute plus
-    the reverse pass.  Median of `repeats` timings of each."""
+    checkpointed run with its observables (each kernel launched directly);
+    backward = segment recompute plus the reverse pass.  Median of `repeats`
+    timings of each."""
     import torch
 
     from paper_2003_14061_amd import inputs, md
@@ -413,7 +417,6 @@ def run_adjoint(precision, repeats=3):
                              eps=eps, sigma=sigma, precision=precision, reorder=False)
 
     target = sim_at(1.05, 0.98).traj_forward(S, k, B, 2.5)[1:]
-    sim = sim_at(1.0, 1.0)
     tf, tb = [], []
     for _ in range(repeats + 1):  # the first pass is a warm-up
         sim = sim_at(1.0, 1.0)
@@ -433,10 +436,11 @@ def run_adjoint(precision, repeats=3):
     fwd, bwd = tf[len(tf) // 2], tb[len(tb) // 2]
     return {"ratio": bwd / fwd, "forward_ms": 1e3 * fwd, "backward_ms": 1e3 * bwd,
             "forward_atom_steps_per_s": w.n * S / fwd,
+            "forward_us_per_step": 1e6 * fwd / S,
             "grad_eps": float(gth[0]), "grad_sigma": float(gth[1])}
 
 
-def run_batch(steps=500, warmup=20, tune_cache=None):
+def run_batch(steps=500, warmup=20, tune_cache=None, fixed_tuning=None):
     """The batched ensemble: 64 WCA replicas, N uniform on [500, 32000] and
     rho on [0.6, 0.9] (seeded), T 1, dt 0.005, skin 0.3, FP32-mixed, launch
     shape (tile block, lanes per atom, workgroup size) from the autotuner or
@@ -458,9 +462,14 @@ def run_batch(steps=500, warmup=20, tune_cache=None):
               dict(tile_cells=8, tile_y=2, tile_z=2)]
     cands = [dict(force_lanes=l, force_block=fb, **t) for t in shapes for l in (2, 4, 8)
              for fb in (256, 512)]
-    if tune_cache:
-        os.makedirs(os.path.dirname(os.path.abspath(tune_cache)), exist_ok=True)
-    best, costs = b.autotune(cands, reps=3, cache_path=tune_cache or None)
+    if fixed_tuning:  # a given shape instead of the autotuner (profiling runs)
+        cands, best, costs = [fixed_tuning], 0, [-1.0]
+        b.set_tuning(**fixed_tuning)
+        b.prepare()
+    else:
+        if tune_cache:
+            os.makedirs(os.path.dirname(os.path.abspath(tune_cache)), exist_ok=True)
+        best, costs = b.autotune(cands, reps=3, cache_path=tune_cache or None)
     b.run(warmup, graph=True)  # builds the warm-up graph
     b.synchronize()
     b.run(steps, graph=True)  # capture and instantiate the timed graph once
@@ -485,7 +494,8 @@ def run_batch(steps=500, warmup=20, tune_cache=None):
     return {"value": n_tot * steps / wall, "ms_per_step": 1e3 * wall / steps,
             "n_atoms": n_tot, "replicas": len(reps), "steps": steps,
             "autotune": {"best": cands[best] if best >= 0 else b.get_tuning(),
-                         "cache": tune_cache or None, "cache_hit": all(c < 0 for c in costs),
+                         "cache": tune_cache or None, "fixed": bool(fixed_tuning),
+                         "cache_hit": not fixed_tuning and all(c < 0 for c in costs),
                          "costs_ms": [round(c, 4) for c in costs]},
             "force_ms_avg": round(f_ms, 5), "mean_nl": round(mean_nl, 2),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -686,7 +696,8 @@ def main():
     if not args.no_small:
         out["wca_4000_cells"], out["wca_256k"] = run_small(args.drift_steps)
     if not args.no_batch:
-        bt = run_batch(steps=args.batch_steps, tune_cache=args.tune_cache)
+        bt = run_batch(steps=args.batch_steps, tune_cache=args.tune_cache,
+                       fixed_tuning=json.loads(args.batch_tuning) if args.batch_tuning else None)
         print(f"[bench] batch done: {bt['value']:.3e} atom-steps/s", file=sys.stderr, flush=True)
         out["batched_ensemble"] = dict(bt, workload="64 WCA replicas, N~U[500,32000], "
                                        "rho~U[0.6,0.9], T=1, dt=0.005, skin 0.3, FP32-mixed, "

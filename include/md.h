@@ -301,7 +301,9 @@ md_status md_step(md_ctx* ctx, int32_t n_steps, int32_t record_every);
 /* md_set_graph: with enable != 0 md_step replays runs of 32 steps from a HIP
  * graph captured at its first use (recaptured after md_bind, md_set_tuning or
  * a different record_every); the first step of a call and the remainder are
- * launched directly.  The default is on for systems of at most 131 072 atoms,
+ * launched directly.  A call of 10 to 32 steps replays one graph of all its
+ * steps but the first (recaptured when that length changes), and calls of up
+ * to 9 steps launch directly.  The default is on for systems of at most 131 072 atoms,
  * whose steps are bound by launch latency, and off above (measured on
  * MI355X: graph replays pay less per idle kernel but slightly more between
  * long ones).  When the bound stream is the

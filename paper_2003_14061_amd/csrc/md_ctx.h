@@ -57,6 +57,7 @@ struct md_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int g_record = -1;                     // record_every the graph was captured with
+    int g_len = 0;                         // steps in the graph
     hipStream_t g_run = nullptr;           // stream it was captured on
     hipStream_t gstream = nullptr;         // own stream, when the bound one is the null stream
     hipEvent_t gev[2] = {nullptr, nullptr};

@@ -64,3 +64,16 @@ def test_graph_on_a_caller_stream_and_after_a_new_launch_shape():
     got = run(True, 70, 1, tuning=t, **dict(kw))
     for k in ("pos", "vel", "f"):
         assert np.array_equal(ref[2][k], got[2][k]), k
+
+
+@pytest.mark.parametrize("steps", [9, 10, 20, 33])
+def test_short_calls_replay_a_graph_of_their_length(steps):
+    """Calls of 10-32 steps replay one graph of steps - 1; 9 launch directly;
+    repeated calls of one length reuse it, a new length recaptures."""
+    kw = dict(CASES["wca_cells"])
+    a = run(False, steps, 1, **dict(kw))
+    b = run(True, steps, 1, **dict(kw))
+    assert np.array_equal(a[0], b[0])
+    for k in ("pos", "vel", "f"):
+        assert np.array_equal(a[2][k], b[2][k]), k
+    assert b[1]["step"] == 2 * steps and b[1]["flags"] == 0
