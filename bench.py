@@ -149,14 +149,14 @@ def energy_drift(sim, w, steps, every=10):
 
 
 def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled", detail=True,
-            drift_steps=0, keep_state=False):
+            drift_steps=0, keep_state=False, reorder=None):
     import torch
 
     from paper_2003_14061_amd import md
 
     sim = md.Simulation(w.pos, w.vel, w.L, r_cut=w.r_cut, skin=w.skin, dt=w.dt,
                         shifted=w.shifted, precision=precision, neighbor_list=w.use_nl,
-                        newton3=newton3, pipeline=pipeline)
+                        newton3=newton3, pipeline=pipeline, reorder=reorder)
     sim.prepare()
     sim.step(warmup)  # more than 32 steps: md_step captures its graph here
     o0 = sim.reduce()
@@ -169,24 +169,34 @@ def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled", detail
     t1 = time.perf_counter()
     o1 = sim.reduce()
     e1 = (o1["U"] + o1["K"]) / w.n
-    # the same number of steps with every force launch bracketed by HIP events
-    # on the bound stream (direct launches of the same kernels): the force
-    # kernel's average duration, and the step rate without the graph
-    sim.set_timing(True)
+    # the same number of steps with every kernel launched directly (the step
+    # rate without the graph)
+    sim.set_graph(False)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     sim.step(steps)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
-    f_ms, f_launches = sim.get_timing()
-    sim.set_timing(False)
     direct = w.n * steps / (t3 - t2)
+    # and again with every part of each step bracketed by HIP events on the
+    # bound stream: the force kernel's average duration and the split of a
+    # step's time over its parts (the rows of the paper's Table 2)
+    sim.set_timing(True)
+    sim.step(steps)
+    f_ms, f_launches = sim.get_timing()
+    parts = sim.get_timing_parts()
+    sim.set_timing(False)
+    sim.set_graph(True)
+    tot = sum(ms for ms, _ in parts.values())
+    split = {k: {"us_per_step": round(1e3 * ms / steps, 2),
+                 "pct": round(100.0 * ms / tot, 1) if tot > 0 else None}
+             for k, (ms, _) in parts.items()}
     if not detail:
         wall = t1 - t0
         res = {"value": w.n * steps / wall, "ms_per_step": 1e3 * wall / steps,
                "value_direct_launches": direct,
                "force_ms_avg": f_ms / max(f_launches, 1), "energy_drift_per_atom": e1 - e0,
-               "rebuilds": int(o1["n_rebuilds"] - o0["n_rebuilds"])}
+               "rebuilds": int(o1["n_rebuilds"] - o0["n_rebuilds"]), "parts": split}
         res["energy_drift"] = energy_drift(sim, w, drift_steps)
         del sim
         torch.cuda.synchronize()
@@ -205,6 +215,7 @@ def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled", detail
         "rebuilds": int(o1["n_rebuilds"] - o0["n_rebuilds"]),
         "energy_drift_per_atom": e1 - e0,
         "T_end": o1["T"],
+        "parts": split,
     }
     bpa = force_bytes_per_atom(mean_nl, precision)
     t_force = res["force_ms_avg"] * 1e-3
@@ -616,7 +627,7 @@ def main():
               flush=True)
     lay = None
     if not args.no_layers:
-        lay = run_gpu(w, "fp64", args.steps, args.warmup, pipeline="layers")
+        lay = run_gpu(w, "fp64", args.steps, args.warmup, pipeline="layers", reorder=100)
         print(f"[bench] fp64 layer-matrix pipeline done: {lay['value']:.3e} atom-steps/s",
               file=sys.stderr, flush=True)
     n3 = None
@@ -664,6 +675,7 @@ def main():
         "force_ms_avg": round(fp64["force_ms_avg"], 5),
         "value_direct_launches": (round(fp64["value_direct_launches"], 1)
                                   if "value_direct_launches" in fp64 else None),
+        "parts": fp64.get("parts"),
     }
     if mixed is not None:
         ferr = (error_fp32(w, fp64["final_pos"], fp64["final_vel"])
@@ -682,8 +694,12 @@ def main():
             "force_ms_avg": round(lay["force_ms_avg"], 5), "rebuilds": lay["rebuilds"],
             "energy_drift_per_atom": lay["energy_drift_per_atom"],
             "tiled_speedup": round(fp64["value"] / lay["value"], 3),
+            "steps": args.steps, "reorder_every": 100,
+            "parts": lay["parts"], "tiled_parts": fp64.get("parts"),
             "kernels": "k_layer_clear, k_layer_assign, k_layer_nl, k_layer_forces: one thread "
-                       "per atom, 32-bit neighbor matrix, partners gathered from HBM"}
+                       "per atom, 32-bit neighbor matrix, partners gathered from HBM; every "
+                       "100 steps k_scan, k_layer_pack, k_layer_permute, k_layer_copyback "
+                       "and a forced rebuild of both matrices"}
     if n3 is not None:
         out["newton3_fp64"] = {"value": round(n3["value"], 1),
                                "ms_per_step": round(n3["ms_per_step"], 5),

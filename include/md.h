@@ -99,7 +99,11 @@ typedef struct {
     int32_t nl_capacity; /* list entries reserved per atom; 0 picks a bound from the
                             density */
     int32_t reorder;     /* 1: permute the atom slots into cell order at every rebuild
-                            (section 4.1, factor (1)); 0: never permute */
+                            (section 4.1, factor (1)); 0: never permute.  MD_PIPE_LAYERS:
+                            k > 0 permutes them into the layer matrix's cell order every
+                            k-th step of md_step, counted from md_bind (section 2.4 item
+                            (4); the paper's runs use k = 100, section 3), then rebuilds
+                            both matrices; md_step launches directly then (no graph) */
     int32_t block;       /* threads per workgroup for per-atom kernels, a multiple of 64
                             in [64, 1024]; 0 = 256 */
     int32_t pipeline;    /* MD_PIPE_TILED (default): LDS-staged tiles, 16-bit list entries;
@@ -372,9 +376,24 @@ md_status md_autotune(md_ctx* ctx, const md_tuning* candidates, int32_t n, int32
 /* md_set_timing: when enable != 0, bracket every force-pass launch with HIP
  * events on the bound stream; md_get_timing returns the summed elapsed time
  * (ms) and the number of timed launches since timing was enabled, and
- * synchronizes the stream. */
+ * synchronizes the stream.  While timing is on, md_step also brackets every
+ * other part of each step and launches each kernel directly;
+ * md_get_timing_parts returns, per part (MD_PART_*, the rows of the paper's
+ * breakdown of a step's time, section 3.2 Table 2), the summed time (ms)
+ * in ms[MD_PART_COUNT] and the number of timed launch groups in
+ * launches[MD_PART_COUNT].  The energy and virial are summed inside the
+ * force pass and the kinetic sums inside the integration pass; MD_PART_ENERGY
+ * is the per-system pass that completes these reductions (with the step
+ * record and the rebuild decision).  MD_PART_CELLS is the cell build (the
+ * counting sort with its reorder, or the layer matrix), MD_PART_NEIGHBORS
+ * the list or neighbor-matrix build, MD_PART_REORDER the layer pipeline's
+ * periodic reorder.  The rebuild-gated parts are timed on every step, idle
+ * or not.  Synchronizes the stream. */
+enum { MD_PART_NEIGHBORS = 0, MD_PART_FORCES = 1, MD_PART_INTEGRATE = 2, MD_PART_ENERGY = 3,
+       MD_PART_CELLS = 4, MD_PART_REORDER = 5, MD_PART_COUNT = 6 };
 md_status md_set_timing(md_ctx* ctx, int32_t enable);
 md_status md_get_timing(md_ctx* ctx, double* total_ms, int64_t* launches);
+md_status md_get_timing_parts(md_ctx* ctx, double* ms, int64_t* launches);
 
 /* ---- Reverse mode: gradients of trajectory observables ----
  *

@@ -180,10 +180,10 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
         (p.newton3 != 0 && p.newton3 != 1) || (p.newton3 && p.mode != MD_NEIGHBOR_LIST) ||
         (p.pipeline != MD_PIPE_TILED && p.pipeline != MD_PIPE_LAYERS &&
          p.pipeline != MD_PIPE_ALLPAIRS) ||
-        (p.pipeline == MD_PIPE_LAYERS &&
-         (p.mode != MD_NEIGHBOR_LIST || p.newton3 != 0 || p.reorder != 0)) ||
+        (p.pipeline == MD_PIPE_LAYERS && (p.mode != MD_NEIGHBOR_LIST || p.newton3 != 0)) ||
         (p.pipeline == MD_PIPE_ALLPAIRS && (p.mode != MD_CELLS_ONLY || p.reorder != 0)) ||
-        p.nl_capacity < 0 || (p.reorder != 0 && p.reorder != 1) || p.block % 64 != 0 ||
+        p.nl_capacity < 0 || p.reorder < 0 ||
+        (p.pipeline != MD_PIPE_LAYERS && p.reorder > 1) || p.block % 64 != 0 ||
         p.block < 64 || p.block > 1024)
         return MD_ERR_ARG;
 
@@ -467,6 +467,7 @@ static md_status bind_to(md_ctx* c, const md_buffers* bf, char* ws, void* stream
     c->lds_limit = (size_t)lds;
     plan_tiles(c);
     c->bound = true;
+    c->host_steps = 0;
     c->cells_ok = c->nl_ok = c->forces_ok = false;
     launch_clear(k, c->stream);
     return launched();
@@ -582,10 +583,13 @@ extern "C" md_status md_build_neighbors(md_ctx* c)
     return launched();
 }
 
-static void timed_forces(md_ctx* c)
+// Launches fn on the bound stream; with timing on, between two events
+// counted toward part (MD_PART_*).
+template <class Fn>
+static void timed(md_ctx* c, int part, Fn&& fn)
 {
     if (!c->timing) {
-        forces_any(c->kp, c->stream);
+        fn();
         return;
     }
     hipEvent_t ev[2];
@@ -598,10 +602,16 @@ static void timed_forces(md_ctx* c)
         }
     }
     (void)hipEventRecord(ev[0], c->stream);
-    forces_any(c->kp, c->stream);
+    fn();
     (void)hipEventRecord(ev[1], c->stream);
     c->ev_pending.push_back(ev[0]);
     c->ev_pending.push_back(ev[1]);
+    c->ev_part.push_back(part);
+}
+
+static void timed_forces(md_ctx* c)
+{
+    timed(c, MD_PART_FORCES, [&] { forces_any(c->kp, c->stream); });
 }
 
 static md_status fold_timing(md_ctx* c)
@@ -612,12 +622,18 @@ static md_status fold_timing(md_ctx* c)
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, c->ev_pending[k], c->ev_pending[k + 1]) != hipSuccess)
             return MD_ERR_HIP;
-        c->timed_ms += ms;
-        c->timed_launches += 1;
+        const int part = c->ev_part[k / 2];
+        if (part == MD_PART_FORCES) {
+            c->timed_ms += ms;
+            c->timed_launches += 1;
+        }
+        c->part_ms[part] += ms;
+        c->part_launches[part] += 1;
         c->ev_free.push_back(c->ev_pending[k]);
         c->ev_free.push_back(c->ev_pending[k + 1]);
     }
     c->ev_pending.clear();
+    c->ev_part.clear();
     return MD_OK;
 }
 
@@ -675,24 +691,41 @@ static void drop_graph(md_ctx* c)
     c->g_run = nullptr;
 }
 
-// Launches of n steps; first: the first of them is the first step of the run.
+// The layer pipeline's periodic reorder (md_params.reorder = k > 0): due
+// before the force pass of every k-th step.
+static bool layer_reorder_on(const md_ctx* c)
+{
+    return c->kp.pipeline == MD_PIPE_LAYERS && c->kp.reorder > 0;
+}
+
+// Launches of n steps, the first of them step step0 + 1 since md_bind;
+// first: it is the first step of the run.
 static md_status step_launches(md_ctx* c, hipStream_t s, bool first, int32_t n,
-                               int32_t record_every)
+                               int32_t record_every, int64_t step0)
 {
     const KParams& k = c->kp;
     const bool nl = c->prm.mode == MD_NEIGHBOR_LIST;
-    for (int32_t i = 0; i < n; ++i) {
-        launch_integrate(k, first && i == 0 ? 0 : 1, record_every, s);
-        cells_any(k, 0, s);
-        if (nl) neighbors_any(k, 0, s);
-        if (s == c->stream) {
-            timed_forces(c);
-            if (c->timing && c->ev_pending.size() >= 8192) {
-                md_status st = fold_timing(c);
-                if (st != MD_OK) return st;
-            }
-        } else {
+    if (s != c->stream) {  // captured into a graph: never timed, never reordered
+        for (int32_t i = 0; i < n; ++i) {
+            launch_integrate(k, first && i == 0 ? 0 : 1, record_every, s);
+            cells_any(k, 0, s);
+            if (nl) neighbors_any(k, 0, s);
             forces_any(k, s);
+        }
+        return MD_OK;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        const int phase = first && i == 0 ? 0 : 1;
+        timed(c, MD_PART_INTEGRATE, [&] { launch_integrate_pass(k, phase, record_every, s); });
+        timed(c, MD_PART_ENERGY, [&] { launch_integrate_finish(k, phase, record_every, s); });
+        const bool reorder = layer_reorder_on(c) && (step0 + i + 1) % k.reorder == 0;
+        if (reorder) timed(c, MD_PART_REORDER, [&] { launch_layer_reorder(k, s); });
+        timed(c, MD_PART_CELLS, [&] { cells_any(k, reorder ? 1 : 0, s); });
+        if (nl) timed(c, MD_PART_NEIGHBORS, [&] { neighbors_any(k, reorder ? 1 : 0, s); });
+        timed_forces(c);
+        if (c->timing && c->ev_pending.size() >= 8192) {
+            md_status st = fold_timing(c);
+            if (st != MD_OK) return st;
         }
     }
     return MD_OK;
@@ -719,7 +752,7 @@ static md_status step_graphs(md_ctx* c, int32_t len, int32_t n_graphs, int32_t r
         drop_graph(c);
         if (hipStreamBeginCapture(run, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return MD_ERR_HIP;
-        const md_status st = step_launches(c, run, false, len, record_every);
+        const md_status st = step_launches(c, run, false, len, record_every, 0);
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(run, &g);
         if (st != MD_OK) return st;
@@ -751,16 +784,19 @@ extern "C" md_status md_step(md_ctx* c, int32_t n_steps, int32_t record_every)
     if (!c->forces_ok) return MD_ERR_STATE;
     if (n_steps == 0) return MD_OK;
     md_status st;
-    if (c->timing || !c->graph_on || n_steps <= kGraphMin) {
-        st = step_launches(c, c->stream, true, n_steps, record_every);
+    const int64_t step0 = c->host_steps;
+    if (c->timing || !c->graph_on || layer_reorder_on(c) || n_steps <= kGraphMin) {
+        st = step_launches(c, c->stream, true, n_steps, record_every, step0);
     } else {
         const int32_t rest = n_steps - 1;
         const int32_t len = rest < kGraphSteps ? rest : kGraphSteps, n_graphs = rest / len;
-        st = step_launches(c, c->stream, true, 1, record_every);
+        st = step_launches(c, c->stream, true, 1, record_every, step0);
         if (st == MD_OK) st = step_graphs(c, len, n_graphs, record_every);
         if (st == MD_OK)
-            st = step_launches(c, c->stream, false, rest - n_graphs * len, record_every);
+            st = step_launches(c, c->stream, false, rest - n_graphs * len, record_every,
+                               step0 + 1 + (int64_t)n_graphs * len);
     }
+    c->host_steps = step0 + n_steps;
     if (st != MD_OK) return st;
     launch_integrate(c->kp, 2, record_every, c->stream);
     return launched();
@@ -1153,6 +1189,21 @@ extern "C" md_status md_set_timing(md_ctx* c, int32_t enable)
     c->timing = enable != 0;
     c->timed_ms = 0.0;
     c->timed_launches = 0;
+    for (int k = 0; k < MD_PART_COUNT; ++k) {
+        c->part_ms[k] = 0.0;
+        c->part_launches[k] = 0;
+    }
+    return st;
+}
+
+extern "C" md_status md_get_timing_parts(md_ctx* c, double* ms, int64_t* launches)
+{
+    if (!c || !ms || !launches) return MD_ERR_ARG;
+    md_status st = fold_timing(c);
+    for (int k = 0; k < MD_PART_COUNT; ++k) {
+        ms[k] = c->part_ms[k];
+        launches[k] = c->part_launches[k];
+    }
     return st;
 }
 

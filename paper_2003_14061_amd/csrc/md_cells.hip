@@ -296,6 +296,13 @@ void launch_cells(const KParams& p, int force, hipStream_t s)
     cells_seq(Single{p}, shape_of(p), force, s);
 }
 
+// The cell offsets from the occupancy counts alone (forced), for the layer
+// pipeline's reorder.
+void launch_cell_scan(const KParams& p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan<Single>, dim3(1), dim3(kScanThreads), 0, s, Single{p}, 1);
+}
+
 void launch_clear(const Batch& b, const LaunchShape& sh, hipStream_t s) { clear_seq(b, sh, s); }
 
 void launch_cells(const Batch& b, const LaunchShape& sh, int force, hipStream_t s)

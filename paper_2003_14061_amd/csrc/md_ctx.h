@@ -45,8 +45,13 @@ struct md_ctx {
     int nl_method_req = 0;  // requested list-build method (MD_NL_AUTO: by density)
     bool timing = false;
     std::vector<hipEvent_t> ev_free, ev_pending;  // pending holds start/stop pairs
-    double timed_ms = 0.0;
+    double timed_ms = 0.0;                 // force passes (md_get_timing)
     int64_t timed_launches = 0;
+    std::vector<int> ev_part;              // MD_PART_* of each pending pair
+    double part_ms[MD_PART_COUNT] = {};    // md_get_timing_parts
+    int64_t part_launches[MD_PART_COUNT] = {};
+    int64_t host_steps = 0;                // md_step steps since md_bind (the layer reorder
+                                           // schedule)
     size_t lds_limit = 160 * 1024;  // per-workgroup LDS; refreshed from the device at bind
     int tile_cells = 0, tile_y = 0, tile_z = 0;  // requested block size (0: automatic)
     int tile_cells_res = 0, tile_y_res = 0, tile_z_res = 0;  // largest block in use

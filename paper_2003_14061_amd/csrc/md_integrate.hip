@@ -246,21 +246,45 @@ __global__ __launch_bounds__(kIntThreads) void k_observe(KParams p)
 }
 
 template <class B>
-static void integrate_seq(const B& b, const LaunchShape& sh, int phase, int record_every,
-                          hipStream_t s)
+static void integrate_pass(const B& b, const LaunchShape& sh, int phase, int record_every,
+                           hipStream_t s)
 {
     const dim3 g(sh.grid[G_INTEGRATE]), t(kIntThreads);
     if (sh.precision == MD_FP64)
         hipLaunchKernelGGL((k_integrate<double, B>), g, t, 0, s, b, phase, record_every);
     else
         hipLaunchKernelGGL((k_integrate<float, B>), g, t, 0, s, b, phase, record_every);
+}
+
+template <class B>
+static void integrate_finish(const B& b, const LaunchShape& sh, int phase, int record_every,
+                             hipStream_t s)
+{
     hipLaunchKernelGGL(k_int_finish<B>, dim3(sh.grid[G_ONE]), dim3(kFinishThreads), 0, s, b,
                        phase, record_every);
+}
+
+template <class B>
+static void integrate_seq(const B& b, const LaunchShape& sh, int phase, int record_every,
+                          hipStream_t s)
+{
+    integrate_pass(b, sh, phase, record_every, s);
+    integrate_finish(b, sh, phase, record_every, s);
 }
 
 void launch_integrate(const KParams& p, int phase, int record_every, hipStream_t s)
 {
     integrate_seq(Single{p}, shape_of(p), phase, record_every, s);
+}
+
+void launch_integrate_pass(const KParams& p, int phase, int record_every, hipStream_t s)
+{
+    integrate_pass(Single{p}, shape_of(p), phase, record_every, s);
+}
+
+void launch_integrate_finish(const KParams& p, int phase, int record_every, hipStream_t s)
+{
+    integrate_finish(Single{p}, shape_of(p), phase, record_every, s);
 }
 
 void launch_integrate(const Batch& b, const LaunchShape& sh, int phase, int record_every,

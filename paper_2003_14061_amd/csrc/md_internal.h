@@ -261,6 +261,8 @@ void launch_layer_cells(const KParams& p, int force, hipStream_t s);
 void launch_layer_nl(const KParams& p, int force, hipStream_t s);
 void launch_layer_forces(const KParams& p, hipStream_t s);
 void launch_layer_export(const KParams& p, int32_t* out, hipStream_t s);
+void launch_layer_reorder(const KParams& p, hipStream_t s);
+void launch_cell_scan(const KParams& p, hipStream_t s);
 int allpairs_home_blocks(int n);
 void allpairs_split(int n, int* split, int* chunk);
 void launch_allpairs_forces(const KParams& p, hipStream_t s);
@@ -286,6 +288,10 @@ size_t force_lds_bytes(const KParams& p);
 int force_blocks(const KParams& p);  // workgroups of the force pass for the current tuning
 // phase 0: kick + drift; 1: kick, record, kick + drift; 2: kick, record
 void launch_integrate(const KParams& p, int phase, int record_every, hipStream_t s);
+// The two halves of launch_integrate: the per-atom pass, then the per-system
+// finish (reductions, step count and record, rebuild decision).
+void launch_integrate_pass(const KParams& p, int phase, int record_every, hipStream_t s);
+void launch_integrate_finish(const KParams& p, int phase, int record_every, hipStream_t s);
 void launch_observe(const KParams& p, hipStream_t s);
 
 }  // namespace md

@@ -16,9 +16,18 @@
 //
 // The energy and virial of F1 go to per-workgroup partials, reduced like
 // those of the tiled pass.  Separations take the minimum image d - L
-// rint(d/L) in every coordinate (no wrap bits).  Requires reorder = 0: the
-// paper reorders on the host every hundred steps (section 2.4 (4)), which
-// this pipeline leaves out.
+// rint(d/L) in every coordinate (no wrap bits).
+//
+// Reorder (section 2.4, item (4); every 100 steps in the paper's runs,
+// section 3): with md_params.reorder = k > 0, every k-th step packs the
+// layer matrix of the last build into the atom sequence s (cells in order,
+// each cell's layers in order) and permutes the atoms' coordinates,
+// velocities and permanent ids to it through scratch arrays, after which the
+// layer and neighbor matrices are rebuilt.  The paper builds s on the host
+// and names the GPU alternative, a prefix scan of the cell occupancies that
+// tells each cell where its atoms go; that is what is done here (k_scan of
+// the tiled cell build, then one thread per cell).  The forces are not
+// permuted: the force pass that follows rewrites all of them.
 #include "md_pair.h"
 
 namespace md {
@@ -137,6 +146,57 @@ __global__ void k_layer_forces(KParams p)
     }
 }
 
+// ---- reorder ----
+// Every kernel leaves the state alone when a layer overflow is latched (the
+// layer matrix then lacks atoms, so s would not be a permutation).
+
+__device__ __forceinline__ bool layers_whole(const KParams& p)
+{
+    return (p.dev->flags & MD_FLAG_LAYER_OVERFLOW) == 0;
+}
+
+// s: the atoms of cell c at cell_start[c] .. in layer order.
+__global__ void k_layer_pack(KParams p)
+{
+    if (!layers_whole(p)) return;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < p.ncell;
+         c += gridDim.x * blockDim.x) {
+        const int a = p.cell_start[c], cnt = p.cell_start[c + 1] - a;
+        const int* col = p.layers + (int64_t)c * p.n_layers;
+        for (int l = 0; l < cnt && l < p.n_layers; ++l) p.tmp[a + l] = col[l];
+    }
+}
+
+// New slot d takes atom s[d]: coordinates, velocities and id into scratch.
+__global__ void k_layer_permute(KParams p)
+{
+    if (!layers_whole(p)) return;
+    for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < p.n; d += gridDim.x * blockDim.x) {
+        const int a = p.tmp[d];
+        p.sx[d] = p.x[a];
+        p.sy[d] = p.y[a];
+        p.sz[d] = p.z[a];
+        p.svx[d] = p.vx[a];
+        p.svy[d] = p.vy[a];
+        p.svz[d] = p.vz[a];
+        p.sid[d] = p.id[a];
+    }
+}
+
+__global__ void k_layer_copyback(KParams p)
+{
+    if (!layers_whole(p)) return;
+    for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < p.n; d += gridDim.x * blockDim.x) {
+        p.x[d] = p.sx[d];
+        p.y[d] = p.sy[d];
+        p.z[d] = p.sz[d];
+        p.vx[d] = p.svx[d];
+        p.vy[d] = p.svy[d];
+        p.vz[d] = p.svz[d];
+        p.id[d] = p.sid[d];
+    }
+}
+
 // W with -1 past each atom's length (the layout of md_export_neighbors).
 __global__ void k_layer_export(KParams p, int32_t* out)
 {
@@ -173,6 +233,16 @@ void launch_layer_forces(const KParams& p, hipStream_t s)
         hipLaunchKernelGGL((k_layer_forces<double, AccD>), g, dim3(p.block), 0, s, p);
     else
         hipLaunchKernelGGL((k_layer_forces<float, AccF>), g, dim3(p.block), 0, s, p);
+}
+
+void launch_layer_reorder(const KParams& p, hipStream_t s)
+{
+    launch_cell_scan(p, s);
+    int gc = (p.ncell + p.block - 1) / p.block;
+    gc = gc < p.gate_grid ? gc : p.gate_grid;
+    hipLaunchKernelGGL(k_layer_pack, dim3(gc), dim3(p.block), 0, s, p);
+    hipLaunchKernelGGL(k_layer_permute, atom_grid(p), dim3(p.block), 0, s, p);
+    hipLaunchKernelGGL(k_layer_copyback, atom_grid(p), dim3(p.block), 0, s, p);
 }
 
 void launch_layer_export(const KParams& p, int32_t* out, hipStream_t s)

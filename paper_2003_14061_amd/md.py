@@ -32,6 +32,7 @@ EXPORTS = ("md_init", "md_workspace_bytes", "md_geometry", "md_layout", "md_bind
            "md_bind_static", "md_set_graph",
            "md_build_cells", "md_build_neighbors", "md_forces", "md_step", "md_reduce",
            "md_history", "md_set_tuning", "md_get_tuning", "md_set_timing", "md_get_timing",
+           "md_get_timing_parts",
            "md_export_neighbors", "md_traj_workspace_bytes", "md_traj_forward",
            "md_traj_backward", "md_batch_init", "md_batch_workspace_bytes", "md_batch_replica",
            "md_batch_bind", "md_batch_prepare", "md_batch_forces", "md_batch_layout",
@@ -132,6 +133,7 @@ def lib():
         "md_get_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
         "md_set_timing": (C.c_int, [P, C.c_int32]),
         "md_get_timing": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "md_get_timing_parts": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "md_traj_workspace_bytes": (C.c_size_t, [P, C.POINTER(TrajParams)]),
         "md_traj_forward": (C.c_int, [P, C.POINTER(TrajParams), P, P]),
         "md_traj_backward": (C.c_int, [P, C.POINTER(TrajParams), P, P, P, P, P]),
@@ -300,6 +302,19 @@ def md_get_timing(ctx):
     return ms.value, n.value
 
 
+MD_PART_NEIGHBORS, MD_PART_FORCES, MD_PART_INTEGRATE, MD_PART_ENERGY, MD_PART_CELLS, \
+    MD_PART_REORDER, MD_PART_COUNT = range(7)
+PART_NAMES = ("neighbors", "forces", "integrate", "energy", "cells", "reorder")
+
+
+def md_get_timing_parts(ctx):
+    """{part: (ms, launch groups)} of md_set_timing's per-part events."""
+    ms = (C.c_double * MD_PART_COUNT)()
+    n = (C.c_int64 * MD_PART_COUNT)()
+    _check(lib().md_get_timing_parts(ctx, ms, n), "md_get_timing_parts")
+    return {PART_NAMES[k]: (ms[k], n[k]) for k in range(MD_PART_COUNT)}
+
+
 def md_destroy(ctx):
     lib().md_destroy(ctx)
 
@@ -336,11 +351,17 @@ class Simulation:
             neighbor_list = False  # no cells and no list: every pair is tested
         if reorder is None:
             reorder = bool(neighbor_list) and pipe == MD_PIPE_TILED
+        if pipe == MD_PIPE_LAYERS:
+            # the interval in steps of the layer pipeline's reorder (True: the
+            # paper's 100), 0 for none
+            reorder = 100 if reorder is True else int(reorder or 0)
+        else:
+            reorder = int(bool(reorder))
         self.params = Params(int(n), MD_LJ_SHIFTED if shifted else MD_LJ_TRUNC, float(L),
                              float(eps), float(sigma), float(mass), float(r_cut), float(skin),
                              float(dt), MD_FP64 if precision == "fp64" else MD_FP32_MIXED,
                              MD_NEIGHBOR_LIST if neighbor_list else MD_CELLS_ONLY,
-                             int(bool(newton3)), int(nl_capacity), int(bool(reorder)),
+                             int(bool(newton3)), int(nl_capacity), reorder,
                              int(block), pipe)
         self.n = n
         self.L = float(L)
@@ -501,6 +522,9 @@ class Simulation:
 
     def get_timing(self):
         return md_get_timing(self.ctx)
+
+    def get_timing_parts(self):
+        return md_get_timing_parts(self.ctx)
 
     # -- views of the device state
     def ws_array(self, which, dtype):

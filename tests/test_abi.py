@@ -85,7 +85,7 @@ def test_geometry_of_the_workloads():
     dict(n=0), dict(r_cut=-1.0), dict(dt=0.0), dict(skin=-0.1), dict(block=100),
     dict(block=2048), dict(precision=7), dict(mode=3), dict(reorder=2), dict(cap=-1),
     dict(newton3=2), dict(newton3=-1), dict(newton3=1, mode=md.MD_CELLS_ONLY),
-    dict(pipeline=3), dict(pipeline=-1), dict(pipeline=1, reorder=1),
+    dict(pipeline=3), dict(pipeline=-1), dict(pipeline=1, reorder=-1), dict(reorder=-1),
     dict(pipeline=1, reorder=0, newton3=1), dict(pipeline=1, reorder=0, mode=md.MD_CELLS_ONLY),
     dict(pipeline=2, reorder=0), dict(pipeline=2, reorder=1, mode=md.MD_CELLS_ONLY),
     dict(pipeline=2, reorder=0, mode=md.MD_CELLS_ONLY, newton3=1),

@@ -136,3 +136,83 @@ def test_layer_overflow_is_latched():
         sim.reduce()
     assert e.value.status == -8
     assert sim.reduce(check=False)["flags"] & 4
+
+
+@pytest.mark.parametrize("name", ["wca13500", "lj32000"])
+def test_layers_reorder_every_k_steps(name):
+    """The paper's periodic reorder (section 2.4 item (4)): every 10th step
+    the atoms are permuted into the layer matrix's cell order and both
+    matrices rebuilt.  The trajectory stays the oracle's (the list holds the
+    same pairs; only summation order and the rebuild schedule move), the
+    slots end up in cell order, and the ids follow the atoms."""
+    steps, every = 40, 10
+    n, rho, rc, jit, lat = CASES[name]
+    L, pos, vel = state(n, rho, 23, jitter=min(jit, 0.03), lattice=lat)
+    sim = md.Simulation(pos, vel, L, r_cut=rc, skin=0.3, dt=0.005, pipeline="layers",
+                        reorder=every)
+    s = oracle.make_sys(n, L, r_cut=rc, skin=0.3, dt=0.005, nl_cap=sim.grid.nl_capacity)
+    sim.prepare()
+    assert np.array_equal(sim.ids(), np.arange(n))
+    # the layer matrix of the last build before step 10 gives the sequence
+    sim.step(every - 1, record_every=1)
+    nl_ = sim.grid.n_layers
+    lay, cnt_, ids0 = sim._host(sim.ws_array(md.MD_ARR_LAYERS, torch.int32),
+                                sim.ws_array(md.MD_ARR_LAYER_COUNT, torch.int32), sim.id)
+    lay = lay.reshape(-1, nl_)
+    seq = np.concatenate([lay[c, :cnt_[c]] for c in range(len(cnt_))])
+    assert sorted(seq.tolist()) == list(range(n))
+    sim.step(1, record_every=1)
+    assert np.array_equal(sim.ids(), ids0[seq])
+    sim.step(steps - every, record_every=1)
+    h = sim.history()
+    st = sim.state()
+    p_ref, v_ref, _, o_ref, _ = oracle.run(s, pos, vel, steps)
+    e_scale = np.abs(o_ref["U"]).max() + np.abs(o_ref["K"]).max()
+    assert np.max(np.abs(h["U"] - o_ref["U"])) <= 1e-10 * e_scale
+    assert np.max(np.abs(h["K"] - o_ref["K"])) <= 1e-10 * e_scale
+    assert np.abs(min_image(st["pos"] - p_ref, L)).max() < 1e-10
+    assert np.abs(st["vel"] - v_ref).max() < 1e-9
+    ids = sim.ids()
+    assert sorted(ids.tolist()) == list(range(n)) and not np.array_equal(ids, np.arange(n))
+    # forces of the final state against the oracle's
+    nc = sim.grid.nc
+    p = np.mod(st["pos"], L)
+    cells = oracle.build_cells(s, nc, p)
+    cnt, nl, _ = oracle.build_nl(s, nc, p, cells)
+    per_atom, normwise = force_errors(st["f"], oracle.forces_nl(s, p, cnt, nl))
+    assert per_atom <= 1e-12 and normwise <= 1e-12
+
+
+def test_layers_timing_parts():
+    """md_set_timing brackets every part of a step (the rows of the paper's
+    Table 2): one group per step for each part, one reorder per k steps, and
+    the force part is what md_get_timing reports."""
+    n, rho, rc, jit, lat = CASES["wca13500"]
+    L, pos, vel = state(n, rho, 23, jitter=0.03, lattice=lat)
+    sim = md.Simulation(pos, vel, L, r_cut=rc, skin=0.3, dt=0.005, pipeline="layers",
+                        reorder=10)
+    sim.prepare()
+    sim.set_timing(True)
+    sim.step(30)
+    parts = sim.get_timing_parts()
+    for k in ("neighbors", "forces", "integrate", "energy", "cells"):
+        assert parts[k][1] == 30 and parts[k][0] > 0, k
+    assert parts["reorder"][1] == 3 and parts["reorder"][0] > 0
+    f_ms, f_n = sim.get_timing()
+    assert f_n == 30 and f_ms == pytest.approx(parts["forces"][0])
+    assert sim.reduce()["flags"] == 0
+
+
+def test_layers_reorder_with_overflow_leaves_the_state():
+    """A latched layer overflow stops the reorder (the layer matrix then
+    lacks atoms): the slots keep their atoms."""
+    L, pos, vel = state(2000, 0.1, 3, lattice=False)
+    grid = np.stack(np.meshgrid(*[np.arange(4)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    pos[:64] = 0.5 + 0.6 * grid
+    vel[:] = 0.0
+    sim = md.Simulation(pos, vel, L, r_cut=2.5, skin=0.3, dt=0.001, pipeline="layers",
+                        reorder=2)
+    sim.prepare()
+    sim.step(4)
+    assert np.array_equal(sim.ids(), np.arange(2000))
+    assert sim.reduce(check=False)["flags"] & 4
