@@ -470,8 +470,9 @@ def run_batch(steps=500, warmup=20, tune_cache=None, fixed_tuning=None):
     n_tot = sum(w.n for w in reps)
     b = md.Batch(systems, precision="fp32")
     shapes = [{}, dict(tile_cells=4, tile_y=4, tile_z=4), dict(tile_cells=4, tile_y=2, tile_z=2),
-              dict(tile_cells=8, tile_y=2, tile_z=2)]
-    cands = [dict(force_lanes=l, force_block=fb, **t) for t in shapes for l in (2, 4, 8)
+              dict(tile_cells=8, tile_y=2, tile_z=2), dict(tile_cells=8, tile_y=4, tile_z=4),
+              dict(tile_cells=6, tile_y=6, tile_z=6)]
+    cands = [dict(force_lanes=l, force_block=fb, **t) for t in shapes for l in (1, 2, 4)
              for fb in (256, 512)]
     if fixed_tuning:  # a given shape instead of the autotuner (profiling runs)
         cands, best, costs = [fixed_tuning], 0, [-1.0]

@@ -705,11 +705,15 @@ static md_status step_launches(md_ctx* c, hipStream_t s, bool first, int32_t n,
 {
     const KParams& k = c->kp;
     const bool nl = c->prm.mode == MD_NEIGHBOR_LIST;
+    // the reorder's copy-back folded into the list build (tiled lists)
+    const int fold = nl && k.pipeline == MD_PIPE_TILED && k.reorder && !k.bonded_on
+                         ? kFoldCopy
+                         : 0;
     if (s != c->stream) {  // captured into a graph: never timed, never reordered
         for (int32_t i = 0; i < n; ++i) {
             launch_integrate(k, first && i == 0 ? 0 : 1, record_every, s);
-            cells_any(k, 0, s);
-            if (nl) neighbors_any(k, 0, s);
+            cells_any(k, fold, s);
+            if (nl) neighbors_any(k, fold, s);
             forces_any(k, s);
         }
         return MD_OK;
@@ -720,8 +724,8 @@ static md_status step_launches(md_ctx* c, hipStream_t s, bool first, int32_t n,
         timed(c, MD_PART_ENERGY, [&] { launch_integrate_finish(k, phase, record_every, s); });
         const bool reorder = layer_reorder_on(c) && (step0 + i + 1) % k.reorder == 0;
         if (reorder) timed(c, MD_PART_REORDER, [&] { launch_layer_reorder(k, s); });
-        timed(c, MD_PART_CELLS, [&] { cells_any(k, reorder ? 1 : 0, s); });
-        if (nl) timed(c, MD_PART_NEIGHBORS, [&] { neighbors_any(k, reorder ? 1 : 0, s); });
+        timed(c, MD_PART_CELLS, [&] { cells_any(k, reorder ? 1 : fold, s); });
+        if (nl) timed(c, MD_PART_NEIGHBORS, [&] { neighbors_any(k, reorder ? 1 : fold, s); });
         timed_forces(c);
         if (c->timing && c->ev_pending.size() >= 8192) {
             md_status st = fold_timing(c);

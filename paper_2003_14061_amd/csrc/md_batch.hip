@@ -162,8 +162,10 @@ void step_sequence(md_batch* b, int32_t n_steps, int32_t record_every)
     const bool nl = b->sh.mode == MD_NEIGHBOR_LIST;
     for (int32_t s = 0; s < n_steps; ++s) {
         launch_integrate(b->dev, b->sh, s == 0 ? 0 : 1, record_every, b->stream);
-        launch_cells(b->dev, b->sh, 0, b->stream);
-        if (nl) launch_neighbors(b->dev, b->sh, 0, b->stream);
+        // the reorder's copy-back folded into the list build
+        const int fold = nl && b->sh.reorder ? kFoldCopy : 0;
+        launch_cells(b->dev, b->sh, fold, b->stream);
+        if (nl) launch_neighbors(b->dev, b->sh, fold, b->stream);
         launch_forces(b->dev, b->sh, b->stream);
     }
     launch_integrate(b->dev, b->sh, 2, record_every, b->stream);

@@ -272,8 +272,10 @@ static void clear_seq(const B& b, const LaunchShape& sh, hipStream_t s)
 }
 
 template <class B>
-static void cells_seq(const B& b, const LaunchShape& sh, int force, hipStream_t s)
+static void cells_seq(const B& b, const LaunchShape& sh, int flags, hipStream_t s)
 {
+    const int force = flags & 1;
+    const bool copy = !(flags & kFoldCopy);  // else the list build copies back
     const dim3 atoms(sh.grid[G_ATOMS]), blk(sh.block);
     hipLaunchKernelGGL(k_bin<B>, atoms, blk, 0, s, b, force);
     hipLaunchKernelGGL(k_scan<B>, dim3(sh.grid[G_ONE]), dim3(kScanThreads), 0, s, b, force);
@@ -282,10 +284,10 @@ static void cells_seq(const B& b, const LaunchShape& sh, int force, hipStream_t 
         hipLaunchKernelGGL((k_cellsort<double, B, false>), atoms, blk, 0, s, b, force);
     } else if (sh.precision == MD_FP64) {
         hipLaunchKernelGGL((k_cellsort<double, B, true>), atoms, blk, 0, s, b, force);
-        hipLaunchKernelGGL((k_copyback<double, B>), atoms, blk, 0, s, b, force);
+        if (copy) hipLaunchKernelGGL((k_copyback<double, B>), atoms, blk, 0, s, b, force);
     } else {
         hipLaunchKernelGGL((k_cellsort<float, B, true>), atoms, blk, 0, s, b, force);
-        hipLaunchKernelGGL((k_copyback<float, B>), atoms, blk, 0, s, b, force);
+        if (copy) hipLaunchKernelGGL((k_copyback<float, B>), atoms, blk, 0, s, b, force);
     }
 }
 

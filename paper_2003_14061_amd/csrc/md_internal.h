@@ -272,6 +272,12 @@ void launch_bond_map(const KParams& p, int force, hipStream_t s);
 void launch_bonded(const KParams& p, hipStream_t s);
 
 void launch_clear(const KParams& p, hipStream_t s);
+// launch_cells / launch_neighbors flags: bit 0 forces the build (else it is
+// gated by the rebuild flag); kFoldCopy (tiled pipeline with reorder, list
+// mode) leaves the cell-sorted data in the scratch arrays, and the list
+// build copies each tile's home atoms into the state arrays (saving the
+// separate copy-back pass and its launch).
+constexpr int kFoldCopy = 2;
 void launch_cells(const KParams& p, int force, hipStream_t s);
 void launch_neighbors(const KParams& p, int force, hipStream_t s);
 void launch_nl_export(const KParams& p, int32_t* out, hipStream_t s);

@@ -43,6 +43,56 @@ __device__ __forceinline__ double readlane_f64(double v, int lane)
 // LDS bytes of the list build: the staged tile.
 size_t nl_lds_bytes(const KParams& p) { return stage_bytes(p, p.scap); }
 
+// The copy-back of the reorder folded into the list build (kFoldCopy): the
+// cell build left the atoms' data in cell order in the scratch arrays, so
+// the list is built over the view of p with state and scratch arrays
+// exchanged (positions read from the sorted copy), and every home atom's
+// data is copied from there into the state arrays (each atom is the home
+// atom of exactly one tile; no tile reads another's home data from the
+// state arrays during the build).
+__device__ __forceinline__ KParams scratch_view(const KParams& p)
+{
+    KParams q = p;
+    q.x = p.sx; q.sx = p.x;
+    q.y = p.sy; q.sy = p.y;
+    q.z = p.sz; q.sz = p.z;
+    q.vx = p.svx; q.svx = p.vx;
+    q.vy = p.svy; q.svy = p.vy;
+    q.vz = p.svz; q.svz = p.vz;
+    // the force scratch arrays are typed double but hold the force type
+    q.fx = p.sfx; q.sfx = static_cast<double*>(p.fx);
+    q.fy = p.sfy; q.sfy = static_cast<double*>(p.fy);
+    q.fz = p.sfz; q.sfz = static_cast<double*>(p.fz);
+    q.id = p.sid; q.sid = p.id;
+    q.cell_of = p.scell; q.scell = p.cell_of;
+    return q;
+}
+
+// Home atom at slot k, over scratch_view: its sorted data into the state.
+template <bool kCopy>
+__device__ __forceinline__ void copy_home(const KParams& q, int k)
+{
+    if (!kCopy) return;
+    q.sx[k] = q.x[k];
+    q.sy[k] = q.y[k];
+    q.sz[k] = q.z[k];
+    q.svx[k] = q.vx[k];
+    q.svy[k] = q.vy[k];
+    q.svz[k] = q.vz[k];
+    if (q.precision == MD_FP64) {
+        q.sfx[k] = static_cast<const double*>(q.fx)[k];
+        q.sfy[k] = static_cast<const double*>(q.fy)[k];
+        q.sfz[k] = static_cast<const double*>(q.fz)[k];
+    } else {
+        reinterpret_cast<float*>(q.sfx)[k] = static_cast<const float*>(q.fx)[k];
+        reinterpret_cast<float*>(q.sfy)[k] = static_cast<const float*>(q.fy)[k];
+        reinterpret_cast<float*>(q.sfz)[k] = static_cast<const float*>(q.fz)[k];
+    }
+    q.sid[k] = q.id[k];
+    q.scell[k] = q.cell_of[k];
+    q.order[k] = k;
+}
+
 // One home cell hc of the tile, by one wave.  The candidates (the 9 windows
 // of three cells next to it, concatenated, in canonical order)
 // are taken kNlRounds x 64 at a time: lane l holds candidate k0 + 64 r + l
@@ -68,7 +118,7 @@ __device__ __forceinline__ int home_cell(const Stage& s, int hc)
     return home_row_cell(s, r) + (a - 1);
 }
 
-template <int kImage, bool kHalf, bool kFits, bool kSmall>
+template <int kImage, bool kHalf, bool kFits, bool kSmall, bool kCopy>
 __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, int hc)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -192,6 +242,7 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
             p.xr[slot_l] = hx;
             p.yr[slot_l] = hy;
             p.zr[slot_l] = hz;
+            copy_home<kCopy>(p, slot_l);
         }
         const int mmax = wave_max(home_lane ? mreg : 0);
         if (lane == 0 && mmax > 0) {
@@ -217,7 +268,7 @@ __device__ __forceinline__ int home_column_cell(const Stage& s, int t1, int e)
 
 // The list of home atom h, by one lane.  Returns the number of entries found
 // (beyond the capacity: overflow).
-template <int kImage, bool kFits, bool kHalf>
+template <int kImage, bool kFits, bool kHalf, bool kCopy>
 __device__ __forceinline__ int nl_home_atom(const KParams& p, const Stage& s, int h)
 {
     int e_self, pos_i, t1;
@@ -282,16 +333,17 @@ __device__ __forceinline__ int nl_home_atom(const KParams& p, const Stage& s, in
     p.xr[slot_i] = xi;
     p.yr[slot_i] = yi;
     p.zr[slot_i] = zi;
+    copy_home<kCopy>(p, slot_i);
     return (int)m;
 }
 
-template <int kImage, bool kFits, bool kHalf>
+template <int kImage, bool kFits, bool kHalf, bool kCopy>
 __device__ __forceinline__ void nl_lanes(const KParams& p, const Stage& s)
 {
     const int nh = home_count(s);
     int mmax = 0;
     for (int h = threadIdx.x; h < nh; h += blockDim.x) {
-        const int m = nl_home_atom<kImage, kFits, kHalf>(p, s, h);
+        const int m = nl_home_atom<kImage, kFits, kHalf, kCopy>(p, s, h);
         mmax = m > mmax ? m : mmax;
     }
     mmax = wave_max(mmax);
@@ -302,7 +354,7 @@ __device__ __forceinline__ void nl_lanes(const KParams& p, const Stage& s)
 }
 
 // One tile's lists (every thread of the workgroup calls it).
-template <int kMethod, bool kHalf>
+template <int kMethod, bool kHalf, bool kCopy>
 __device__ __forceinline__ void nl_tile(const KParams& p, int t, char* smem)
 {
     const Tile g = tile_of(p, t);
@@ -316,6 +368,7 @@ __device__ __forceinline__ void nl_tile(const KParams& p, int t, char* smem)
             int e, pos;
             home_atom(s, h, e, pos);
             p.nl_count[atom_at(p, pos)] = 0;
+            copy_home<kCopy>(p, atom_at(p, pos));
         }
         if (threadIdx.x == 0) atomicOr(&p.dev->flags, (int)MD_FLAG_NL_OVERFLOW);
         return;
@@ -326,15 +379,15 @@ __device__ __forceinline__ void nl_tile(const KParams& p, int t, char* smem)
     if (kMethod == MD_NL_LANES) {
         if (!s.fits) {
             if (mode == 2)
-                nl_lanes<2, false, kHalf>(p, s);
+                nl_lanes<2, false, kHalf, kCopy>(p, s);
             else
-                nl_lanes<1, false, kHalf>(p, s);
+                nl_lanes<1, false, kHalf, kCopy>(p, s);
         } else if (mode == 0) {
-            nl_lanes<0, true, kHalf>(p, s);
+            nl_lanes<0, true, kHalf, kCopy>(p, s);
         } else if (mode == 1) {
-            nl_lanes<1, true, kHalf>(p, s);
+            nl_lanes<1, true, kHalf, kCopy>(p, s);
         } else {
-            nl_lanes<2, true, kHalf>(p, s);
+            nl_lanes<2, true, kHalf, kCopy>(p, s);
         }
         return;
     }
@@ -345,21 +398,21 @@ __device__ __forceinline__ void nl_tile(const KParams& p, int t, char* smem)
     for (int hc = wid; hc < ncells; hc += nw) {
         if (!s.fits) {
             if (mode == 2)
-                nl_home_cell<2, kHalf, false, false>(p, s, hc);
+                nl_home_cell<2, kHalf, false, false, kCopy>(p, s, hc);
             else
-                nl_home_cell<1, kHalf, false, false>(p, s, hc);
+                nl_home_cell<1, kHalf, false, false, kCopy>(p, s, hc);
         } else if (mode == 0) {
             if (small)
-                nl_home_cell<0, kHalf, true, true>(p, s, hc);
+                nl_home_cell<0, kHalf, true, true, kCopy>(p, s, hc);
             else
-                nl_home_cell<0, kHalf, true, false>(p, s, hc);
+                nl_home_cell<0, kHalf, true, false, kCopy>(p, s, hc);
         } else if (mode == 1) {
             if (small)
-                nl_home_cell<1, kHalf, true, true>(p, s, hc);
+                nl_home_cell<1, kHalf, true, true, kCopy>(p, s, hc);
             else
-                nl_home_cell<1, kHalf, true, false>(p, s, hc);
+                nl_home_cell<1, kHalf, true, false, kCopy>(p, s, hc);
         } else {
-            nl_home_cell<2, kHalf, true, false>(p, s, hc);
+            nl_home_cell<2, kHalf, true, false, kCopy>(p, s, hc);
         }
     }
 }
@@ -370,7 +423,7 @@ __device__ __forceinline__ void nl_tile(const KParams& p, int t, char* smem)
 // from the uneven tile counts of the last wave of workgroups); tile v keeps
 // the XCD-aware order (v mod 8 is the workgroup's XCD when n is a multiple
 // of 8).
-template <class B, int kMethod, bool kHalf>
+template <class B, int kMethod, bool kHalf, bool kCopy>
 __global__ void k_nl_tiles(B b, int force)
 {
     Wg wg;
@@ -378,8 +431,9 @@ __global__ void k_nl_tiles(B b, int force)
     if (!b.fetch(G_NL, wg, p)) return;
     if (!force && !p.dev->rebuild) return;
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    for (int v = wg.id; v < p.n_tiles; v += wg.n) {
-        nl_tile<kMethod, kHalf>(p, xcd_tile(v, p.n_tiles), smem);
+    const KParams q = kCopy ? scratch_view(p) : p;
+    for (int v = wg.id; v < q.n_tiles; v += wg.n) {
+        nl_tile<kMethod, kHalf, kCopy>(q, xcd_tile(v, q.n_tiles), smem);
         __syncthreads();  // the next tile reuses the LDS
     }
 }
@@ -409,24 +463,29 @@ __global__ void k_nl_export(KParams p, int32_t* out)
     }
 }
 
-template <class B, bool kHalf>
+template <class B, bool kHalf, bool kCopy>
 static void neighbors_seq(const B& b, const LaunchShape& sh, int force, hipStream_t s)
 {
     const dim3 g(sh.grid[G_NL]), t(sh.nl_block);
     if (sh.nl_method == MD_NL_CELL_WAVES)
-        hipLaunchKernelGGL((k_nl_tiles<B, MD_NL_CELL_WAVES, kHalf>), g, t, sh.nl_lds, s, b,
-                           force);
+        hipLaunchKernelGGL((k_nl_tiles<B, MD_NL_CELL_WAVES, kHalf, kCopy>), g, t, sh.nl_lds, s,
+                           b, force);
     else
-        hipLaunchKernelGGL((k_nl_tiles<B, MD_NL_LANES, kHalf>), g, t, sh.nl_lds, s, b, force);
+        hipLaunchKernelGGL((k_nl_tiles<B, MD_NL_LANES, kHalf, kCopy>), g, t, sh.nl_lds, s, b,
+                           force);
 }
 
 template <class B>
-static void neighbors_seq(const B& b, const LaunchShape& sh, int force, hipStream_t s)
+static void neighbors_seq(const B& b, const LaunchShape& sh, int flags, hipStream_t s)
 {
+    const int force = flags & 1;
+    const bool copy = (flags & kFoldCopy) && sh.reorder;
     if (sh.newton3)
-        neighbors_seq<B, true>(b, sh, force, s);
+        copy ? neighbors_seq<B, true, true>(b, sh, force, s)
+             : neighbors_seq<B, true, false>(b, sh, force, s);
     else
-        neighbors_seq<B, false>(b, sh, force, s);
+        copy ? neighbors_seq<B, false, true>(b, sh, force, s)
+             : neighbors_seq<B, false, false>(b, sh, force, s);
 }
 
 void launch_neighbors(const KParams& p, int force, hipStream_t s)
