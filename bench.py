@@ -512,8 +512,9 @@ def run_batch(steps=500, warmup=20, tune_cache=None, fixed_tuning=None):
             "force_ms_avg": round(f_ms, 5), "mean_nl": round(mean_nl, 2),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                         "traffic": None, "kernel": "k_forces_tiles<Batch>",
-                         "bytes_per_atom": round(bpa, 2)},
+                         "traffic": measured_traffic(n_tot, "fp32"),
+                         "kernel": "k_forces_tiles<Batch>", "bytes_per_atom": round(bpa, 2),
+                         "units_per_launch": n_tot},
             "flags": flags}
 
 
