@@ -158,10 +158,10 @@ def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled", detail
                         shifted=w.shifted, precision=precision, neighbor_list=w.use_nl,
                         newton3=newton3, pipeline=pipeline, reorder=reorder)
     sim.prepare()
-    sim.step(warmup)  # more than 32 steps: md_step captures its graph here
+    sim.step(warmup)
     o0 = sim.reduce()
     e0 = (o0["U"] + o0["K"]) / w.n
-    # the timed run: md_step as it runs by default (graph replays)
+    # the timed run: md_step as it runs by default (direct launches)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
@@ -169,15 +169,17 @@ def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled", detail
     t1 = time.perf_counter()
     o1 = sim.reduce()
     e1 = (o1["U"] + o1["K"]) / w.n
-    # the same number of steps with every kernel launched directly (the step
-    # rate without the graph)
-    sim.set_graph(False)
+    # the same number of steps replayed from md_step's HIP graph (runs of 32
+    # steps, captured by a first short run), for comparison
+    sim.set_graph(True)
+    sim.step(40)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     sim.step(steps)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
-    direct = w.n * steps / (t3 - t2)
+    graphed = w.n * steps / (t3 - t2)
+    sim.set_graph(False)
     # and again with every part of each step bracketed by HIP events on the
     # bound stream: the force kernel's average duration and the split of a
     # step's time over its parts (the rows of the paper's Table 2)
@@ -186,7 +188,6 @@ def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled", detail
     f_ms, f_launches = sim.get_timing()
     parts = sim.get_timing_parts()
     sim.set_timing(False)
-    sim.set_graph(True)
     tot = sum(ms for ms, _ in parts.values())
     split = {k: {"us_per_step": round(1e3 * ms / steps, 2),
                  "pct": round(100.0 * ms / tot, 1) if tot > 0 else None}
@@ -194,7 +195,7 @@ def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled", detail
     if not detail:
         wall = t1 - t0
         res = {"value": w.n * steps / wall, "ms_per_step": 1e3 * wall / steps,
-               "value_direct_launches": direct,
+               "value_graph_replays": graphed,
                "force_ms_avg": f_ms / max(f_launches, 1), "energy_drift_per_atom": e1 - e0,
                "rebuilds": int(o1["n_rebuilds"] - o0["n_rebuilds"]), "parts": split}
         res["energy_drift"] = energy_drift(sim, w, drift_steps)
@@ -208,7 +209,7 @@ def run_gpu(w, precision, steps, warmup, newton3=False, pipeline="tiled", detail
     res = {
         "value": w.n * steps / wall,
         "ms_per_step": 1e3 * wall / steps,
-        "value_direct_launches": direct,
+        "value_graph_replays": graphed,
         "force_ms_avg": f_ms / max(f_launches, 1),
         "force_launches": f_launches,
         "mean_nl": mean_nl,
@@ -340,7 +341,7 @@ def run_small(drift_steps):
     c1 = {"workload": "wca_4000: WCA (LJ cut and shifted at 2^(1/6) sigma), N=4000 FCC, "
                       "rho=0.8, T=1, dt=0.005, cells only, FP64, 1000 steps",
           "value": round(c1["value"], 1), "us_per_step": round(1e3 * c1["ms_per_step"], 3),
-          "value_direct_launches": round(c1["value_direct_launches"], 1),
+          "value_graph_replays": round(c1["value_graph_replays"], 1),
           "force_us_avg": round(1e3 * c1["force_ms_avg"], 3),
           "energy_drift": c1["energy_drift"]}
     print(f"[bench] wca_4000 done: {c1['value']:.3e} atom-steps/s", file=sys.stderr, flush=True)
@@ -351,7 +352,7 @@ def run_small(drift_steps):
         r = run_gpu(w2, prec, 2000, 100, drift_steps=drift_steps)
         c2[prec if prec == "fp64" else "fp32_mixed"] = {
             "value": round(r["value"], 1), "us_per_step": round(1e3 * r["ms_per_step"], 3),
-            "value_direct_launches": round(r["value_direct_launches"], 1),
+            "value_graph_replays": round(r["value_graph_replays"], 1),
             "force_us_avg": round(1e3 * r["force_ms_avg"], 3), "rebuilds": r["rebuilds"],
             "mean_nl": round(r["mean_nl"], 2), "roofline": r["roofline"],
             "energy_drift": r["energy_drift"]}
@@ -490,6 +491,11 @@ def run_batch(steps=500, warmup=20, tune_cache=None, fixed_tuning=None):
     b.run(steps, graph=True)
     b.synchronize()
     wall = time.perf_counter() - t0
+    # the same steps with every kernel launched directly, for comparison
+    t0 = time.perf_counter()
+    b.run(steps, graph=False)
+    b.synchronize()
+    wall_direct = time.perf_counter() - t0
     # the force pass alone, all replicas in one launch (HIP events on the batch stream)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     with torch.cuda.stream(b.stream):
@@ -504,6 +510,7 @@ def run_batch(steps=500, warmup=20, tune_cache=None, fixed_tuning=None):
     achieved = bpa * n_tot / (f_ms * 1e-3) / 1e9
     flags = max(b.reduce(r)["flags"] for r in range(len(reps)))
     return {"value": n_tot * steps / wall, "ms_per_step": 1e3 * wall / steps,
+            "value_direct_launches": n_tot * steps / wall_direct,
             "n_atoms": n_tot, "replicas": len(reps), "steps": steps,
             "autotune": {"best": cands[best] if best >= 0 else b.get_tuning(),
                          "cache": tune_cache or None, "fixed": bool(fixed_tuning),
@@ -675,8 +682,8 @@ def main():
         "energy_drift_per_atom": fp64["energy_drift_per_atom"],
         "energy_drift": fp64.get("energy_drift"),
         "force_ms_avg": round(fp64["force_ms_avg"], 5),
-        "value_direct_launches": (round(fp64["value_direct_launches"], 1)
-                                  if "value_direct_launches" in fp64 else None),
+        "value_graph_replays": (round(fp64["value_graph_replays"], 1)
+                                if "value_graph_replays" in fp64 else None),
         "parts": fp64.get("parts"),
     }
     if mixed is not None:

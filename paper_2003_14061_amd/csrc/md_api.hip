@@ -160,7 +160,6 @@ static void relayout(md_ctx* c)
 static md_status launched() { return hip_ok(hipGetLastError()); }
 
 static void drop_graph(md_ctx* c);  // md_step's captured graph (below)
-constexpr int kGraphAtoms = 131072;  // md_step graph on by default up to this size
 
 extern "C" md_status md_init(const md_params* in, md_ctx** out)
 {
@@ -199,7 +198,7 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
     md_ctx* c = new (std::nothrow) md_ctx();
     if (!c) return MD_ERR_ARG;
     c->prm = p;
-    c->graph_on = p.n_atoms <= kGraphAtoms;
+    c->graph_on = false;  // md_set_graph
     const int64_t n = p.n_atoms;
     const int npad = (int)((n + 63) / 64 * 64);
     int cap = 0;
@@ -664,12 +663,13 @@ extern "C" md_status md_forces(md_ctx* c)
 //
 // A step is a fixed launch sequence (integrate, the rebuild-gated cell and
 // list kernels, forces), so runs of kGraphSteps steps can be captured once
-// into a HIP graph and replayed.  Measured on MI355X: an idle kernel costs
-// about 1.6 us from a graph against 2.7 us launched on a stream, and the
-// 4000-atom cells-only system steps 8% faster from the graph; with kernels of
-// tens of microseconds and more the graph is 1.5-2% slower (256 000 and 2.048M
-// atoms), so the graph is on by default up to kGraphAtoms atoms
-// (md_set_graph overrides).  The first step of a call (its integrate kernel
+// into a HIP graph and replayed (md_set_graph), for callers that need the
+// step as a graph.  It is off by default: with the present launch sequence
+// (an integration pass and its one-workgroup finish, the gated cell and list
+// kernels, the force pass) direct launches measured faster on MI355X at
+// every size tried, 9-20% per step for 4000 to 131 072 atoms (4000-atom WCA
+// cells-only 29.7 against 32.4 us, 32 000-atom LJ 38.2 against 45.9 us).
+// The first step of a call (its integrate kernel
 // only kicks and drifts) and the remainder are launched directly.  A call of
 // fewer than kGraphSteps + 1 steps (but at least kGraphMin + 1) replays one
 // graph of its own length instead, so that repeated short calls (the
