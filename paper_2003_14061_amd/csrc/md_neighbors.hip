@@ -287,13 +287,18 @@ __device__ __forceinline__ int nl_home_atom(const KParams& p, const Stage& s, in
     uint64_t* col = p.nl64 + slot_i;
     uint64_t chunk = 0;
     uint32_t m = 0;
+    // An interior tile (kImage 0) has no wrapped cell: the three cells of a
+    // window are consecutive cells of one row, contiguous both among the staged
+    // atoms and in the cell-ordered slots, with no wrap bits, so each window is
+    // walked as one run (9 loops instead of 27).
+    constexpr int kRuns = kImage == 0 ? 1 : 3;
     for (int sg = 0; sg < 9; ++sg) {
         const int tw = window_cell(s, home_t, sg);
 #pragma unroll
-        for (int w = 0; w < 3; ++w) {
+        for (int w = 0; w < kRuns; ++w) {
             const int t = tw + w;
-            const int eb = s.off[t], ee = s.off[t + 1];
-            const int fl = s.flag[t];
+            const int eb = s.off[t], ee = s.off[t + (kImage == 0 ? 3 : 1)];
+            const int fl = kImage == 0 ? 0 : s.flag[t];
             const int tslot = kFits && !kHalf ? 0 : s.slot[t];
             const uint64_t tag = (uint64_t)fl << kEntryBits;
             if (kHalf && tslot + (ee - eb) <= pos_i) continue;
