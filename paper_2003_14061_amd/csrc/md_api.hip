@@ -530,14 +530,17 @@ extern "C" md_status md_bind_static(md_ctx* c, const md_buffers* bf, void* strea
 }
 
 // The stages of either pipeline.
-static void cells_any(const KParams& k, int force, hipStream_t s)
+// flags: bit 0 forces the build; the tiled cell build also takes kFoldCopy,
+// kFoldBin and kSortSmallOk (md_internal.h).
+static void cells_any(const KParams& k, int flags, hipStream_t s)
 {
+    const int force = flags & 1;
     if (k.pipeline == MD_PIPE_LAYERS)
         launch_layer_cells(k, force, s);
     else if (k.pipeline == MD_PIPE_ALLPAIRS) {
         if (force) launch_allpairs_fold(k, s);  // in a step the drift folds
     } else
-        launch_cells(k, force, s);
+        launch_cells(k, flags, s);
     if (k.bonded_on) launch_bond_map(k, force, s);  // after any permutation of the slots
 }
 
@@ -549,14 +552,15 @@ static void neighbors_any(const KParams& k, int force, hipStream_t s)
         launch_neighbors(k, force, s);
 }
 
-static void forces_any(const KParams& k, hipStream_t s)
+// flags: kFoldCopy for the tiled cells-only pass (md_internal.h).
+static void forces_any(const KParams& k, hipStream_t s, int flags = 0)
 {
     if (k.pipeline == MD_PIPE_LAYERS)
         launch_layer_forces(k, s);
     else if (k.pipeline == MD_PIPE_ALLPAIRS)
         launch_allpairs_forces(k, s);
     else
-        launch_forces(k, s);
+        launch_forces(k, s, flags);
     if (k.bonded_on) launch_bonded(k, s);  // adds to the pair forces
 }
 
@@ -608,9 +612,9 @@ static void timed(md_ctx* c, int part, Fn&& fn)
     c->ev_part.push_back(part);
 }
 
-static void timed_forces(md_ctx* c)
+static void timed_forces(md_ctx* c, int flags = 0)
 {
-    timed(c, MD_PART_FORCES, [&] { forces_any(c->kp, c->stream); });
+    timed(c, MD_PART_FORCES, [&] { forces_any(c->kp, c->stream, flags); });
 }
 
 static md_status fold_timing(md_ctx* c)
@@ -705,28 +709,36 @@ static md_status step_launches(md_ctx* c, hipStream_t s, bool first, int32_t n,
 {
     const KParams& k = c->kp;
     const bool nl = c->prm.mode == MD_NEIGHBOR_LIST;
-    // the reorder's copy-back folded into the list build (tiled lists)
-    const int fold = nl && k.pipeline == MD_PIPE_TILED && k.reorder && !k.bonded_on
-                         ? kFoldCopy
-                         : 0;
+    const bool tiled = k.pipeline == MD_PIPE_TILED;
+    // the reorder's copy-back folded into the pass after the cell build (the
+    // list build, or the cells-only force pass)
+    const int fold = tiled && k.reorder && !k.bonded_on ? kFoldCopy : 0;
+    // cells only: the cells are rebuilt every step, so the integration pass
+    // bins the atoms and a small system sorts them in one workgroup
+    const bool cells = tiled && !nl;
+    const int cflags = fold | (cells ? kFoldBin | kSortSmallOk : 0);
+    const int fflags = cells ? fold : 0;
     if (s != c->stream) {  // captured into a graph: never timed, never reordered
         for (int32_t i = 0; i < n; ++i) {
-            launch_integrate(k, first && i == 0 ? 0 : 1, record_every, s);
-            cells_any(k, fold, s);
+            const int phase = first && i == 0 ? 0 : 1;
+            launch_integrate_pass(k, phase, record_every, s, cells);
+            launch_integrate_finish(k, phase, record_every, s);
+            cells_any(k, cflags, s);
             if (nl) neighbors_any(k, fold, s);
-            forces_any(k, s);
+            forces_any(k, s, fflags);
         }
         return MD_OK;
     }
     for (int32_t i = 0; i < n; ++i) {
         const int phase = first && i == 0 ? 0 : 1;
-        timed(c, MD_PART_INTEGRATE, [&] { launch_integrate_pass(k, phase, record_every, s); });
+        timed(c, MD_PART_INTEGRATE,
+              [&] { launch_integrate_pass(k, phase, record_every, s, cells); });
         timed(c, MD_PART_ENERGY, [&] { launch_integrate_finish(k, phase, record_every, s); });
         const bool reorder = layer_reorder_on(c) && (step0 + i + 1) % k.reorder == 0;
         if (reorder) timed(c, MD_PART_REORDER, [&] { launch_layer_reorder(k, s); });
-        timed(c, MD_PART_CELLS, [&] { cells_any(k, reorder ? 1 : fold, s); });
+        timed(c, MD_PART_CELLS, [&] { cells_any(k, reorder ? 1 : cflags, s); });
         if (nl) timed(c, MD_PART_NEIGHBORS, [&] { neighbors_any(k, reorder ? 1 : fold, s); });
-        timed_forces(c);
+        timed_forces(c, fflags);
         if (c->timing && c->ev_pending.size() >= 8192) {
             md_status st = fold_timing(c);
             if (st != MD_OK) return st;

@@ -58,7 +58,6 @@ __global__ void k_bin(B b, int force)
     KParams p;
     if (!b.fetch(G_ATOMS, wg, p)) return;
     if (!rebuild_on(p, force)) return;
-    const int lane = threadIdx.x & (kWave - 1);
     for (int i0 = wg.id * blockDim.x; i0 < p.n; i0 += wg.n * blockDim.x) {
         const int i = i0 + threadIdx.x;
         const bool act = i < p.n;
@@ -74,26 +73,7 @@ __global__ void k_bin(B b, int force)
             c = cell_of_pos(x, y, z, p);
             p.cell_of[i] = c;
         }
-        // Atoms stored in cell order put a wave's lanes into runs of one
-        // cell: the first lane of each run takes one atomic for the whole run
-        // (all runs of the wave at once) and the others rank themselves by
-        // their distance from it.  A cell met in two runs takes two atomics;
-        // the in-cell order is fixed later, so only distinct slots matter.
-        const int prev = __shfl_up(c, 1, kWave);
-        const bool head = act && (lane == 0 || prev != c);
-        const uint64_t heads = __ballot(head);
-        const int n_act = (int)__popcll(__ballot(act));  // active lanes are a prefix
-        const uint64_t upto = (2ull << lane) - 1ull;     // lanes 0..lane
-        const int h = act ? 63 - (int)__clzll(heads & upto) : lane;
-        int base = 0;
-        if (head) {
-            const uint64_t later = heads & ~upto;
-            int end = later ? (int)__ffsll((unsigned long long)later) - 1 : kWave;
-            end = end < n_act ? end : n_act;
-            base = atomicAdd(&p.cell_count[c], end - lane);
-        }
-        base = __shfl(base, h, kWave);
-        if (act) p.slot[i] = base + (lane - h);
+        rank_in_cell(p, act, c, i);
     }
 }
 
@@ -115,14 +95,10 @@ __device__ __forceinline__ int wave_incl_scan(int v)
 // clears the counts for the next binning and records the largest
 // occupancy.  A single launch, so that a step with no rebuild pays for one
 // idle kernel here rather than three.
-template <class B>
-__global__ __launch_bounds__(kScanThreads) void k_scan(B b, int force)
+// The scan itself, by one workgroup of kScanThreads threads (wsum: LDS, one
+// int per wave).
+__device__ __forceinline__ void scan_cells(const KParams& p, int* wsum)
 {
-    Wg wg;
-    KParams p;
-    if (!b.fetch(G_ONE, wg, p)) return;
-    if (!rebuild_on(p, force)) return;
-    __shared__ int wsum[kScanThreads / kWave];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     int carry = 0, m = 0;
     for (int c0 = 0; c0 < p.ncell; c0 += kScanThreads * kScanPer) {
@@ -190,24 +166,69 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(B b, int force)
 }
 
 template <class B>
+__global__ __launch_bounds__(kScanThreads) void k_scan(B b, int force)
+{
+    Wg wg;
+    KParams p;
+    if (!b.fetch(G_ONE, wg, p)) return;
+    if (!rebuild_on(p, force)) return;
+    __shared__ int wsum[kScanThreads / kWave];
+    scan_cells(p, wsum);
+}
+
+// Slot q of atom i in cell order (in the order the atomics gave), with its
+// permanent id beside it for the in-cell rank.
+__device__ __forceinline__ void scatter_atom(const KParams& p, int i)
+{
+    const int q = p.cell_start[p.cell_of[i]] + p.slot[i];
+    p.tmp[q] = i;
+    p.tmp[p.n + q] = p.id[i];  // the ids of a cell side by side
+}
+
+// Canonical order inside each cell: ascending permanent id.  The atom at
+// slot-order position q counts the members of its cell with a smaller id
+// (ids are distinct); that count is its place.  With kPermute the atom's
+// data go to that place in the scratch arrays (the permutation into cell
+// order, scattered from the atom rather than gathered by a second pass).
+template <typename F, bool kPermute>
+__device__ __forceinline__ void sort_slot(const KParams& p, int q)
+{
+    const int32_t* ids = p.tmp + p.n;  // ids in slot order (scatter_atom)
+    const int s = p.tmp[q];
+    const int c = p.cell_of[s];
+    const int a = p.cell_start[c], cnt = p.cell_start[c + 1] - a;
+    const int key = ids[q];
+    int rank = 0;
+#pragma unroll 4
+    for (int j = 0; j < cnt; ++j) rank += ids[a + j] < key ? 1 : 0;
+    const int d = a + rank;
+    p.order[d] = s;
+    if (kPermute) {
+        p.sx[d] = p.x[s];
+        p.sy[d] = p.y[s];
+        p.sz[d] = p.z[s];
+        p.svx[d] = p.vx[s];
+        p.svy[d] = p.vy[s];
+        p.svz[d] = p.vz[s];
+        reinterpret_cast<F*>(p.sfx)[d] = static_cast<const F*>(p.fx)[s];
+        reinterpret_cast<F*>(p.sfy)[d] = static_cast<const F*>(p.fy)[s];
+        reinterpret_cast<F*>(p.sfz)[d] = static_cast<const F*>(p.fz)[s];
+        p.sid[d] = key;
+        p.scell[d] = c;
+    }
+}
+
+template <class B>
 __global__ void k_scatter(B b, int force)
 {
     Wg wg;
     KParams p;
     if (!b.fetch(G_ATOMS, wg, p)) return;
     if (!rebuild_on(p, force)) return;
-    for (int i = wg.id * blockDim.x + threadIdx.x; i < p.n; i += wg.n * blockDim.x) {
-        const int q = p.cell_start[p.cell_of[i]] + p.slot[i];
-        p.tmp[q] = i;
-        p.tmp[p.n + q] = p.id[i];  // the ids of a cell side by side, for k_cellsort
-    }
+    for (int i = wg.id * blockDim.x + threadIdx.x; i < p.n; i += wg.n * blockDim.x)
+        scatter_atom(p, i);
 }
 
-// Canonical order inside each cell: ascending permanent id.  One lane per
-// atom counts the members of its cell with a smaller id (ids are distinct);
-// that count is its place.  With kPermute the atom's data go to that place
-// in the scratch arrays (the permutation into cell order, scattered from the
-// atom rather than gathered by a second pass).
 template <typename F, class B, bool kPermute>
 __global__ void k_cellsort(B b, int force)
 {
@@ -215,31 +236,27 @@ __global__ void k_cellsort(B b, int force)
     KParams p;
     if (!b.fetch(G_ATOMS, wg, p)) return;
     if (!rebuild_on(p, force)) return;
-    const int32_t* ids = p.tmp + p.n;  // ids in slot order (k_scatter)
-    for (int q = wg.id * blockDim.x + threadIdx.x; q < p.n; q += wg.n * blockDim.x) {
-        const int s = p.tmp[q];
-        const int c = p.cell_of[s];
-        const int a = p.cell_start[c], cnt = p.cell_start[c + 1] - a;
-        const int key = ids[q];
-        int rank = 0;
-#pragma unroll 4
-        for (int j = 0; j < cnt; ++j) rank += ids[a + j] < key ? 1 : 0;
-        const int d = a + rank;
-        p.order[d] = s;
-        if (kPermute) {
-            p.sx[d] = p.x[s];
-            p.sy[d] = p.y[s];
-            p.sz[d] = p.z[s];
-            p.svx[d] = p.vx[s];
-            p.svy[d] = p.vy[s];
-            p.svz[d] = p.vz[s];
-            reinterpret_cast<F*>(p.sfx)[d] = static_cast<const F*>(p.fx)[s];
-            reinterpret_cast<F*>(p.sfy)[d] = static_cast<const F*>(p.fy)[s];
-            reinterpret_cast<F*>(p.sfz)[d] = static_cast<const F*>(p.fz)[s];
-            p.sid[d] = key;
-            p.scell[d] = c;
-        }
-    }
+    for (int q = wg.id * blockDim.x + threadIdx.x; q < p.n; q += wg.n * blockDim.x)
+        sort_slot<F, kPermute>(p, q);
+}
+
+// Small systems (at most kSortSmall atoms): the scan, the scatter and the
+// in-cell sort by one workgroup, one launch instead of three (their
+// barriers order the global writes of one phase before the reads of the
+// next inside the workgroup).
+template <typename F, class B, bool kPermute>
+__global__ __launch_bounds__(kScanThreads) void k_sort_small(B b, int force)
+{
+    Wg wg;
+    KParams p;
+    if (!b.fetch(G_ONE, wg, p)) return;
+    if (!rebuild_on(p, force)) return;
+    __shared__ int wsum[kScanThreads / kWave];
+    scan_cells(p, wsum);
+    __syncthreads();
+    for (int i = threadIdx.x; i < p.n; i += blockDim.x) scatter_atom(p, i);
+    __syncthreads();
+    for (int q = threadIdx.x; q < p.n; q += blockDim.x) sort_slot<F, kPermute>(p, q);
 }
 
 template <typename F, class B>
@@ -272,22 +289,35 @@ static void clear_seq(const B& b, const LaunchShape& sh, hipStream_t s)
 }
 
 template <class B>
-static void cells_seq(const B& b, const LaunchShape& sh, int flags, hipStream_t s)
+static void cells_seq(const B& b, const LaunchShape& sh, int flags, hipStream_t s, int n_small)
 {
     const int force = flags & 1;
-    const bool copy = !(flags & kFoldCopy);  // else the list build copies back
+    const bool copy = !(flags & kFoldCopy);  // else the list or force pass copies back
     const dim3 atoms(sh.grid[G_ATOMS]), blk(sh.block);
-    hipLaunchKernelGGL(k_bin<B>, atoms, blk, 0, s, b, force);
-    hipLaunchKernelGGL(k_scan<B>, dim3(sh.grid[G_ONE]), dim3(kScanThreads), 0, s, b, force);
-    hipLaunchKernelGGL(k_scatter<B>, atoms, blk, 0, s, b, force);
-    if (!sh.reorder) {
-        hipLaunchKernelGGL((k_cellsort<double, B, false>), atoms, blk, 0, s, b, force);
-    } else if (sh.precision == MD_FP64) {
-        hipLaunchKernelGGL((k_cellsort<double, B, true>), atoms, blk, 0, s, b, force);
-        if (copy) hipLaunchKernelGGL((k_copyback<double, B>), atoms, blk, 0, s, b, force);
+    if (!(flags & kFoldBin)) hipLaunchKernelGGL(k_bin<B>, atoms, blk, 0, s, b, force);
+    if (n_small) {  // one system of at most kSortSmall atoms
+        const dim3 one(1), t(kScanThreads);
+        if (!sh.reorder)
+            hipLaunchKernelGGL((k_sort_small<double, B, false>), one, t, 0, s, b, force);
+        else if (sh.precision == MD_FP64)
+            hipLaunchKernelGGL((k_sort_small<double, B, true>), one, t, 0, s, b, force);
+        else
+            hipLaunchKernelGGL((k_sort_small<float, B, true>), one, t, 0, s, b, force);
     } else {
-        hipLaunchKernelGGL((k_cellsort<float, B, true>), atoms, blk, 0, s, b, force);
-        if (copy) hipLaunchKernelGGL((k_copyback<float, B>), atoms, blk, 0, s, b, force);
+        hipLaunchKernelGGL(k_scan<B>, dim3(sh.grid[G_ONE]), dim3(kScanThreads), 0, s, b, force);
+        hipLaunchKernelGGL(k_scatter<B>, atoms, blk, 0, s, b, force);
+        if (!sh.reorder)
+            hipLaunchKernelGGL((k_cellsort<double, B, false>), atoms, blk, 0, s, b, force);
+        else if (sh.precision == MD_FP64)
+            hipLaunchKernelGGL((k_cellsort<double, B, true>), atoms, blk, 0, s, b, force);
+        else
+            hipLaunchKernelGGL((k_cellsort<float, B, true>), atoms, blk, 0, s, b, force);
+    }
+    if (sh.reorder && copy) {
+        if (sh.precision == MD_FP64)
+            hipLaunchKernelGGL((k_copyback<double, B>), atoms, blk, 0, s, b, force);
+        else
+            hipLaunchKernelGGL((k_copyback<float, B>), atoms, blk, 0, s, b, force);
     }
 }
 
@@ -295,7 +325,8 @@ void launch_clear(const KParams& p, hipStream_t s) { clear_seq(Single{p}, shape_
 
 void launch_cells(const KParams& p, int force, hipStream_t s)
 {
-    cells_seq(Single{p}, shape_of(p), force, s);
+    const bool small = (force & kSortSmallOk) && p.n <= kSortSmall;
+    cells_seq(Single{p}, shape_of(p), force, s, small ? p.n : 0);
 }
 
 // The cell offsets from the occupancy counts alone (forced), for the layer
@@ -309,7 +340,7 @@ void launch_clear(const Batch& b, const LaunchShape& sh, hipStream_t s) { clear_
 
 void launch_cells(const Batch& b, const LaunchShape& sh, int force, hipStream_t s)
 {
-    cells_seq(b, sh, force, s);
+    cells_seq(b, sh, force, s, 0);
 }
 
 }  // namespace md

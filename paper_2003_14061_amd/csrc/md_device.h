@@ -192,4 +192,93 @@ __device__ __forceinline__ bool last_block(DevState* dev, int n_wg)
     return last;
 }
 
+// Slot of atom i inside its cell c (every lane of the wave calls it; act:
+// lane i holds an atom).  Atoms stored in cell order put a wave's lanes into
+// runs of one cell: the first lane of each run takes one atomic for the whole
+// run (all runs of the wave at once) and the others rank themselves by their
+// distance from it.  A cell met in two runs takes two atomics; the in-cell
+// order is fixed later, so only distinct slots matter.
+__device__ __forceinline__ void rank_in_cell(const KParams& p, bool act, int c, int i)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int prev = __shfl_up(c, 1, kWave);
+    const bool head = act && (lane == 0 || prev != c);
+    const uint64_t heads = __ballot(head);
+    const int n_act = (int)__popcll(__ballot(act));  // active lanes are a prefix
+    const uint64_t upto = (2ull << lane) - 1ull;     // lanes 0..lane
+    const int h = act ? 63 - (int)__clzll(heads & upto) : lane;
+    int base = 0;
+    if (head) {
+        const uint64_t later = heads & ~upto;
+        int end = later ? (int)__ffsll((unsigned long long)later) - 1 : kWave;
+        end = end < n_act ? end : n_act;
+        base = atomicAdd(&p.cell_count[c], end - lane);
+    }
+    base = __shfl(base, h, kWave);
+    if (act) p.slot[i] = base + (lane - h);
+}
+
+// The copy-back of the reorder folded into the pass that follows the cell
+// build (kFoldCopy: the list build, or the cells-only force pass): the cell
+// build left the atoms' data in cell order in the scratch arrays, so that
+// pass runs over the view of p with state and scratch arrays exchanged
+// (positions read from the sorted copy), and every atom's data is copied
+// from there into the state arrays by the one thread that owns it (its
+// tile's, or its own); no thread reads another atom's data from the state
+// arrays during the pass.
+__device__ __forceinline__ KParams scratch_view(const KParams& p)
+{
+    KParams q = p;
+    q.x = p.sx; q.sx = p.x;
+    q.y = p.sy; q.sy = p.y;
+    q.z = p.sz; q.sz = p.z;
+    q.vx = p.svx; q.svx = p.vx;
+    q.vy = p.svy; q.svy = p.vy;
+    q.vz = p.svz; q.svz = p.vz;
+    // the force scratch arrays are typed double but hold the force type
+    q.fx = p.sfx; q.sfx = static_cast<double*>(p.fx);
+    q.fy = p.sfy; q.sfy = static_cast<double*>(p.fy);
+    q.fz = p.sfz; q.sfz = static_cast<double*>(p.fz);
+    q.id = p.sid; q.sid = p.id;
+    q.cell_of = p.scell; q.scell = p.cell_of;
+    return q;
+}
+
+// Atom at slot k, over scratch_view: its sorted data into the state (the
+// forces too unless kForces is false, for a pass that writes them anew).
+template <bool kCopy, bool kForces = true>
+__device__ __forceinline__ void copy_home(const KParams& q, int k)
+{
+    if (!kCopy) return;
+    q.sx[k] = q.x[k];
+    q.sy[k] = q.y[k];
+    q.sz[k] = q.z[k];
+    q.svx[k] = q.vx[k];
+    q.svy[k] = q.vy[k];
+    q.svz[k] = q.vz[k];
+    if (!kForces) {
+    } else if (q.precision == MD_FP64) {
+        q.sfx[k] = static_cast<const double*>(q.fx)[k];
+        q.sfy[k] = static_cast<const double*>(q.fy)[k];
+        q.sfz[k] = static_cast<const double*>(q.fz)[k];
+    } else {
+        reinterpret_cast<float*>(q.sfx)[k] = static_cast<const float*>(q.fx)[k];
+        reinterpret_cast<float*>(q.sfy)[k] = static_cast<const float*>(q.fy)[k];
+        reinterpret_cast<float*>(q.sfz)[k] = static_cast<const float*>(q.fz)[k];
+    }
+    q.sid[k] = q.id[k];
+    q.scell[k] = q.cell_of[k];
+    q.order[k] = k;
+}
+
+// One home cell hc of the tile, by one wave.  The candidates (the 9 windows
+// of three cells next to it, concatenated, in canonical order)
+// are taken kNlRounds x 64 at a time: lane l holds candidate k0 + 64 r + l
+// (position, wrap bits, encoded entry) in registers.  Each home atom hh in
+// turn is broadcast from lane hh (readlane) and tested against the block;
+// for round r the hit ballot places the hits: a hit lane's entry goes to
+// list position m_hh + (hits of lower lanes), m_hh being hh's running list
+// length, kept in a scalar register while hh is tested and in lane hh of a
+// vector register between blocks.  Lanes past the candidates read the home
+// cell's first atom (e = hb) and never hit.
 }  // namespace md

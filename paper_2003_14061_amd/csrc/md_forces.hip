@@ -260,12 +260,18 @@ __device__ __forceinline__ void walk_cell(const KParams& p, int i, double xi, do
     }
 }
 
-template <typename F, typename Acc, class B>
+// kCopy (md_step with reorder): the cell build left the sorted data in the
+// scratch arrays; the pass reads them there and each atom's lane 0 copies its
+// atom into the state arrays, forces written straight into the state.
+template <typename F, typename Acc, class B, bool kCopy>
 __global__ void k_forces_cells(B b)
 {
     Wg wg;
-    KParams p;
-    if (!b.fetch(G_TILES, wg, p)) return;
+    KParams pw;
+    if (!b.fetch(G_TILES, wg, pw)) return;
+    const KParams p = kCopy ? scratch_view(pw) : pw;
+    F* const fout[3] = {static_cast<F*>(pw.fx), static_cast<F*>(pw.fy),
+                        static_cast<F*>(pw.fz)};
     __shared__ double red[(1024 / kWave) * 2];
     const int64_t t = (int64_t)xcd_tile(wg.id, wg.n) * blockDim.x + threadIdx.x;
     const int i = (int)(t / kCellLanes), sub = (int)(t % kCellLanes);
@@ -287,9 +293,10 @@ __global__ void k_forces_cells(B b)
     if (i < p.n && sub == 0) {
         F fx, fy, fz;
         lean_finish(p, a, fx, fy, fz, e[0], e[1]);
-        static_cast<F*>(p.fx)[i] = fx;
-        static_cast<F*>(p.fy)[i] = fy;
-        static_cast<F*>(p.fz)[i] = fz;
+        copy_home<kCopy, false>(p, i);
+        fout[0][i] = fx;
+        fout[1][i] = fy;
+        fout[2][i] = fz;
         if (!isfinite(e[0] + (double)fx + (double)fy + (double)fz))
             atomicOr(&p.dev->flags, (int)MD_FLAG_NONFINITE);
     }
@@ -332,14 +339,19 @@ static void tiles_seq(const B& b, const LaunchShape& sh, hipStream_t s)
 }
 
 template <class B>
-static void forces_seq(const B& b, const LaunchShape& sh, hipStream_t s)
+static void forces_seq(const B& b, const LaunchShape& sh, hipStream_t s, int flags = 0)
 {
     if (sh.mode == MD_CELLS_ONLY) {
         const dim3 g(sh.grid[G_TILES]), t(sh.block);
-        if (sh.precision == MD_FP64)
-            hipLaunchKernelGGL((k_forces_cells<double, AccD, B>), g, t, 0, s, b);
+        const bool copy = (flags & kFoldCopy) && sh.reorder;
+        if (sh.precision == MD_FP64 && copy)
+            hipLaunchKernelGGL((k_forces_cells<double, AccD, B, true>), g, t, 0, s, b);
+        else if (sh.precision == MD_FP64)
+            hipLaunchKernelGGL((k_forces_cells<double, AccD, B, false>), g, t, 0, s, b);
+        else if (copy)
+            hipLaunchKernelGGL((k_forces_cells<float, AccF, B, true>), g, t, 0, s, b);
         else
-            hipLaunchKernelGGL((k_forces_cells<float, AccF, B>), g, t, 0, s, b);
+            hipLaunchKernelGGL((k_forces_cells<float, AccF, B, false>), g, t, 0, s, b);
         return;
     }
     if (sh.precision == MD_FP64)
@@ -374,7 +386,10 @@ LaunchShape shape_of(const KParams& p)
     return sh;
 }
 
-void launch_forces(const KParams& p, hipStream_t s) { forces_seq(Single{p}, shape_of(p), s); }
+void launch_forces(const KParams& p, hipStream_t s, int flags)
+{
+    forces_seq(Single{p}, shape_of(p), s, flags);
+}
 
 void launch_forces(const Batch& b, const LaunchShape& sh, hipStream_t s) { forces_seq(b, sh, s); }
 

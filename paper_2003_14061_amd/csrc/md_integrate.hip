@@ -92,7 +92,10 @@ __device__ void record_step(const KParams& p, int n_wg, int record_every, double
     }
 }
 
-template <typename F, class B>
+// kBin (cells-only steps, which rebuild the cells every step): the drift also
+// folds the positions into [0, L) and bins them (cell and slot, as k_bin), so
+// that the cell build that follows starts at the scan.
+template <typename F, class B, bool kBin>
 __global__ __launch_bounds__(kIntThreads) void k_integrate(B b, int phase, int record_every)
 {
     Wg wg;
@@ -106,55 +109,65 @@ __global__ __launch_bounds__(kIntThreads) void k_integrate(B b, int phase, int r
     double dmax2 = 0.0;
     const int stride = wg.n * blockDim.x;
     const bool drift_now = phase <= 1, track = phase <= 1 && p.mode == MD_NEIGHBOR_LIST;
-    const bool fold = p.pipeline == MD_PIPE_ALLPAIRS;
-    for (int i = wg.id * blockDim.x + threadIdx.x; i < p.n; i += stride) {
-        // every input first, so that one round of loads serves the iteration
-        const double gx = (double)fx[i], gy = (double)fy[i], gz = (double)fz[i];
-        double vx = p.vx[i], vy = p.vy[i], vz = p.vz[i];
-        double x = 0.0, y = 0.0, z = 0.0, rx = 0.0, ry = 0.0, rz = 0.0;
-        if (drift_now) {
-            x = p.x[i];
-            y = p.y[i];
-            z = p.z[i];
-        }
-        if (track) {
-            rx = p.xr[i];
-            ry = p.yr[i];
-            rz = p.zr[i];
-        }
-        if (phase >= 1) {  // second half kick of the finished step
-            vx = kick(vx, p.hdt, gx);
-            vy = kick(vy, p.hdt, gy);
-            vz = kick(vz, p.hdt, gz);
-            acc[0] += (vx * vx + vy * vy) + vz * vz;
-            acc[1] += vx;
-            acc[2] += vy;
-            acc[3] += vz;
-        }
-        if (drift_now) {  // first half kick and drift of the next step
-            vx = kick(vx, p.hdt, gx);
-            vy = kick(vy, p.hdt, gy);
-            vz = kick(vz, p.hdt, gz);
-            x = drift(x, p.dt, vx);
-            y = drift(y, p.dt, vy);
-            z = drift(z, p.dt, vz);
-            if (fold) {  // no cell build follows to fold them
-                x = wrap(x, p.L);
-                y = wrap(y, p.L);
-                z = wrap(z, p.L);
+    const bool fold = p.pipeline == MD_PIPE_ALLPAIRS || kBin;
+    for (int i0 = wg.id * blockDim.x; i0 < p.n; i0 += stride) {
+        const int i = i0 + threadIdx.x;
+        int c = -1;
+        if (i < p.n) {
+            // every input first, so that one round of loads serves the iteration
+            const double gx = (double)fx[i], gy = (double)fy[i], gz = (double)fz[i];
+            double vx = p.vx[i], vy = p.vy[i], vz = p.vz[i];
+            double x = 0.0, y = 0.0, z = 0.0, rx = 0.0, ry = 0.0, rz = 0.0;
+            if (drift_now) {
+                x = p.x[i];
+                y = p.y[i];
+                z = p.z[i];
             }
-            p.x[i] = x;
-            p.y[i] = y;
-            p.z[i] = z;
             if (track) {
-                const double d2 = dist2(minimg(x - rx, p.L, p.invL), minimg(y - ry, p.L, p.invL),
-                                        minimg(z - rz, p.L, p.invL));
-                dmax2 = d2 > dmax2 ? d2 : dmax2;
+                rx = p.xr[i];
+                ry = p.yr[i];
+                rz = p.zr[i];
             }
+            if (phase >= 1) {  // second half kick of the finished step
+                vx = kick(vx, p.hdt, gx);
+                vy = kick(vy, p.hdt, gy);
+                vz = kick(vz, p.hdt, gz);
+                acc[0] += (vx * vx + vy * vy) + vz * vz;
+                acc[1] += vx;
+                acc[2] += vy;
+                acc[3] += vz;
+            }
+            if (drift_now) {  // first half kick and drift of the next step
+                vx = kick(vx, p.hdt, gx);
+                vy = kick(vy, p.hdt, gy);
+                vz = kick(vz, p.hdt, gz);
+                x = drift(x, p.dt, vx);
+                y = drift(y, p.dt, vy);
+                z = drift(z, p.dt, vz);
+                if (fold) {  // no cell build follows to fold them (or it starts here)
+                    x = wrap(x, p.L);
+                    y = wrap(y, p.L);
+                    z = wrap(z, p.L);
+                }
+                if (kBin) {
+                    c = cell_of_pos(x, y, z, p);
+                    p.cell_of[i] = c;
+                }
+                p.x[i] = x;
+                p.y[i] = y;
+                p.z[i] = z;
+                if (track) {
+                    const double d2 =
+                        dist2(minimg(x - rx, p.L, p.invL), minimg(y - ry, p.L, p.invL),
+                              minimg(z - rz, p.L, p.invL));
+                    dmax2 = d2 > dmax2 ? d2 : dmax2;
+                }
+            }
+            p.vx[i] = vx;
+            p.vy[i] = vy;
+            p.vz[i] = vz;
         }
-        p.vx[i] = vx;
-        p.vy[i] = vy;
-        p.vz[i] = vz;
+        if (kBin && drift_now) rank_in_cell(p, i < p.n, c, i);
     }
     block_sum<5>(acc, red);
     dmax2 = wave_max(dmax2);
@@ -247,13 +260,19 @@ __global__ __launch_bounds__(kIntThreads) void k_observe(KParams p)
 
 template <class B>
 static void integrate_pass(const B& b, const LaunchShape& sh, int phase, int record_every,
-                           hipStream_t s)
+                           hipStream_t s, bool bin = false)
 {
     const dim3 g(sh.grid[G_INTEGRATE]), t(kIntThreads);
-    if (sh.precision == MD_FP64)
-        hipLaunchKernelGGL((k_integrate<double, B>), g, t, 0, s, b, phase, record_every);
-    else
-        hipLaunchKernelGGL((k_integrate<float, B>), g, t, 0, s, b, phase, record_every);
+    if (bin && phase <= 1) {
+        if (sh.precision == MD_FP64)
+            hipLaunchKernelGGL((k_integrate<double, B, true>), g, t, 0, s, b, phase, record_every);
+        else
+            hipLaunchKernelGGL((k_integrate<float, B, true>), g, t, 0, s, b, phase, record_every);
+    } else if (sh.precision == MD_FP64) {
+        hipLaunchKernelGGL((k_integrate<double, B, false>), g, t, 0, s, b, phase, record_every);
+    } else {
+        hipLaunchKernelGGL((k_integrate<float, B, false>), g, t, 0, s, b, phase, record_every);
+    }
 }
 
 template <class B>
@@ -277,9 +296,10 @@ void launch_integrate(const KParams& p, int phase, int record_every, hipStream_t
     integrate_seq(Single{p}, shape_of(p), phase, record_every, s);
 }
 
-void launch_integrate_pass(const KParams& p, int phase, int record_every, hipStream_t s)
+void launch_integrate_pass(const KParams& p, int phase, int record_every, hipStream_t s,
+                           bool bin)
 {
-    integrate_pass(Single{p}, shape_of(p), phase, record_every, s);
+    integrate_pass(Single{p}, shape_of(p), phase, record_every, s, bin);
 }
 
 void launch_integrate_finish(const KParams& p, int phase, int record_every, hipStream_t s)

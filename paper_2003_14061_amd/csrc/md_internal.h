@@ -278,10 +278,19 @@ void launch_clear(const KParams& p, hipStream_t s);
 // build copies each tile's home atoms into the state arrays (saving the
 // separate copy-back pass and its launch).
 constexpr int kFoldCopy = 2;
+// Further launch_cells flags of md_step's cells-only sequence: kFoldBin --
+// the integration pass has already binned the atoms (k_bin is left out);
+// kSortSmallOk -- a system of at most kSortSmall atoms scans, scatters and
+// sorts in one workgroup (k_sort_small).  launch_forces takes kFoldCopy:
+// the cells-only force pass then copies each atom back from the scratch
+// arrays.
+constexpr int kFoldBin = 4;
+constexpr int kSortSmallOk = 8;
+constexpr int kSortSmall = 16384;
 void launch_cells(const KParams& p, int force, hipStream_t s);
 void launch_neighbors(const KParams& p, int force, hipStream_t s);
 void launch_nl_export(const KParams& p, int32_t* out, hipStream_t s);
-void launch_forces(const KParams& p, hipStream_t s);
+void launch_forces(const KParams& p, hipStream_t s, int flags = 0);
 // the same over a batch of replicas
 void launch_clear(const Batch& b, const LaunchShape& sh, hipStream_t s);
 void launch_cells(const Batch& b, const LaunchShape& sh, int force, hipStream_t s);
@@ -296,7 +305,9 @@ int force_blocks(const KParams& p);  // workgroups of the force pass for the cur
 void launch_integrate(const KParams& p, int phase, int record_every, hipStream_t s);
 // The two halves of launch_integrate: the per-atom pass, then the per-system
 // finish (reductions, step count and record, rebuild decision).
-void launch_integrate_pass(const KParams& p, int phase, int record_every, hipStream_t s);
+// bin: the pass also bins the atoms (cells-only steps; with phase <= 1 only).
+void launch_integrate_pass(const KParams& p, int phase, int record_every, hipStream_t s,
+                           bool bin = false);
 void launch_integrate_finish(const KParams& p, int phase, int record_every, hipStream_t s);
 void launch_observe(const KParams& p, hipStream_t s);
 

@@ -43,66 +43,6 @@ __device__ __forceinline__ double readlane_f64(double v, int lane)
 // LDS bytes of the list build: the staged tile.
 size_t nl_lds_bytes(const KParams& p) { return stage_bytes(p, p.scap); }
 
-// The copy-back of the reorder folded into the list build (kFoldCopy): the
-// cell build left the atoms' data in cell order in the scratch arrays, so
-// the list is built over the view of p with state and scratch arrays
-// exchanged (positions read from the sorted copy), and every home atom's
-// data is copied from there into the state arrays (each atom is the home
-// atom of exactly one tile; no tile reads another's home data from the
-// state arrays during the build).
-__device__ __forceinline__ KParams scratch_view(const KParams& p)
-{
-    KParams q = p;
-    q.x = p.sx; q.sx = p.x;
-    q.y = p.sy; q.sy = p.y;
-    q.z = p.sz; q.sz = p.z;
-    q.vx = p.svx; q.svx = p.vx;
-    q.vy = p.svy; q.svy = p.vy;
-    q.vz = p.svz; q.svz = p.vz;
-    // the force scratch arrays are typed double but hold the force type
-    q.fx = p.sfx; q.sfx = static_cast<double*>(p.fx);
-    q.fy = p.sfy; q.sfy = static_cast<double*>(p.fy);
-    q.fz = p.sfz; q.sfz = static_cast<double*>(p.fz);
-    q.id = p.sid; q.sid = p.id;
-    q.cell_of = p.scell; q.scell = p.cell_of;
-    return q;
-}
-
-// Home atom at slot k, over scratch_view: its sorted data into the state.
-template <bool kCopy>
-__device__ __forceinline__ void copy_home(const KParams& q, int k)
-{
-    if (!kCopy) return;
-    q.sx[k] = q.x[k];
-    q.sy[k] = q.y[k];
-    q.sz[k] = q.z[k];
-    q.svx[k] = q.vx[k];
-    q.svy[k] = q.vy[k];
-    q.svz[k] = q.vz[k];
-    if (q.precision == MD_FP64) {
-        q.sfx[k] = static_cast<const double*>(q.fx)[k];
-        q.sfy[k] = static_cast<const double*>(q.fy)[k];
-        q.sfz[k] = static_cast<const double*>(q.fz)[k];
-    } else {
-        reinterpret_cast<float*>(q.sfx)[k] = static_cast<const float*>(q.fx)[k];
-        reinterpret_cast<float*>(q.sfy)[k] = static_cast<const float*>(q.fy)[k];
-        reinterpret_cast<float*>(q.sfz)[k] = static_cast<const float*>(q.fz)[k];
-    }
-    q.sid[k] = q.id[k];
-    q.scell[k] = q.cell_of[k];
-    q.order[k] = k;
-}
-
-// One home cell hc of the tile, by one wave.  The candidates (the 9 windows
-// of three cells next to it, concatenated, in canonical order)
-// are taken kNlRounds x 64 at a time: lane l holds candidate k0 + 64 r + l
-// (position, wrap bits, encoded entry) in registers.  Each home atom hh in
-// turn is broadcast from lane hh (readlane) and tested against the block;
-// for round r the hit ballot places the hits: a hit lane's entry goes to
-// list position m_hh + (hits of lower lanes), m_hh being hh's running list
-// length, kept in a scalar register while hh is tested and in lane hh of a
-// vector register between blocks.  Lanes past the candidates read the home
-// cell's first atom (e = hb) and never hit.
 // Staged cell of column a - 1 in the row (dz, dy) = (sg / 3 - 1, sg % 3 - 1)
 // next to home cell home_t (at column a): the first cell of window sg.
 __device__ __forceinline__ int window_cell(const Stage& s, int home_t, int sg)
