@@ -718,12 +718,22 @@ static md_status step_launches(md_ctx* c, hipStream_t s, bool first, int32_t n,
     const bool cells = tiled && !nl;
     const int cflags = fold | (cells ? kFoldBin | kSortSmallOk : 0);
     const int fflags = cells ? fold : 0;
+    // a small cells-only system finishes the integration pass inside its one
+    // cell-sort workgroup (one launch less)
+    const bool small = cells && k.n <= kSortSmall && !k.bonded_on;
+    auto finish_and_cells = [&](int phase) {
+        if (small) {
+            launch_sort_small_finish(k, phase, record_every, s);
+        } else {
+            launch_integrate_finish(k, phase, record_every, s);
+            cells_any(k, cflags, s);
+        }
+    };
     if (s != c->stream) {  // captured into a graph: never timed, never reordered
         for (int32_t i = 0; i < n; ++i) {
             const int phase = first && i == 0 ? 0 : 1;
             launch_integrate_pass(k, phase, record_every, s, cells);
-            launch_integrate_finish(k, phase, record_every, s);
-            cells_any(k, cflags, s);
+            finish_and_cells(phase);
             if (nl) neighbors_any(k, fold, s);
             forces_any(k, s, fflags);
         }
@@ -733,10 +743,14 @@ static md_status step_launches(md_ctx* c, hipStream_t s, bool first, int32_t n,
         const int phase = first && i == 0 ? 0 : 1;
         timed(c, MD_PART_INTEGRATE,
               [&] { launch_integrate_pass(k, phase, record_every, s, cells); });
-        timed(c, MD_PART_ENERGY, [&] { launch_integrate_finish(k, phase, record_every, s); });
         const bool reorder = layer_reorder_on(c) && (step0 + i + 1) % k.reorder == 0;
-        if (reorder) timed(c, MD_PART_REORDER, [&] { launch_layer_reorder(k, s); });
-        timed(c, MD_PART_CELLS, [&] { cells_any(k, reorder ? 1 : cflags, s); });
+        if (small) {  // the finish and the cell build in one launch (counted as cells)
+            timed(c, MD_PART_CELLS, [&] { finish_and_cells(phase); });
+        } else {
+            timed(c, MD_PART_ENERGY, [&] { launch_integrate_finish(k, phase, record_every, s); });
+            if (reorder) timed(c, MD_PART_REORDER, [&] { launch_layer_reorder(k, s); });
+            timed(c, MD_PART_CELLS, [&] { cells_any(k, reorder ? 1 : cflags, s); });
+        }
         if (nl) timed(c, MD_PART_NEIGHBORS, [&] { neighbors_any(k, reorder ? 1 : fold, s); });
         timed_forces(c, fflags);
         if (c->timing && c->ev_pending.size() >= 8192) {

@@ -19,7 +19,7 @@
 // forces the build), so a step's launch sequence is fixed.  Each kernel is a
 // template over where its parameters come from (one system, or one replica
 // of a batch: md_internal.h).
-#include "md_device.h"
+#include "md_finish.h"
 
 namespace md {
 
@@ -243,14 +243,23 @@ __global__ void k_cellsort(B b, int force)
 // Small systems (at most kSortSmall atoms): the scan, the scatter and the
 // in-cell sort by one workgroup, one launch instead of three (their
 // barriers order the global writes of one phase before the reads of the
-// next inside the workgroup).
-template <typename F, class B, bool kPermute>
-__global__ __launch_bounds__(kScanThreads) void k_sort_small(B b, int force)
+// next inside the workgroup).  kFinish (cells-only steps, which rebuild
+// every step): the workgroup first finishes the integration pass before it
+// (finish_step), in place of k_int_finish.
+template <typename F, class B, bool kPermute, bool kFinish>
+__global__ __launch_bounds__(kScanThreads) void k_sort_small(B b, int force, int phase,
+                                                             int record_every)
 {
     Wg wg;
     KParams p;
     if (!b.fetch(G_ONE, wg, p)) return;
-    if (!rebuild_on(p, force)) return;
+    if (kFinish) {
+        __shared__ double red[(kScanThreads / kWave) * 5];
+        finish_step(p, phase, record_every, red);
+        __syncthreads();
+    } else if (!rebuild_on(p, force)) {
+        return;
+    }
     __shared__ int wsum[kScanThreads / kWave];
     scan_cells(p, wsum);
     __syncthreads();
@@ -298,11 +307,14 @@ static void cells_seq(const B& b, const LaunchShape& sh, int flags, hipStream_t 
     if (n_small) {  // one system of at most kSortSmall atoms
         const dim3 one(1), t(kScanThreads);
         if (!sh.reorder)
-            hipLaunchKernelGGL((k_sort_small<double, B, false>), one, t, 0, s, b, force);
+            hipLaunchKernelGGL((k_sort_small<double, B, false, false>), one, t, 0, s, b, force,
+                               0, 0);
         else if (sh.precision == MD_FP64)
-            hipLaunchKernelGGL((k_sort_small<double, B, true>), one, t, 0, s, b, force);
+            hipLaunchKernelGGL((k_sort_small<double, B, true, false>), one, t, 0, s, b, force, 0,
+                               0);
         else
-            hipLaunchKernelGGL((k_sort_small<float, B, true>), one, t, 0, s, b, force);
+            hipLaunchKernelGGL((k_sort_small<float, B, true, false>), one, t, 0, s, b, force, 0,
+                               0);
     } else {
         hipLaunchKernelGGL(k_scan<B>, dim3(sh.grid[G_ONE]), dim3(kScanThreads), 0, s, b, force);
         hipLaunchKernelGGL(k_scatter<B>, atoms, blk, 0, s, b, force);
@@ -334,6 +346,23 @@ void launch_cells(const KParams& p, int force, hipStream_t s)
 void launch_cell_scan(const KParams& p, hipStream_t s)
 {
     hipLaunchKernelGGL(k_scan<Single>, dim3(1), dim3(kScanThreads), 0, s, Single{p}, 1);
+}
+
+// The cells-only step's cell build of a small system (atoms binned by the
+// integration pass) with the finish of that pass in front (see k_sort_small).
+void launch_sort_small_finish(const KParams& p, int phase, int record_every, hipStream_t s)
+{
+    const dim3 one(1), t(kScanThreads);
+    const Single b{p};
+    if (!p.reorder)
+        hipLaunchKernelGGL((k_sort_small<double, Single, false, true>), one, t, 0, s, b, 1, phase,
+                           record_every);
+    else if (p.precision == MD_FP64)
+        hipLaunchKernelGGL((k_sort_small<double, Single, true, true>), one, t, 0, s, b, 1, phase,
+                           record_every);
+    else
+        hipLaunchKernelGGL((k_sort_small<float, Single, true, true>), one, t, 0, s, b, 1, phase,
+                           record_every);
 }
 
 void launch_clear(const Batch& b, const LaunchShape& sh, hipStream_t s) { clear_seq(b, sh, s); }

@@ -20,77 +20,9 @@
 // cost every workgroup an agent-scope release, which on this GPU writes
 // back its XCD's L2 and measured several microseconds per launch, more
 // than the extra launch.
-#include "md_device.h"
+#include "md_finish.h"
 
 namespace md {
-
-// Sum partials [nb][stride] (component k) over workgroups in a fixed order,
-// by one workgroup (k_int_finish, or the last one of k_observe, see
-// last_block), reading the partials with coherent loads.
-__device__ double finish_sum(const double* part, int nb, int stride, int k, double* red)
-{
-    double v[1] = {0.0};
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) v[0] += load_coherent(part + b * stride + k);
-    block_sum<1>(v, red);
-    return v[0];
-}
-
-__device__ double finish_max(const double* part, int nb, int stride, int k, double* red)
-{
-    double m = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        double t = load_coherent(part + b * stride + k);
-        m = t > m ? t : m;
-    }
-    m = wave_max(m);
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    __syncthreads();
-    if (lane == 0) red[wid] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < (int)blockDim.x / kWave; ++w) t = red[w] > t ? red[w] : t;
-        m = t;
-    }
-    __syncthreads();
-    return m;
-}
-
-// Finish a completed step: count it, and on steps the history asks for, sum
-// U, W (last force pass) and K, P (this kernel's n_wg partials) and append
-// them.
-__device__ void record_step(const KParams& p, int n_wg, int record_every, double* red)
-{
-    DevState* dd = p.dev;
-    const int64_t step = dd->step + 1;
-    __syncthreads();
-    if (threadIdx.x == 0) dd->step = step;
-    if (!(record_every > 0 && step % record_every == 0)) return;
-    double U = finish_sum(p.fpart, p.nblk_force, 2, 0, red);
-    double W = finish_sum(p.fpart, p.nblk_force, 2, 1, red);
-    if (p.bonded_on) {
-        U += finish_sum(p.bpart, p.nblk_bonded, 2, 0, red);
-        W += finish_sum(p.bpart, p.nblk_bonded, 2, 1, red);
-    }
-    const double K = finish_sum(p.ipart, n_wg, 8, 0, red);
-    const double Px = finish_sum(p.ipart, n_wg, 8, 1, red);
-    const double Py = finish_sum(p.ipart, n_wg, 8, 2, red);
-    const double Pz = finish_sum(p.ipart, n_wg, 8, 3, red);
-    if (threadIdx.x == 0) {
-        md_record* r = p.hist + (dd->hist_count % kHistCap);
-        r->step = step;
-        r->U = U;
-        r->K = 0.5 * p.mass * K;
-        r->W = W;
-        r->P[0] = p.mass * Px;
-        r->P[1] = p.mass * Py;
-        r->P[2] = p.mass * Pz;
-        r->dmax = sqrt(dd->dmax2);
-        r->rebuilt = dd->rebuild;
-        r->pad = 0;
-        dd->hist_count += 1;
-    }
-}
 
 // kBin (cells-only steps, which rebuild the cells every step): the drift also
 // folds the positions into [0, L) and bins them (cell and slot, as k_bin), so
@@ -192,10 +124,7 @@ __global__ __launch_bounds__(kIntThreads) void k_integrate(B b, int phase, int r
     }
 }
 
-// The end of an integration pass (one workgroup per system): count the
-// step and record it (phase >= 1), and from the largest displacement decide
-// whether the cells and list are rebuilt before the next force pass
-// (phase <= 1).
+// The end of an integration pass (one workgroup per system, see finish_step).
 template <class B>
 __global__ __launch_bounds__(kFinishThreads) void k_int_finish(B b, int phase, int record_every)
 {
@@ -203,18 +132,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_int_finish(B b, int phase, i
     KParams p;
     if (!b.fetch(G_ONE, wg, p)) return;
     __shared__ double red[(kFinishThreads / kWave) * 5];
-    const int n_wg = grid_of(p, G_INTEGRATE);
-    if (phase >= 1) record_step(p, n_wg, record_every, red);
-    if (phase <= 1) {
-        const double m = finish_max(p.ipart, n_wg, 8, 4, red);
-        if (threadIdx.x == 0) {
-            DevState* d = p.dev;
-            d->dmax2 = m;
-            const int rb = p.mode == MD_CELLS_ONLY ? 1 : (m > p.disp_thr2 ? 1 : 0);
-            d->rebuild = rb;
-            if (rb) d->n_rebuilds += 1;
-        }
-    }
+    finish_step(p, phase, record_every, red);
 }
 
 // Observables of the current state: K and P from the velocities, U and W
@@ -237,14 +155,14 @@ __global__ __launch_bounds__(kIntThreads) void k_observe(KParams p)
         for (int k = 0; k < 4; ++k) o[k] = acc[k];
     }
     if (!last_block(p.dev, gridDim.x)) return;
-    double U = finish_sum(p.fpart, p.nblk_force, 2, 0, red);
-    double W = finish_sum(p.fpart, p.nblk_force, 2, 1, red);
+    double U = finish_sum<kIntThreads>(p.fpart, p.nblk_force, 2, 0, red);
+    double W = finish_sum<kIntThreads>(p.fpart, p.nblk_force, 2, 1, red);
     if (p.bonded_on) {
-        U += finish_sum(p.bpart, p.nblk_bonded, 2, 0, red);
-        W += finish_sum(p.bpart, p.nblk_bonded, 2, 1, red);
+        U += finish_sum<kIntThreads>(p.bpart, p.nblk_bonded, 2, 0, red);
+        W += finish_sum<kIntThreads>(p.bpart, p.nblk_bonded, 2, 1, red);
     }
     double s[4];
-    for (int k = 0; k < 4; ++k) s[k] = finish_sum(p.ipart, gridDim.x, 8, k, red);
+    for (int k = 0; k < 4; ++k) s[k] = finish_sum<kIntThreads>(p.ipart, gridDim.x, 8, k, red);
     if (threadIdx.x == 0) {
         DevState* d = p.dev;
         d->obs[0] = U;

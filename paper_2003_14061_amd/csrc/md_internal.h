@@ -263,6 +263,7 @@ void launch_layer_forces(const KParams& p, hipStream_t s);
 void launch_layer_export(const KParams& p, int32_t* out, hipStream_t s);
 void launch_layer_reorder(const KParams& p, hipStream_t s);
 void launch_cell_scan(const KParams& p, hipStream_t s);
+void launch_sort_small_finish(const KParams& p, int phase, int record_every, hipStream_t s);
 int allpairs_home_blocks(int n);
 void allpairs_split(int n, int* split, int* chunk);
 void launch_allpairs_forces(const KParams& p, hipStream_t s);
