@@ -470,11 +470,10 @@ def run_batch(steps=500, warmup=20, tune_cache=None, fixed_tuning=None):
                for w in reps]
     n_tot = sum(w.n for w in reps)
     b = md.Batch(systems, precision="fp32")
-    shapes = [{}, dict(tile_cells=4, tile_y=4, tile_z=4), dict(tile_cells=4, tile_y=2, tile_z=2),
-              dict(tile_cells=8, tile_y=2, tile_z=2), dict(tile_cells=8, tile_y=4, tile_z=4),
-              dict(tile_cells=6, tile_y=6, tile_z=6)]
-    cands = [dict(force_lanes=l, force_block=fb, **t) for t in shapes for l in (1, 2, 4)
-             for fb in (256, 512)]
+    shapes = [{}] + [dict(tile_cells=x, tile_y=y, tile_z=z) for x, y, z in (
+        (4, 4, 4), (5, 5, 5), (5, 5, 4), (6, 6, 6), (8, 4, 4), (4, 4, 2), (8, 2, 2))]
+    cands = [dict(force_lanes=l, force_block=fb, **t) for t in shapes for l in (1, 2)
+             for fb in (128, 192, 256, 320, 512)]
     if fixed_tuning:  # a given shape instead of the autotuner (profiling runs)
         cands, best, costs = [fixed_tuning], 0, [-1.0]
         b.set_tuning(**fixed_tuning)
