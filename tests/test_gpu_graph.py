@@ -34,6 +34,10 @@ def run(graph, steps, record_every, stream=None, tuning=None, **kw):
 CASES = {
     "lj_list": dict(n=32000, rho=0.8442, r_cut=2.5, skin=0.3, dt=0.004),
     "wca_cells": dict(n=4000, rho=0.8, r_cut=WCA, dt=0.005, neighbor_list=False),
+    "wca_cells_reorder": dict(n=4000, rho=0.8, r_cut=WCA, dt=0.005, neighbor_list=False,
+                              reorder=True),
+    "wca_cells_20000": dict(n=20000, rho=0.8, r_cut=WCA, dt=0.005, neighbor_list=False,
+                            reorder=True),
     "lj_list_fp32": dict(n=13500, rho=0.8, r_cut=2.5, skin=0.3, dt=0.004, precision="fp32"),
 }
 

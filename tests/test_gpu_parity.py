@@ -42,6 +42,11 @@ CASES = {
     "wca6000_block64": (6000, 0.8, WCA, 0.1, True, True, {"block": 64}),
     "lj9000_block1024": (9000, 0.7, 2.5, 0.1, True, True, {"block": 1024}),
     "wca5000_cells_block128": (5000, 0.6, WCA, 0.0, False, False, {"block": 128}),
+    # cells only with the slots reordered: in a step the force pass copies the
+    # sorted data back; above 16384 atoms the sort runs over the whole grid
+    "wca4000_cells_reorder": (4000, 0.8, WCA, 0.06, True, False, {"reorder": True}),
+    "wca20000_cells_reorder": (20000, 0.8, WCA, 0.05, True, False, {"reorder": True}),
+    "wca20000_cells": (20000, 0.8, WCA, 0.05, True, False, {}),
 }
 
 
@@ -110,7 +115,8 @@ def _compare_run(name, steps, precision="fp64", seed=23):
 
 
 @pytest.mark.parametrize("name", ["wca13500_nl_run", "lj32000_nl", "wca4000_cells",
-                                  "lj4000_noreorder", "wca108_nc3"])
+                                  "lj4000_noreorder", "wca108_nc3", "wca4000_cells_reorder",
+                                  "wca20000_cells_reorder", "wca20000_cells"])
 def test_short_run_fp64(name):
     steps = 40
     sim, s, hist, obs, st, (p_ref, v_ref, f_ref, o_ref, nreb) = _compare_run(name, steps)
@@ -129,7 +135,8 @@ def test_short_run_fp64(name):
         assert np.allclose(hist["dmax"], np.sqrt(o_ref["dmax2"]), rtol=1e-9, atol=1e-12)
 
 
-@pytest.mark.parametrize("name", ["wca13500_nl_run", "lj32000_nl", "wca4000_cells"])
+@pytest.mark.parametrize("name", ["wca13500_nl_run", "lj32000_nl", "wca4000_cells",
+                                  "wca4000_cells_reorder", "wca20000_cells_reorder"])
 def test_short_run_fp32_mixed(name):
     steps = 40
     sim, s, hist, obs, st, (p_ref, v_ref, f_ref, o_ref, nreb) = _compare_run(name, steps, "fp32")
