@@ -125,6 +125,22 @@ __device__ __forceinline__ T wave_max(T v)
     return v;
 }
 
+// The maximum of v over the workgroup, valid in thread 0 (0 elsewhere).  Every
+// thread of the workgroup calls it.  Kernels fold a per-thread maximum into a
+// device-wide one with this and a single global atomic per workgroup: atomics
+// from every wave on one word serialize in L2 (one per wave of a 2 M-atom list
+// build cost about a millisecond).
+__device__ __forceinline__ int workgroup_max(int v)
+{
+    __shared__ int m;
+    if (threadIdx.x == 0) m = 0;
+    __syncthreads();
+    v = wave_max(v);
+    if ((threadIdx.x & (kWave - 1)) == 0 && v > 0) atomicMax(&m, v);
+    __syncthreads();
+    return threadIdx.x == 0 ? m : 0;
+}
+
 // Sum K values across the workgroup; the result is valid in thread 0.
 // red must hold (blockDim.x / 64) * K doubles of LDS.
 template <int K>

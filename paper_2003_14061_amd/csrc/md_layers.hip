@@ -62,8 +62,8 @@ __global__ void k_layer_assign(KParams p, int force)
             atomicOr(&p.dev->flags, (int)MD_FLAG_LAYER_OVERFLOW);
         occ = l + 1 > occ ? l + 1 : occ;
     }
-    occ = wave_max(occ);
-    if ((threadIdx.x & (kWave - 1)) == 0 && occ > 0) atomicMax(&p.dev->max_occ, occ);
+    occ = workgroup_max(occ);
+    if (threadIdx.x == 0 && occ > 0) atomicMax(&p.dev->max_occ, occ);
 }
 
 // N5: the neighbor matrix, and the displacement references.
@@ -105,8 +105,8 @@ __global__ void k_layer_nl(KParams p, int force)
         p.zr[i] = zi;
         longest = m > longest ? m : longest;
     }
-    longest = wave_max(longest);
-    if ((threadIdx.x & (kWave - 1)) == 0 && longest > 0) {
+    longest = workgroup_max(longest);
+    if (threadIdx.x == 0 && longest > 0) {
         atomicMax(&p.dev->max_nl, longest);
         if (longest > p.cap) atomicOr(&p.dev->flags, (int)MD_FLAG_NL_OVERFLOW);
     }

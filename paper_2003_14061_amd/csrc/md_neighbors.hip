@@ -58,8 +58,10 @@ __device__ __forceinline__ int home_cell(const Stage& s, int hc)
     return home_row_cell(s, r) + (a - 1);
 }
 
+// The lists of home cell hc's atoms; wmax: the longest list of this lane's
+// home atoms so far.
 template <int kImage, bool kHalf, bool kFits, bool kSmall, bool kCopy>
-__device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, int hc)
+__device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, int hc, int& wmax)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int home_t = home_cell(s, hc);
@@ -77,6 +79,13 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
     const uint32_t cap = (uint32_t)p.cap;  // a multiple of 4
     uint16_t* nl16 = reinterpret_cast<uint16_t*>(p.nl64);
     const uint32_t npad4 = 4u * (uint32_t)p.npad;  // 16-bit entries per chunk row
+    // kSmall (the list within 32-bit byte offsets, rows within 24-bit products):
+    // hits go out as buffer stores, the list's base in a resource, the home
+    // atom's chunk column as the scalar offset and row and column of the entry
+    // as the 32-bit lane offset (no 64-bit address arithmetic per hit)
+    const uint32_t rowb = 8u * (uint32_t)p.npad;
+    __amdgpu_buffer_rsrc_t rsrc;
+    if (kSmall) rsrc = __builtin_amdgcn_make_buffer_rsrc(p.nl64, 0, -1, kBufferWord3);
     for (int h0 = hb; h0 < he; h0 += kWave) {
         const int nhs = he - h0 < kWave ? he - h0 : kWave;
         const bool home_lane = lane < nhs;
@@ -92,7 +101,6 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
         }
         int mreg = 0;  // lane hh: home atom hh's list length so far
         for (int k0 = 0; k0 < ncand; k0 += kNlRounds * kWave) {
-            const int nr = (ncand - k0 + kWave - 1) / kWave;  // rounds with candidates
             double cx[kNlRounds], cy[kNlRounds], cz[kNlRounds];
             int ce[kNlRounds], cfl[kNlRounds], cpos[kNlRounds];
             uint16_t cenc[kNlRounds];
@@ -158,13 +166,17 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
                         uint32_t m = __builtin_amdgcn_mbcnt_hi(
                             (uint32_t)(mk[r] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk[r], m_h));
                         m = m < cap ? m : cap;
-                        const uint32_t col = (m & 3u) | slot4;
                         if (kSmall) {
-                            uint32_t idx = __umul24(m >> 2, npad4) + col;
-                            asm volatile("" : "+v"(idx));  // keep the 32-bit index
-                            nl16[idx] = cenc[r];
+                            // row (m >> 2) of rowb bytes, entry m & 3 of the chunk:
+                            // 2 m + (m >> 2) (rowb - 8), one 24-bit multiply-add
+                            uint32_t off;
+                            asm("v_mad_u32_u24 %0, %1, %2, %3"
+                                : "=v"(off)
+                                : "v"(m >> 2), "s"(rowb - 8u), "v"(2u * m));
+                            __builtin_amdgcn_raw_buffer_store_b16(cenc[r], rsrc, (int)off,
+                                                                  (int)(2u * slot4), 0);
                         } else {
-                            nl16[(size_t)(m >> 2) * npad4 + col] = cenc[r];
+                            nl16[(size_t)(m >> 2) * npad4 + ((m & 3u) | slot4)] = cenc[r];
                         }
                     }
                     m_h += (uint32_t)__popcll(mk[r]);
@@ -184,11 +196,7 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
             p.zr[slot_l] = hz;
             copy_home<kCopy>(p, slot_l);
         }
-        const int mmax = wave_max(home_lane ? mreg : 0);
-        if (lane == 0 && mmax > 0) {
-            atomicMax(&p.dev->max_nl, mmax);
-            if (mmax > p.cap) atomicOr(&p.dev->flags, (int)MD_FLAG_NL_OVERFLOW);
-        }
+        wmax = home_lane && mreg > wmax ? mreg : wmax;
     }
 }
 
@@ -283,24 +291,19 @@ __device__ __forceinline__ int nl_home_atom(const KParams& p, const Stage& s, in
 }
 
 template <int kImage, bool kFits, bool kHalf, bool kCopy>
-__device__ __forceinline__ void nl_lanes(const KParams& p, const Stage& s)
+__device__ __forceinline__ void nl_lanes(const KParams& p, const Stage& s, int& wmax)
 {
     const int nh = home_count(s);
-    int mmax = 0;
     for (int h = threadIdx.x; h < nh; h += blockDim.x) {
         const int m = nl_home_atom<kImage, kFits, kHalf, kCopy>(p, s, h);
-        mmax = m > mmax ? m : mmax;
-    }
-    mmax = wave_max(mmax);
-    if ((threadIdx.x & (kWave - 1)) == 0 && mmax > 0) {
-        atomicMax(&p.dev->max_nl, mmax);
-        if (mmax > p.cap) atomicOr(&p.dev->flags, (int)MD_FLAG_NL_OVERFLOW);
+        wmax = m > wmax ? m : wmax;
     }
 }
 
-// One tile's lists (every thread of the workgroup calls it).
+// One tile's lists (every thread of the workgroup calls it); wmax: the longest
+// list this thread has seen (its wave's, in the cell-wave build).
 template <int kMethod, bool kHalf, bool kCopy>
-__device__ __forceinline__ void nl_tile(const KParams& p, int t, char* smem)
+__device__ __forceinline__ void nl_tile(const KParams& p, int t, char* smem, int& wmax)
 {
     const Tile g = tile_of(p, t);
     Stage s = stage_layout(p, smem);
@@ -324,40 +327,42 @@ __device__ __forceinline__ void nl_tile(const KParams& p, int t, char* smem)
     if (kMethod == MD_NL_LANES) {
         if (!s.fits) {
             if (mode == 2)
-                nl_lanes<2, false, kHalf, kCopy>(p, s);
+                nl_lanes<2, false, kHalf, kCopy>(p, s, wmax);
             else
-                nl_lanes<1, false, kHalf, kCopy>(p, s);
+                nl_lanes<1, false, kHalf, kCopy>(p, s, wmax);
         } else if (mode == 0) {
-            nl_lanes<0, true, kHalf, kCopy>(p, s);
+            nl_lanes<0, true, kHalf, kCopy>(p, s, wmax);
         } else if (mode == 1) {
-            nl_lanes<1, true, kHalf, kCopy>(p, s);
+            nl_lanes<1, true, kHalf, kCopy>(p, s, wmax);
         } else {
-            nl_lanes<2, true, kHalf, kCopy>(p, s);
+            nl_lanes<2, true, kHalf, kCopy>(p, s, wmax);
         }
         return;
     }
     const int wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const int ncells = g.kx * g.ky * g.kz;
-    // list rows by 24-bit products while 4 n_pad < 2^24
-    const bool small = 4u * (uint32_t)p.npad < (1u << 24);
+    // list rows by 24-bit products while 8 n_pad < 2^24, the whole list (its
+    // spare row included) within 32-bit byte offsets
+    const bool small = 8u * (uint32_t)p.npad < (1u << 24) &&
+                       (uint64_t)(p.cap / kChunk + 1) * 8u * (uint64_t)p.npad < (1ull << 32);
     for (int hc = wid; hc < ncells; hc += nw) {
         if (!s.fits) {
             if (mode == 2)
-                nl_home_cell<2, kHalf, false, false, kCopy>(p, s, hc);
+                nl_home_cell<2, kHalf, false, false, kCopy>(p, s, hc, wmax);
             else
-                nl_home_cell<1, kHalf, false, false, kCopy>(p, s, hc);
+                nl_home_cell<1, kHalf, false, false, kCopy>(p, s, hc, wmax);
         } else if (mode == 0) {
             if (small)
-                nl_home_cell<0, kHalf, true, true, kCopy>(p, s, hc);
+                nl_home_cell<0, kHalf, true, true, kCopy>(p, s, hc, wmax);
             else
-                nl_home_cell<0, kHalf, true, false, kCopy>(p, s, hc);
+                nl_home_cell<0, kHalf, true, false, kCopy>(p, s, hc, wmax);
         } else if (mode == 1) {
             if (small)
-                nl_home_cell<1, kHalf, true, true, kCopy>(p, s, hc);
+                nl_home_cell<1, kHalf, true, true, kCopy>(p, s, hc, wmax);
             else
-                nl_home_cell<1, kHalf, true, false, kCopy>(p, s, hc);
+                nl_home_cell<1, kHalf, true, false, kCopy>(p, s, hc, wmax);
         } else {
-            nl_home_cell<2, kHalf, true, false, kCopy>(p, s, hc);
+            nl_home_cell<2, kHalf, true, false, kCopy>(p, s, hc, wmax);
         }
     }
 }
@@ -377,9 +382,16 @@ __global__ void k_nl_tiles(B b, int force)
     if (!force && !p.dev->rebuild) return;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const KParams q = kCopy ? scratch_view(p) : p;
+    int wmax = 0;
     for (int v = wg.id; v < q.n_tiles; v += wg.n) {
-        nl_tile<kMethod, kHalf, kCopy>(q, xcd_tile(v, q.n_tiles), smem);
+        nl_tile<kMethod, kHalf, kCopy>(q, xcd_tile(v, q.n_tiles), smem, wmax);
         __syncthreads();  // the next tile reuses the LDS
+    }
+    // the longest list: one global atomic per workgroup
+    const int mmax = workgroup_max(wmax);
+    if (threadIdx.x == 0 && mmax > 0) {
+        atomicMax(&q.dev->max_nl, mmax);
+        if (mmax > q.cap) atomicOr(&q.dev->flags, (int)MD_FLAG_NL_OVERFLOW);
     }
 }
 

@@ -54,6 +54,9 @@ constexpr int kEntryBits = 13;
 constexpr int kEntryMask = (1 << kEntryBits) - 1;
 constexpr int kMaxStaged = 1 << kEntryBits;  // virtual layout limit
 constexpr int kChunk = 4;                    // entries per 8-byte list chunk
+// Fourth word of a raw buffer resource on the gfx9 family (CDNA): 32-bit
+// data, no swizzle, the range check on the byte offset alone.
+constexpr int kBufferWord3 = 0x00020000;
 
 struct Tile {
     int cx0, cy0, cz0, kx, ky, kz;
