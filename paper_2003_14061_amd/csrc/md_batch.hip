@@ -120,6 +120,7 @@ md_status upload(md_batch* b)
     sh.mode = p0.mode;
     sh.newton3 = p0.newton3;
     for (int r = 0; r < R; ++r) {
+        sh.nl_full |= kp[r].nc < 5 || !nl_small(kp[r]);
         const int nlb = kp[r].nl_block;
         sh.nl_block = nlb > sh.nl_block ? nlb : sh.nl_block;
         if (p0.mode == MD_NEIGHBOR_LIST) {

@@ -287,14 +287,4 @@ __device__ __forceinline__ void copy_home(const KParams& q, int k)
     q.order[k] = k;
 }
 
-// One home cell hc of the tile, by one wave.  The candidates (the 9 windows
-// of three cells next to it, concatenated, in canonical order)
-// are taken kNlRounds x 64 at a time: lane l holds candidate k0 + 64 r + l
-// (position, wrap bits, encoded entry) in registers.  Each home atom hh in
-// turn is broadcast from lane hh (readlane) and tested against the block;
-// for round r the hit ballot places the hits: a hit lane's entry goes to
-// list position m_hh + (hits of lower lanes), m_hh being hh's running list
-// length, kept in a scalar register while hh is tested and in lane hh of a
-// vector register between blocks.  Lanes past the candidates read the home
-// cell's first atom (e = hb) and never hit.
 }  // namespace md

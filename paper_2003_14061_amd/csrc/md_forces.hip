@@ -383,6 +383,7 @@ LaunchShape shape_of(const KParams& p)
     sh.reorder = p.reorder;
     sh.mode = p.mode;
     sh.newton3 = p.newton3;
+    sh.nl_full = p.nc < 5 || !nl_small(p);
     return sh;
 }
 

@@ -237,7 +237,19 @@ struct LaunchShape {
     int block, force_block, force_lanes, nl_block, nl_method, newton3;
     size_t nl_lds, force_lds;
     int precision, reorder, mode;
+    // the list build's full kernel: some system has fewer than 5 cells per side
+    // (image mode 2) or a list beyond the buffer stores' reach (nl_small)
+    int nl_full;
 };
+
+// The cell-wave list build stores hits through 32-bit byte offsets, row
+// products in 24 bits: 8 n_pad < 2^24 and the whole list (its spare chunk row
+// included) below 4 GiB.
+__host__ __device__ inline bool nl_small(const KParams& p)
+{
+    return 8ull * (uint64_t)p.npad < (1ull << 24) &&
+           (uint64_t)(p.cap / 4 + 1) * 8ull * (uint64_t)p.npad < (1ull << 32);
+}
 
 LaunchShape shape_of(const KParams& p);
 

@@ -58,10 +58,19 @@ __device__ __forceinline__ int home_cell(const Stage& s, int hc)
     return home_row_cell(s, r) + (a - 1);
 }
 
-// The lists of home cell hc's atoms; wmax: the longest list of this lane's
-// home atoms so far.
-template <int kImage, bool kHalf, bool kFits, bool kSmall, bool kCopy>
-__device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, int hc, int& wmax)
+// The lists of home cell hc's atoms, by one wave; wmax: the longest list of
+// this lane's home atoms so far.  The candidates (the 9 windows of three cells
+// next to it, concatenated, in canonical order) are taken kRounds x 64 at a
+// time: lane l holds candidate k0 + 64 r + l (position, wrap bits, encoded
+// entry) in registers.  Each home atom hh in turn is broadcast from lane hh
+// (readlane) and tested against the block; for round r the hit ballot places
+// the hits: a hit lane's entry goes to list position m_hh + (hits of lower
+// lanes), m_hh being hh's running list length, kept in a scalar register while
+// hh is tested and in lane hh of a vector register between blocks.  Lanes past
+// the candidates read the home cell's first atom (e = hb) and never hit.
+template <int kImage, bool kHalf, bool kFits, bool kCopy, int kRounds, bool kFull>
+__device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, int hc, bool small,
+                                             int& wmax)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int home_t = home_cell(s, hc);
@@ -79,13 +88,15 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
     const uint32_t cap = (uint32_t)p.cap;  // a multiple of 4
     uint16_t* nl16 = reinterpret_cast<uint16_t*>(p.nl64);
     const uint32_t npad4 = 4u * (uint32_t)p.npad;  // 16-bit entries per chunk row
-    // kSmall (the list within 32-bit byte offsets, rows within 24-bit products):
-    // hits go out as buffer stores, the list's base in a resource, the home
-    // atom's chunk column as the scalar offset and row and column of the entry
-    // as the 32-bit lane offset (no 64-bit address arithmetic per hit)
+    // small (the list within 32-bit byte offsets, rows within 24-bit products,
+    // always so without kFull): hits go out as buffer stores, the list's base
+    // in a resource, the home atom's chunk column as the scalar offset and row
+    // and column of the entry as the 32-bit lane offset (no 64-bit address
+    // arithmetic per hit).  With kFull the choice is a uniform branch at the
+    // store (a second copy of the loop would raise the register count).
     const uint32_t rowb = 8u * (uint32_t)p.npad;
-    __amdgpu_buffer_rsrc_t rsrc;
-    if (kSmall) rsrc = __builtin_amdgcn_make_buffer_rsrc(p.nl64, 0, -1, kBufferWord3);
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(p.nl64, 0, -1, kBufferWord3);
     for (int h0 = hb; h0 < he; h0 += kWave) {
         const int nhs = he - h0 < kWave ? he - h0 : kWave;
         const bool home_lane = lane < nhs;
@@ -100,12 +111,12 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
             hz = p.z[slot_l];
         }
         int mreg = 0;  // lane hh: home atom hh's list length so far
-        for (int k0 = 0; k0 < ncand; k0 += kNlRounds * kWave) {
-            double cx[kNlRounds], cy[kNlRounds], cz[kNlRounds];
-            int ce[kNlRounds], cfl[kNlRounds], cpos[kNlRounds];
-            uint16_t cenc[kNlRounds];
+        for (int k0 = 0; k0 < ncand; k0 += kRounds * kWave) {
+            double cx[kRounds], cy[kRounds], cz[kRounds];
+            int ce[kRounds], cfl[kRounds], cpos[kRounds];
+            uint16_t cenc[kRounds];
 #pragma unroll
-            for (int r = 0; r < kNlRounds; ++r) {
+            for (int r = 0; r < kRounds; ++r) {
                 const int k = k0 + r * kWave + lane;
                 const bool valid = k < ncand;
                 int sg = 0, pre = 0;
@@ -142,10 +153,10 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
                 const uint32_t slot4 = 4u * (uint32_t)__builtin_amdgcn_readlane(slot_l, hh);
                 uint32_t m_h = (uint32_t)__builtin_amdgcn_readlane(mreg, hh);
                 // the tests of all rounds first (independent), then the stores
-                bool hit[kNlRounds];
-                uint64_t mk[kNlRounds];
+                bool hit[kRounds];
+                uint64_t mk[kRounds];
 #pragma unroll
-                for (int r = 0; r < kNlRounds; ++r) {
+                for (int r = 0; r < kRounds; ++r) {
                     double dx = xi - cx[r], dy = yi - cy[r], dz = zi - cz[r];
                     image<kImage>(p, cfl[r], dx, dy, dz);
                     // each condition balloted on its own (the compare results are
@@ -159,14 +170,14 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
                     hit[r] = near & other & later;
                 }
 #pragma unroll
-                for (int r = 0; r < kNlRounds; ++r) {
+                for (int r = 0; r < kRounds; ++r) {
                     if (hit[r]) {
                         // position m_h plus the hits of lower lanes; past the
                         // capacity into the spare chunk row (counted, not kept)
                         uint32_t m = __builtin_amdgcn_mbcnt_hi(
                             (uint32_t)(mk[r] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk[r], m_h));
                         m = m < cap ? m : cap;
-                        if (kSmall) {
+                        if (!kFull || small) {
                             // row (m >> 2) of rowb bytes, entry m & 3 of the chunk:
                             // 2 m + (m >> 2) (rowb - 8), one 24-bit multiply-add
                             uint32_t off;
@@ -198,6 +209,15 @@ __device__ __forceinline__ void nl_home_cell(const KParams& p, const Stage& s, i
         }
         wmax = home_lane && mreg > wmax ? mreg : wmax;
     }
+}
+
+// True when home cell hc (0 .. kx ky kz - 1, x fastest) of tile g lies on a
+// periodic boundary: some of its 26 neighbor cells wrap.
+__device__ __forceinline__ bool home_wraps(const KParams& p, const Tile& g, int hc)
+{
+    const int a = hc % g.kx, r = hc / g.kx, b = r % g.ky, c = r / g.ky;
+    const int xx = g.cx0 + a, yy = g.cy0 + b, zz = g.cz0 + c, e = p.nc - 1;
+    return xx == 0 || xx == e || yy == 0 || yy == e || zz == 0 || zz == e;
 }
 
 // Home cell of row cell t1 (column 1 of its home row) holding staged entry e.
@@ -301,8 +321,12 @@ __device__ __forceinline__ void nl_lanes(const KParams& p, const Stage& s, int& 
 }
 
 // One tile's lists (every thread of the workgroup calls it); wmax: the longest
-// list this thread has seen (its wave's, in the cell-wave build).
-template <int kMethod, bool kHalf, bool kCopy>
+// list this thread has seen (its wave's, in the cell-wave build).  kFull: the
+// image rule of grids under 5 cells per side (mode 2) and list stores beyond
+// 32-bit offsets are compiled in; a kernel without them serves only grids of 5
+// cells per side or more whose lists fit the buffer stores, and holds fewer
+// registers.
+template <int kMethod, bool kHalf, bool kCopy, bool kFull>
 __device__ __forceinline__ void nl_tile(const KParams& p, int t, char* smem, int& wmax)
 {
     const Tile g = tile_of(p, t);
@@ -325,44 +349,42 @@ __device__ __forceinline__ void nl_tile(const KParams& p, int t, char* smem, int
     __syncthreads();
     const int mode = image_mode(p, tile_interior(p, g));
     if (kMethod == MD_NL_LANES) {
-        if (!s.fits) {
-            if (mode == 2)
-                nl_lanes<2, false, kHalf, kCopy>(p, s, wmax);
+        if (kFull && mode == 2) {
+            if (s.fits)
+                nl_lanes<2, true, kHalf, kCopy>(p, s, wmax);
             else
-                nl_lanes<1, false, kHalf, kCopy>(p, s, wmax);
+                nl_lanes<2, false, kHalf, kCopy>(p, s, wmax);
+        } else if (!s.fits) {
+            nl_lanes<1, false, kHalf, kCopy>(p, s, wmax);
         } else if (mode == 0) {
             nl_lanes<0, true, kHalf, kCopy>(p, s, wmax);
-        } else if (mode == 1) {
-            nl_lanes<1, true, kHalf, kCopy>(p, s, wmax);
         } else {
-            nl_lanes<2, true, kHalf, kCopy>(p, s, wmax);
+            nl_lanes<1, true, kHalf, kCopy>(p, s, wmax);
         }
         return;
     }
     const int wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const int ncells = g.kx * g.ky * g.kz;
-    // list rows by 24-bit products while 8 n_pad < 2^24, the whole list (its
-    // spare row included) within 32-bit byte offsets
-    const bool small = 8u * (uint32_t)p.npad < (1u << 24) &&
-                       (uint64_t)(p.cap / kChunk + 1) * 8u * (uint64_t)p.npad < (1ull << 32);
+    const bool small = nl_small(p);
+    // Home cells next to a periodic boundary (real index 0 or nc - 1 on some
+    // axis) have wrapped candidates and take the image rule, one round of 64
+    // candidates at a time, as do the rare tiles that do not fit in LDS or
+    // grids under 5 cells per side: those paths then hold fewer registers than
+    // the common one (the kernel's register count is that of its largest path),
+    // which keeps six waves per SIMD.  The other home cells of a boundary tile
+    // have no wrapped candidate and take the interior path.
     for (int hc = wid; hc < ncells; hc += nw) {
-        if (!s.fits) {
-            if (mode == 2)
-                nl_home_cell<2, kHalf, false, false, kCopy>(p, s, hc, wmax);
+        if (kFull && mode == 2) {
+            if (s.fits)
+                nl_home_cell<2, kHalf, true, kCopy, 1, kFull>(p, s, hc, small, wmax);
             else
-                nl_home_cell<1, kHalf, false, false, kCopy>(p, s, hc, wmax);
-        } else if (mode == 0) {
-            if (small)
-                nl_home_cell<0, kHalf, true, true, kCopy>(p, s, hc, wmax);
-            else
-                nl_home_cell<0, kHalf, true, false, kCopy>(p, s, hc, wmax);
-        } else if (mode == 1) {
-            if (small)
-                nl_home_cell<1, kHalf, true, true, kCopy>(p, s, hc, wmax);
-            else
-                nl_home_cell<1, kHalf, true, false, kCopy>(p, s, hc, wmax);
+                nl_home_cell<2, kHalf, false, kCopy, 1, kFull>(p, s, hc, small, wmax);
+        } else if (!s.fits) {
+            nl_home_cell<1, kHalf, false, kCopy, 1, kFull>(p, s, hc, small, wmax);
+        } else if (mode == 0 || !home_wraps(p, g, hc)) {
+            nl_home_cell<0, kHalf, true, kCopy, kNlRounds, kFull>(p, s, hc, small, wmax);
         } else {
-            nl_home_cell<2, kHalf, true, false, kCopy>(p, s, hc, wmax);
+            nl_home_cell<1, kHalf, true, kCopy, kNlRounds, kFull>(p, s, hc, small, wmax);
         }
     }
 }
@@ -373,8 +395,10 @@ __device__ __forceinline__ void nl_tile(const KParams& p, int t, char* smem, int
 // from the uneven tile counts of the last wave of workgroups); tile v keeps
 // the XCD-aware order (v mod 8 is the workgroup's XCD when n is a multiple
 // of 8).
-template <class B, int kMethod, bool kHalf, bool kCopy>
-__global__ void k_nl_tiles(B b, int force)
+// At most 80 VGPRs: six waves per SIMD, which the LDS of the dense LJ tiles
+// (three workgroups of eight waves per CU) allows.
+template <class B, int kMethod, bool kHalf, bool kCopy, bool kFull>
+__global__ __attribute__((amdgpu_waves_per_eu(6))) void k_nl_tiles(B b, int force)
 {
     Wg wg;
     KParams p;
@@ -384,7 +408,7 @@ __global__ void k_nl_tiles(B b, int force)
     const KParams q = kCopy ? scratch_view(p) : p;
     int wmax = 0;
     for (int v = wg.id; v < q.n_tiles; v += wg.n) {
-        nl_tile<kMethod, kHalf, kCopy>(q, xcd_tile(v, q.n_tiles), smem, wmax);
+        nl_tile<kMethod, kHalf, kCopy, kFull>(q, xcd_tile(v, q.n_tiles), smem, wmax);
         __syncthreads();  // the next tile reuses the LDS
     }
     // the longest list: one global atomic per workgroup
@@ -420,16 +444,25 @@ __global__ void k_nl_export(KParams p, int32_t* out)
     }
 }
 
-template <class B, bool kHalf, bool kCopy>
+template <class B, bool kHalf, bool kCopy, bool kFull>
 static void neighbors_seq(const B& b, const LaunchShape& sh, int force, hipStream_t s)
 {
     const dim3 g(sh.grid[G_NL]), t(sh.nl_block);
     if (sh.nl_method == MD_NL_CELL_WAVES)
-        hipLaunchKernelGGL((k_nl_tiles<B, MD_NL_CELL_WAVES, kHalf, kCopy>), g, t, sh.nl_lds, s,
-                           b, force);
+        hipLaunchKernelGGL((k_nl_tiles<B, MD_NL_CELL_WAVES, kHalf, kCopy, kFull>), g, t, sh.nl_lds,
+                           s, b, force);
     else
-        hipLaunchKernelGGL((k_nl_tiles<B, MD_NL_LANES, kHalf, kCopy>), g, t, sh.nl_lds, s, b,
-                           force);
+        hipLaunchKernelGGL((k_nl_tiles<B, MD_NL_LANES, kHalf, kCopy, kFull>), g, t, sh.nl_lds, s,
+                           b, force);
+}
+
+template <class B, bool kHalf, bool kCopy>
+static void neighbors_seq(const B& b, const LaunchShape& sh, int force, hipStream_t s)
+{
+    if (sh.nl_full)
+        neighbors_seq<B, kHalf, kCopy, true>(b, sh, force, s);
+    else
+        neighbors_seq<B, kHalf, kCopy, false>(b, sh, force, s);
 }
 
 template <class B>

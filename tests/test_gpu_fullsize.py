@@ -19,7 +19,8 @@ import oracle
 from paper_2003_14061_amd import inputs
 from paper_2003_14061_amd import md
 
-from gpu_helpers import check_cells, compare_lists, force_errors, min_image
+from gpu_helpers import (WCA, check_cells, compare_lists, force_errors, min_image, pair,
+                         state)
 
 pytestmark = pytest.mark.gpu
 
@@ -149,3 +150,26 @@ def test_fp32_mixed_error_per_observable_on_the_lj_2048k_state(capsys):
     for k, v in err.items():
         assert v <= TOL["fp32"], (k, v)
     assert err["K"] <= 1e-13 and err["T"] <= 1e-13  # integration and K stay FP64
+
+
+def test_cell_wave_lists_past_24_bit_rows_match_the_oracle():
+    """2 200 000 WCA atoms: eight times the padded count passes 2^24, so the
+    cell-wave build (forced here; the automatic choice at 2.3 atoms per cell is
+    a lane per atom) stores its hits through 64-bit addresses in the list
+    build's full kernel.  Every list of every atom, entry by entry in list
+    order, against the oracle's."""
+    n = 2_200_000
+    L, pos, vel = state(n, 0.8, 11, jitter=0.05)
+    sim, s = pair(pos, vel, L, r_cut=WCA)
+    sim.set_tuning(nl_method=md.MD_NL_CELL_WAVES)
+    assert 8 * sim.grid.n_pad >= 1 << 24
+    sim.build_cells()
+    nc, (o_of, o_start, o_atoms) = check_cells(sim, s, pos)
+    sim.build_neighbors()
+    o_cnt, o_nl, longest = oracle.build_nl(s, nc, pos, (o_of, o_start, o_atoms))
+    assert longest <= sim.grid.nl_capacity
+    cnt, nl = sim.neighbor_list()
+    compare_lists(sim.ids(), cnt, nl, o_cnt, o_nl)
+    sim.forces()
+    assert sim.reduce()["flags"] == 0
+
