@@ -64,7 +64,8 @@ size_t table_bytes(const md_batch* b)
     int64_t wg = 0;
     for (const md_ctx* c : b->rep) wg += max_workgroups(c);
     return align_up(sizeof(KParams) * R) + align_up(sizeof(int32_t) * G_KINDS * (R + 1)) +
-           align_up(sizeof(int32_t) * G_KINDS * R) + align_up(sizeof(uint16_t) * (size_t)wg);
+           align_up(sizeof(int32_t) * G_KINDS * R) + align_up(sizeof(int32_t) * R) +
+           align_up(sizeof(uint16_t) * (size_t)wg);
 }
 
 void drop_graph(md_batch* b)
@@ -135,10 +136,17 @@ md_status upload(md_batch* b)
     int32_t* d_count = reinterpret_cast<int32_t*>(
         t + align_up(sizeof(KParams) * (size_t)R) +
         align_up(sizeof(int32_t) * (size_t)G_KINDS * (size_t)(R + 1)));
-    uint16_t* d_rep = reinterpret_cast<uint16_t*>(
+    int32_t* d_gate = reinterpret_cast<int32_t*>(
         reinterpret_cast<char*>(d_count) + align_up(sizeof(int32_t) * (size_t)G_KINDS * R));
+    uint16_t* d_rep = reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(d_gate) +
+                                                  align_up(sizeof(int32_t) * (size_t)R));
     if ((char*)(d_rep + rep_of.size()) > b->ws + b->ws_bytes) return MD_ERR_ARG;
-    if (hipMemcpy(d_kp, kp.data(), sizeof(KParams) * (size_t)R, hipMemcpyHostToDevice) !=
+    // the gate words start closed; every step's integration finish sets them
+    for (int r = 0; r < R; ++r) kp[r].gate = d_gate + r;
+    const std::vector<int32_t> gate0((size_t)R, 0);
+    if (hipMemcpy(d_gate, gate0.data(), sizeof(int32_t) * (size_t)R, hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(d_kp, kp.data(), sizeof(KParams) * (size_t)R, hipMemcpyHostToDevice) !=
             hipSuccess ||
         hipMemcpy(d_first, first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice) !=
             hipSuccess ||
@@ -151,6 +159,7 @@ md_status upload(md_batch* b)
     b->dev.first = d_first;
     b->dev.count = d_count;
     b->dev.rep_of = d_rep;
+    b->dev.gate = d_gate;
     for (int k = 0; k < G_KINDS; ++k) b->dev.rep_base[k] = rep_base[k];
     b->dev.R = R;
     b->sh = sh;

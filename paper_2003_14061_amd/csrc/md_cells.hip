@@ -43,6 +43,7 @@ __global__ void k_clear(B b)
         d->hist_count = 0;
         d->dmax2 = 0.0;
         d->rebuild = 0;
+        if (p.gate) *p.gate = 0;
         d->blocks_done = 0;
         d->flags = 0;
         d->max_occ = 0;
@@ -56,8 +57,7 @@ __global__ void k_bin(B b, int force)
 {
     Wg wg;
     KParams p;
-    if (!b.fetch(G_ATOMS, wg, p)) return;
-    if (!rebuild_on(p, force)) return;
+    if (!b.fetch_gated(G_ATOMS, force, wg, p)) return;
     for (int i0 = wg.id * blockDim.x; i0 < p.n; i0 += wg.n * blockDim.x) {
         const int i = i0 + threadIdx.x;
         const bool act = i < p.n;
@@ -170,8 +170,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(B b, int force)
 {
     Wg wg;
     KParams p;
-    if (!b.fetch(G_ONE, wg, p)) return;
-    if (!rebuild_on(p, force)) return;
+    if (!b.fetch_gated(G_ONE, force, wg, p)) return;
     __shared__ int wsum[kScanThreads / kWave];
     scan_cells(p, wsum);
 }
@@ -223,8 +222,7 @@ __global__ void k_scatter(B b, int force)
 {
     Wg wg;
     KParams p;
-    if (!b.fetch(G_ATOMS, wg, p)) return;
-    if (!rebuild_on(p, force)) return;
+    if (!b.fetch_gated(G_ATOMS, force, wg, p)) return;
     for (int i = wg.id * blockDim.x + threadIdx.x; i < p.n; i += wg.n * blockDim.x)
         scatter_atom(p, i);
 }
@@ -234,8 +232,7 @@ __global__ void k_cellsort(B b, int force)
 {
     Wg wg;
     KParams p;
-    if (!b.fetch(G_ATOMS, wg, p)) return;
-    if (!rebuild_on(p, force)) return;
+    if (!b.fetch_gated(G_ATOMS, force, wg, p)) return;
     for (int q = wg.id * blockDim.x + threadIdx.x; q < p.n; q += wg.n * blockDim.x)
         sort_slot<F, kPermute>(p, q);
 }
@@ -273,8 +270,7 @@ __global__ void k_copyback(B b, int force)
 {
     Wg wg;
     KParams p;
-    if (!b.fetch(G_ATOMS, wg, p)) return;
-    if (!rebuild_on(p, force)) return;
+    if (!b.fetch_gated(G_ATOMS, force, wg, p)) return;
     for (int q = wg.id * blockDim.x + threadIdx.x; q < p.n; q += wg.n * blockDim.x) {
         p.x[q] = p.sx[q];
         p.y[q] = p.sy[q];

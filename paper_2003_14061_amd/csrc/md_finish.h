@@ -100,6 +100,7 @@ __device__ __forceinline__ void finish_step(const KParams& p, int phase, int rec
             d->dmax2 = m;
             const int rb = p.mode == MD_CELLS_ONLY ? 1 : (m > p.disp_thr2 ? 1 : 0);
             d->rebuild = rb;
+            if (p.gate) *p.gate = rb;
             if (rb) d->n_rebuilds += 1;
         }
     }

@@ -52,6 +52,10 @@ struct KParams {
     int32_t* id;
     // workspace arrays
     DevState* dev;
+    // a batch replica's word in the batch's gate array (a copy of dev->rebuild
+    // that the gated kernels read before the replica's parameters); null for a
+    // system alone
+    int32_t* gate = nullptr;
     int32_t *cell_count, *cell_start, *cell_of, *slot, *order, *tmp;
     uint64_t* nl64;       // list chunks: 4 x 16-bit entries, chunk c of slot k at c*npad + k
     int32_t* nl_count;
@@ -203,6 +207,13 @@ struct Single {
         out = p;
         return true;
     }
+    // fetch for a rebuild-gated kernel: also false when the system does not
+    // rebuild this step (and the call does not force it)
+    __device__ __forceinline__ bool fetch_gated(GridKind k, int force, Wg& w, KParams& out) const
+    {
+        fetch(k, w, out);
+        return force || p.dev->rebuild;
+    }
 };
 
 // Independent replicas in one launch.  For grid rule k, replica r owns
@@ -217,13 +228,29 @@ struct Batch {
     const int32_t* __restrict__ first;   // [G_KINDS][R + 1]
     const int32_t* __restrict__ count;   // [G_KINDS][R]
     const uint16_t* __restrict__ rep_of; // workgroup -> replica, all rules back to back
+    const int32_t* __restrict__ gate;    // [R] each replica's rebuild flag (KParams::gate)
     int32_t rep_base[G_KINDS];
     int32_t R;
     __device__ __forceinline__ bool fetch(GridKind k, Wg& w, KParams& out) const
     {
         const int blk = (int)blockIdx.x;
         const int r = rep_of[rep_base[(int)k] + blk];
-        w.id = blk - first[(int)k * (R + 1) + r];
+        return fetch_rep(k, r, w, out);
+    }
+    // fetch for a rebuild-gated kernel: a workgroup of a replica that does not
+    // rebuild this step (unless forced) returns after two dependent loads (its
+    // replica, that replica's gate word) instead of three (its replica, the
+    // replica's parameters, the flag they point to)
+    __device__ __forceinline__ bool fetch_gated(GridKind k, int force, Wg& w, KParams& out) const
+    {
+        const int blk = (int)blockIdx.x;
+        const int r = rep_of[rep_base[(int)k] + blk];
+        if (!force && !gate[r]) return false;
+        return fetch_rep(k, r, w, out);
+    }
+    __device__ __forceinline__ bool fetch_rep(GridKind k, int r, Wg& w, KParams& out) const
+    {
+        w.id = (int)blockIdx.x - first[(int)k * (R + 1) + r];
         w.n = count[(int)k * R + r];
         if (w.id >= w.n) return false;
         out = global_view(kp[r]);

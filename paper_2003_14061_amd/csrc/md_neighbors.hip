@@ -402,8 +402,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(6))) void k_nl_tiles(B b, int forc
 {
     Wg wg;
     KParams p;
-    if (!b.fetch(G_NL, wg, p)) return;
-    if (!force && !p.dev->rebuild) return;
+    if (!b.fetch_gated(G_NL, force, wg, p)) return;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const KParams q = kCopy ? scratch_view(p) : p;
     int wmax = 0;
