@@ -471,8 +471,8 @@ void md_destroy(md_ctx* ctx);
 typedef struct md_batch md_batch;
 
 /* Validates params[0 .. n_replicas-1] (each as md_init would) and plans the
- * shared workspace.  MD_ERR_ARG if the replicas disagree on precision, mode,
- * reorder or block. */
+ * shared workspace; 1 <= n_replicas <= 32768.  MD_ERR_ARG if the replicas
+ * disagree on precision, mode, reorder or block. */
 md_status md_batch_init(const md_params* params, int32_t n_replicas, md_batch** out);
 
 /* Bytes of the one workspace block of the whole batch (256-byte aligned). */

@@ -64,8 +64,7 @@ size_t table_bytes(const md_batch* b)
     int64_t wg = 0;
     for (const md_ctx* c : b->rep) wg += max_workgroups(c);
     return align_up(sizeof(KParams) * R) + align_up(sizeof(int32_t) * G_KINDS * (R + 1)) +
-           align_up(sizeof(int32_t) * G_KINDS * R) + align_up(sizeof(int32_t) * R) +
-           align_up(sizeof(uint16_t) * (size_t)wg);
+           align_up(sizeof(int32_t) * G_KINDS * R) + align_up(sizeof(uint16_t) * (size_t)wg);
 }
 
 void drop_graph(md_batch* b)
@@ -136,17 +135,20 @@ md_status upload(md_batch* b)
     int32_t* d_count = reinterpret_cast<int32_t*>(
         t + align_up(sizeof(KParams) * (size_t)R) +
         align_up(sizeof(int32_t) * (size_t)G_KINDS * (size_t)(R + 1)));
-    int32_t* d_gate = reinterpret_cast<int32_t*>(
+    uint16_t* d_rep = reinterpret_cast<uint16_t*>(
         reinterpret_cast<char*>(d_count) + align_up(sizeof(int32_t) * (size_t)G_KINDS * R));
-    uint16_t* d_rep = reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(d_gate) +
-                                                  align_up(sizeof(int32_t) * (size_t)R));
     if ((char*)(d_rep + rep_of.size()) > b->ws + b->ws_bytes) return MD_ERR_ARG;
-    // the gate words start closed; every step's integration finish sets them
-    for (int r = 0; r < R; ++r) kp[r].gate = d_gate + r;
-    const std::vector<int32_t> gate0((size_t)R, 0);
-    if (hipMemcpy(d_gate, gate0.data(), sizeof(int32_t) * (size_t)R, hipMemcpyHostToDevice) !=
-            hipSuccess ||
-        hipMemcpy(d_kp, kp.data(), sizeof(KParams) * (size_t)R, hipMemcpyHostToDevice) !=
+    // each replica's entries of the gated rules (their gate bits start clear;
+    // every step's integration finish sets them before a gated kernel runs)
+    for (int r = 0; r < R; ++r) {
+        kp[r].rep = r;
+        for (int j = 0; j < 3; ++j) {
+            const int k = (int)kGatedRules[j];
+            kp[r].gate_tab[j] = d_rep + rep_base[k] + first[(size_t)k * (R + 1) + r];
+            kp[r].gate_n[j] = count[(size_t)k * R + r];
+        }
+    }
+    if (hipMemcpy(d_kp, kp.data(), sizeof(KParams) * (size_t)R, hipMemcpyHostToDevice) !=
             hipSuccess ||
         hipMemcpy(d_first, first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice) !=
             hipSuccess ||
@@ -159,7 +161,6 @@ md_status upload(md_batch* b)
     b->dev.first = d_first;
     b->dev.count = d_count;
     b->dev.rep_of = d_rep;
-    b->dev.gate = d_gate;
     for (int k = 0; k < G_KINDS; ++k) b->dev.rep_base[k] = rep_base[k];
     b->dev.R = R;
     b->sh = sh;
@@ -201,7 +202,7 @@ md_status prepare(md_batch* b)
 
 extern "C" md_status md_batch_init(const md_params* params, int32_t n_replicas, md_batch** out)
 {
-    if (!params || !out || n_replicas < 1 || n_replicas > 65536) return MD_ERR_ARG;
+    if (!params || !out || n_replicas < 1 || n_replicas > kRepMask + 1) return MD_ERR_ARG;
     *out = nullptr;
     md_batch* b = new (std::nothrow) md_batch;
     if (!b) return MD_ERR_ARG;

@@ -43,7 +43,6 @@ __global__ void k_clear(B b)
         d->hist_count = 0;
         d->dmax2 = 0.0;
         d->rebuild = 0;
-        if (p.gate) *p.gate = 0;
         d->blocks_done = 0;
         d->flags = 0;
         d->max_occ = 0;

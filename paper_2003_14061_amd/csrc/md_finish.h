@@ -94,14 +94,21 @@ __device__ __forceinline__ void finish_step(const KParams& p, int phase, int rec
     const int n_wg = grid_of(p, G_INTEGRATE);
     if (phase >= 1) record_step(p, n_wg, record_every, red);
     if (phase <= 1) {
+        __shared__ int rb_all;
         const double m = finish_max<kFinishThreads>(p.ipart, n_wg, 8, 4, red);
         if (threadIdx.x == 0) {
             DevState* d = p.dev;
             d->dmax2 = m;
             const int rb = p.mode == MD_CELLS_ONLY ? 1 : (m > p.disp_thr2 ? 1 : 0);
             d->rebuild = rb;
-            if (p.gate) *p.gate = rb;
             if (rb) d->n_rebuilds += 1;
+            rb_all = rb;
+        }
+        if (p.gate_tab[0]) {  // a batch replica: its gate bits in the workgroup table
+            __syncthreads();
+            const uint16_t v = (uint16_t)(p.rep | (rb_all ? kGateBit : 0));
+            for (int j = 0; j < 3; ++j)
+                for (int i = threadIdx.x; i < p.gate_n[j]; i += blockDim.x) p.gate_tab[j][i] = v;
         }
     }
 }

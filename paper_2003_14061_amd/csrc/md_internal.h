@@ -52,10 +52,12 @@ struct KParams {
     int32_t* id;
     // workspace arrays
     DevState* dev;
-    // a batch replica's word in the batch's gate array (a copy of dev->rebuild
-    // that the gated kernels read before the replica's parameters); null for a
-    // system alone
-    int32_t* gate = nullptr;
+    // a batch replica's entries of the batch's workgroup -> replica table in
+    // the grid rules of the rebuild-gated kernels (kGatedRules), whose bit 15
+    // the integration finish sets to the rebuild flag; null for a system alone
+    uint16_t* gate_tab[3] = {nullptr, nullptr, nullptr};
+    int32_t gate_n[3] = {0, 0, 0};
+    int32_t rep = 0;  // the replica's index in its batch
     int32_t *cell_count, *cell_start, *cell_of, *slot, *order, *tmp;
     uint64_t* nl64;       // list chunks: 4 x 16-bit entries, chunk c of slot k at c*npad + k
     int32_t* nl_count;
@@ -128,6 +130,8 @@ struct Wg {
 // The grid rules of the launches; a batched launch concatenates, per rule,
 // the workgroups of every replica.
 enum GridKind { G_ATOMS, G_ONE, G_INTEGRATE, G_TILES, G_NL, G_KINDS };
+// The grid rules of the rebuild-gated kernels (cell chain, list build).
+constexpr GridKind kGatedRules[3] = {G_ATOMS, G_ONE, G_NL};
 
 constexpr int kScanThreads = 1024;  // the one workgroup of the cell-offset scan
 constexpr int kCellLanes = 32;      // lanes per atom of the cells-only force pass
@@ -223,30 +227,33 @@ struct Single {
 // every workgroup of a
 // launch of rule k (from rep_base[k]) to its replica in one load; workgroups
 // in the gaps map to the replica before them and return.
+constexpr int kGateBit = 1 << 15, kRepMask = kGateBit - 1;  // at most 32768 replicas
+
 struct Batch {
     const KParams* __restrict__ kp;      // [R] per-replica parameters (device)
     const int32_t* __restrict__ first;   // [G_KINDS][R + 1]
     const int32_t* __restrict__ count;   // [G_KINDS][R]
-    const uint16_t* __restrict__ rep_of; // workgroup -> replica, all rules back to back
-    const int32_t* __restrict__ gate;    // [R] each replica's rebuild flag (KParams::gate)
+    // workgroup -> replica (bits 0-14), all rules back to back; in the gated
+    // rules bit 15 holds the replica's rebuild flag of the current step
+    const uint16_t* __restrict__ rep_of;
     int32_t rep_base[G_KINDS];
     int32_t R;
     __device__ __forceinline__ bool fetch(GridKind k, Wg& w, KParams& out) const
     {
         const int blk = (int)blockIdx.x;
-        const int r = rep_of[rep_base[(int)k] + blk];
+        const int r = rep_of[rep_base[(int)k] + blk] & kRepMask;
         return fetch_rep(k, r, w, out);
     }
     // fetch for a rebuild-gated kernel: a workgroup of a replica that does not
-    // rebuild this step (unless forced) returns after two dependent loads (its
-    // replica, that replica's gate word) instead of three (its replica, the
-    // replica's parameters, the flag they point to)
+    // rebuild this step (unless forced) returns after one load (its table
+    // entry) instead of three (its replica, the replica's parameters, the
+    // flag they point to)
     __device__ __forceinline__ bool fetch_gated(GridKind k, int force, Wg& w, KParams& out) const
     {
         const int blk = (int)blockIdx.x;
-        const int r = rep_of[rep_base[(int)k] + blk];
-        if (!force && !gate[r]) return false;
-        return fetch_rep(k, r, w, out);
+        const int v = rep_of[rep_base[(int)k] + blk];
+        if (!force && !(v & kGateBit)) return false;
+        return fetch_rep(k, v & kRepMask, w, out);
     }
     __device__ __forceinline__ bool fetch_rep(GridKind k, int r, Wg& w, KParams& out) const
     {
