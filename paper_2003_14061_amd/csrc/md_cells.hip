@@ -96,7 +96,7 @@ __device__ __forceinline__ int wave_incl_scan(int v)
 // idle kernel here rather than three.
 // The scan itself, by one workgroup of kScanThreads threads (wsum: LDS, one
 // int per wave).
-__device__ __forceinline__ void scan_cells(const KParams& p, int* wsum)
+__device__ __forceinline__ void scan_cells(const KParams& p, int* wsum, int* lds_start = nullptr)
 {
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     int carry = 0, m = 0;
@@ -137,15 +137,22 @@ __device__ __forceinline__ void scan_cells(const KParams& p, int* wsum)
         __syncthreads();
         int ex = carry + before + inc - sum;
         if (c + kScanPer <= p.ncell) {
-            *reinterpret_cast<int4*>(p.cell_start + c) =
-                make_int4(ex, ex + v[0], ex + v[0] + v[1], ex + v[0] + v[1] + v[2]);
+            const int4 st = make_int4(ex, ex + v[0], ex + v[0] + v[1], ex + v[0] + v[1] + v[2]);
+            *reinterpret_cast<int4*>(p.cell_start + c) = st;
             *reinterpret_cast<int4*>(p.cell_count + c) = make_int4(0, 0, 0, 0);
+            if (lds_start) {
+                lds_start[c] = st.x;
+                lds_start[c + 1] = st.y;
+                lds_start[c + 2] = st.z;
+                lds_start[c + 3] = st.w;
+            }
         } else {
 #pragma unroll
             for (int k = 0; k < kScanPer; ++k) {
                 if (c + k < p.ncell) {
                     p.cell_start[c + k] = ex;
                     p.cell_count[c + k] = 0;
+                    if (lds_start) lds_start[c + k] = ex;
                 }
                 ex += v[k];
             }
@@ -161,6 +168,7 @@ __device__ __forceinline__ void scan_cells(const KParams& p, int* wsum)
         p.dev->max_occ = tm;
         p.dev->max_nl = 0;
         p.cell_start[p.ncell] = carry;
+        if (lds_start) lds_start[p.ncell] = carry;
     }
 }
 
@@ -264,6 +272,69 @@ __global__ __launch_bounds__(kScanThreads) void k_sort_small(B b, int force, int
     for (int q = threadIdx.x; q < p.n; q += blockDim.x) sort_slot<F, kPermute>(p, q);
 }
 
+// k_sort_small's cells-only form (kFinish) with its tables in LDS: the cell
+// starts (ncell + 1), and per slot-order position q the atom with its cell
+// (atom | cell << kSortAtomBits) and its id (2 n), so that the scatter and the
+// in-cell sort read global memory only for the binning of the integration
+// pass and the atom data they permute.  Same results as k_sort_small; for
+// systems whose tables fit (sort_lds_bytes).
+constexpr int kSortAtomBits = 14;  // atoms of a small system: at most kSortSmall = 2^14
+
+template <typename F, bool kPermute>
+__global__ __launch_bounds__(kScanThreads) void k_sort_lds(Single b, int phase, int record_every)
+{
+    const KParams& p = b.p;
+    {
+        __shared__ double red[(kScanThreads / kWave) * 5];
+        finish_step(p, phase, record_every, red);
+        __syncthreads();
+    }
+    extern __shared__ int lds[];
+    int* cs = lds;                      // [ncell + 1]
+    int* slot_ac = cs + p.ncell + 1;    // [n] atom | cell << kSortAtomBits
+    int* slot_id = slot_ac + p.n;       // [n]
+    __shared__ int wsum[kScanThreads / kWave];
+    scan_cells(p, wsum, cs);
+    __syncthreads();
+    for (int i = threadIdx.x; i < p.n; i += blockDim.x) {
+        const int c = p.cell_of[i], sl = p.slot[i], key = p.id[i];
+        const int q = cs[c] + sl;
+        slot_ac[q] = i | (c << kSortAtomBits);
+        slot_id[q] = key;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < p.n; q += blockDim.x) {
+        const int ac = slot_ac[q], s = ac & ((1 << kSortAtomBits) - 1), c = ac >> kSortAtomBits;
+        const int a = cs[c], cnt = cs[c + 1] - a, key = slot_id[q];
+        int rank = 0;
+        for (int j = 0; j < cnt; ++j) rank += slot_id[a + j] < key ? 1 : 0;
+        const int d = a + rank;
+        p.order[d] = s;
+        if (kPermute) {
+            p.sx[d] = p.x[s];
+            p.sy[d] = p.y[s];
+            p.sz[d] = p.z[s];
+            p.svx[d] = p.vx[s];
+            p.svy[d] = p.vy[s];
+            p.svz[d] = p.vz[s];
+            reinterpret_cast<F*>(p.sfx)[d] = static_cast<const F*>(p.fx)[s];
+            reinterpret_cast<F*>(p.sfy)[d] = static_cast<const F*>(p.fy)[s];
+            reinterpret_cast<F*>(p.sfz)[d] = static_cast<const F*>(p.fz)[s];
+            p.sid[d] = key;
+            p.scell[d] = c;
+        }
+    }
+}
+
+// LDS bytes of k_sort_lds for p, or 0 when its tables do not fit (60 KiB) or
+// a cell index does not fit beside the atom.
+static size_t sort_lds_bytes(const KParams& p)
+{
+    if (p.n > (1 << kSortAtomBits) || p.ncell >= (1 << (31 - kSortAtomBits))) return 0;
+    const size_t b = sizeof(int) * ((size_t)p.ncell + 1 + 2 * (size_t)p.n);
+    return b <= 61440 ? b : 0;
+}
+
 template <typename F, class B>
 __global__ void k_copyback(B b, int force)
 {
@@ -349,6 +420,17 @@ void launch_sort_small_finish(const KParams& p, int phase, int record_every, hip
 {
     const dim3 one(1), t(kScanThreads);
     const Single b{p};
+    const size_t lds = sort_lds_bytes(p);
+    if (lds) {
+        if (!p.reorder)
+            hipLaunchKernelGGL((k_sort_lds<double, false>), one, t, lds, s, b, phase,
+                               record_every);
+        else if (p.precision == MD_FP64)
+            hipLaunchKernelGGL((k_sort_lds<double, true>), one, t, lds, s, b, phase, record_every);
+        else
+            hipLaunchKernelGGL((k_sort_lds<float, true>), one, t, lds, s, b, phase, record_every);
+        return;
+    }
     if (!p.reorder)
         hipLaunchKernelGGL((k_sort_small<double, Single, false, true>), one, t, 0, s, b, 1, phase,
                            record_every);
