@@ -96,6 +96,16 @@ def test_invalid_parameters_are_rejected(bad):
     assert st == -1 and not ctx.value
 
 
+def test_batch_replica_count_is_bounded():
+    """A batch holds 1 to 32768 replicas (their index shares a 16-bit table
+    entry with the rebuild gate); the count is checked before anything else."""
+    p = params(n=4000)
+    for n in (0, 32769):
+        arr = (md.Params * max(n, 1))(*([p] * max(n, 1)))
+        b = C.c_void_p()
+        assert md.lib().md_batch_init(arr, n, C.byref(b)) == -1 and not b.value
+
+
 def test_third_law_variant_is_accepted_with_a_list():
     for prec in (md.MD_FP64, md.MD_FP32_MIXED):
         ctx = md.md_init(params(n=32000, rho=0.8, r_cut=2.5, newton3=1, precision=prec))

@@ -75,6 +75,34 @@ def test_replicas_follow_the_oracle():
         assert np.abs(st["vel"] - v_ref).max() < 1e-9, r
 
 
+def test_a_replica_of_three_cells_per_side_follows_the_oracle():
+    """A 108-atom replica (3 cells per side: the minimum image by rounding) in
+    a batch of larger ones sends the whole batch's list build to its full
+    kernel; every replica still follows the oracle and its own single run."""
+    from gpu_helpers import WCA, state
+    sys_ = systems(n_replicas=3, seed=9)
+    L, pos, vel = state(108, 0.8, 3, jitter=0.05)
+    sys_.append(dict(pos=pos, vel=vel, L=L, r_cut=WCA, dt=0.005, skin=0.3))
+    assert oracle.cells_per_side(L, WCA + 0.3) == 3
+    b = md.Batch(sys_, precision="fp64")
+    b.prepare()
+    steps = 20
+    b.run(steps, record_every=1)
+    for r, sy in enumerate(sys_):
+        s = oracle.make_sys(len(sy["pos"]), sy["L"], r_cut=sy["r_cut"], skin=sy["skin"],
+                            dt=sy["dt"])
+        p_ref, v_ref, _, o_ref, _ = oracle.run(s, sy["pos"], sy["vel"], steps)
+        st, h = b.state(r), b.history(r)
+        e_scale = np.abs(o_ref["U"]).max() + np.abs(o_ref["K"]).max()
+        assert np.max(np.abs(h["U"] - o_ref["U"])) <= 1e-10 * e_scale, r
+        assert np.abs(min_image(st["pos"] - p_ref, sy["L"])).max() < 1e-10, r
+        one = single(sy, "fp64", b, r)
+        one.prepare()
+        one.step(steps, record_every=1)
+        assert np.array_equal(st["pos"], one.state()["pos"]), r
+        assert b.reduce(r)["flags"] == 0
+
+
 def test_autotuner_keeps_its_best_candidate():
     sys_ = systems(n_replicas=4, seed=11)
     b = md.Batch(sys_, precision="fp32")
