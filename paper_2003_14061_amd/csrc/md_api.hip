@@ -309,9 +309,9 @@ extern "C" md_status md_init(const md_params* in, md_ctx** out)
         k.inner_hi = 0.0;  // empty range: always take the minimum image
     }
     k.block = p.block;
-    // FP64: 4 lanes per atom; FP32-mixed: 2 (its shorter pair arithmetic
-    // leaves the lane-sum and pass overheads a larger share)
-    k.force_lanes = p.precision == MD_FP64 ? 4 : 2;
+    // 2 lanes per atom (2.048 M-atom LJ, 512-thread workgroups: FP64 force pass
+    // 255 us at 2 lanes, 267 at 4, 356 at 8; FP32-mixed 228, 244, 324)
+    k.force_lanes = 2;
     k.force_block = 512;
     c->nl_block_req = 0;
     k.int_grid = kIntegrateGridDefault;

@@ -279,7 +279,7 @@ def md_traj_backward(ctx, tp: TrajParams, ws_ptr: int, gobs_ptr: int, gx_ptr: in
            "md_traj_backward")
 
 
-def md_set_tuning(ctx, force_lanes=4, force_block=512, nl_block=0, tile_cells=0, stage_cap=0,
+def md_set_tuning(ctx, force_lanes=2, force_block=512, nl_block=0, tile_cells=0, stage_cap=0,
                   integrate_grid=0, nl_method=MD_NL_AUTO, tile_y=0, tile_z=0):
     t = Tuning(int(force_lanes), int(force_block), int(nl_block), int(tile_cells), int(stage_cap),
                int(integrate_grid), int(nl_method), int(tile_y), int(tile_z))
@@ -611,7 +611,7 @@ def md_batch_replica(b, r):
 
 
 def _tuning_tuple(t: dict):
-    return Tuning(int(t.get("force_lanes", 4)), int(t.get("force_block", 512)),
+    return Tuning(int(t.get("force_lanes", 2)), int(t.get("force_block", 512)),
                   int(t.get("nl_block", 0)), int(t.get("tile_cells", 0)),
                   int(t.get("stage_cap", 0)), int(t.get("integrate_grid", 0)),
                   int(t.get("nl_method", MD_NL_AUTO)), int(t.get("tile_y", 0)),
