@@ -367,12 +367,12 @@ __device__ __forceinline__ void nl_tile(const KParams& p, int t, char* smem, int
     const int ncells = g.kx * g.ky * g.kz;
     const bool small = nl_small(p);
     // Home cells next to a periodic boundary (real index 0 or nc - 1 on some
-    // axis) have wrapped candidates and take the image rule, one round of 64
-    // candidates at a time, as do the rare tiles that do not fit in LDS or
-    // grids under 5 cells per side: those paths then hold fewer registers than
-    // the common one (the kernel's register count is that of its largest path),
-    // which keeps six waves per SIMD.  The other home cells of a boundary tile
-    // have no wrapped candidate and take the interior path.
+    // axis) have wrapped candidates and take the image rule; the other home
+    // cells of a boundary tile have none and take the interior path.  The rare
+    // tiles that do not fit in LDS, and grids under 5 cells per side, take one
+    // round of 64 candidates at a time: those paths then hold fewer registers
+    // than the common ones (the kernel's register count is that of its largest
+    // path), which keeps six waves per SIMD.
     for (int hc = wid; hc < ncells; hc += nw) {
         if (kFull && mode == 2) {
             if (s.fits)
