@@ -76,18 +76,6 @@ __global__ void k_bin(B b, int force)
     }
 }
 
-// Inclusive scan across a wave64.
-__device__ __forceinline__ int wave_incl_scan(int v)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        int t = __shfl_up(v, o, kWave);
-        if (lane >= o) v += t;
-    }
-    return v;
-}
-
 // The cell offsets: one workgroup of kScanThreads threads scans the counts
 // kScanPer cells per thread at a time (one 16-byte load each), in chunks of
 // kScanThreads * kScanPer cells carried over in order; writes cell_start,
@@ -119,13 +107,8 @@ __device__ __forceinline__ void scan_cells(const KParams& p, int* wsum, int* lds
             sum += v[k];
             m = v[k] > m ? v[k] : m;
         }
-        // exclusive scan of the thread sums: wave64 shuffles, then the wave totals
-        int inc = sum;
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const int t = __shfl_up(inc, o, kWave);
-            if (lane >= o) inc += t;
-        }
+        // exclusive scan of the thread sums: wave64 DPP scan, then the wave totals
+        const int inc = wave_scan_incl(sum);
         if (lane == kWave - 1) wsum[wid] = inc;
         __syncthreads();
         int before = 0, total = 0;

@@ -125,6 +125,23 @@ __device__ __forceinline__ T wave_max(T v)
     return v;
 }
 
+// Inclusive prefix sum of v over the 64 lanes of a wave by DPP lane moves on
+// the VALU (no LDS round trip): shifts by 1, 2, 4 and 8 lanes inside each row
+// of 16 lanes (lanes shifted in from outside the row read 0) give each row's
+// own prefix; then each row's last lane is added to the rows above it (lane
+// 15 into rows 1 and 3, lane 31 into rows 2 and 3).  Every lane of the wave
+// must be active.
+__device__ __forceinline__ int wave_scan_incl(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
 // The maximum of v over the workgroup, valid in thread 0 (0 elsewhere).  Every
 // thread of the workgroup calls it.  Kernels fold a per-thread maximum into a
 // device-wide one with this and a single global atomic per workgroup: atomics

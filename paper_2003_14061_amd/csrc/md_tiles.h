@@ -200,12 +200,7 @@ __device__ __forceinline__ void stage_tables(const KParams& p, const Tile& g, St
         }
         // workgroup exclusive scan of cnt
         const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-        int inc = cnt;
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const int v = __shfl_up(inc, o, kWave);
-            if (lane >= o) inc += v;
-        }
+        const int inc = wave_scan_incl(cnt);
         if (lane == kWave - 1) s.scan[wid] = inc;
         __syncthreads();
         int before = 0, tot = 0;
@@ -240,12 +235,7 @@ __device__ __forceinline__ void stage_tables(const KParams& p, const Tile& g, St
             const int t0 = (c * s.rows_y + b) * s.stride;
             cnt = s.off[t0 + g.kx + 1] - s.off[t0 + 1];
         }
-        int inc = cnt;
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const int v = __shfl_up(inc, o, kWave);
-            if (r >= o) inc += v;
-        }
+        const int inc = wave_scan_incl(cnt);
         if (r < s.nhr) s.hp[r + 1] = inc;
         if (r == 0) s.hp[0] = 0;
     }
