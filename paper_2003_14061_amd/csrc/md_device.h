@@ -106,23 +106,79 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks)
 
 // ---- wave64 and workgroup reductions (fixed order: deterministic) ----
 
+// v as read from another lane by DPP control kCtrl under row mask kRows;
+// lanes with no source lane (shifted in from outside their row with kBound,
+// or in a row outside kRows) get old.  32- or 64-bit values (a 64-bit one
+// moves as its two halves).
+template <int kCtrl, int kRows, bool kBound, typename T>
+__device__ __forceinline__ T dpp_read(T old, T v)
+{
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(
+            T, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v),
+                                           kCtrl, kRows, 0xf, kBound));
+    } else {
+        const uint64_t o = __builtin_bit_cast(uint64_t, old), b = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(
+            (int)(uint32_t)o, (int)(uint32_t)b, kCtrl, kRows, 0xf, kBound);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(
+            (int)(uint32_t)(o >> 32), (int)(uint32_t)(b >> 32), kCtrl, kRows, 0xf, kBound);
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    }
+}
+
+// Lane 63's v, in every lane (scalar registers).
+template <typename T>
+__device__ __forceinline__ T from_lane63(T v)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+    } else {
+        const uint64_t b = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    }
+}
+
+// Sum and maximum over the 64 lanes of a wave, in every lane, by DPP lane
+// moves on the VALU (no LDS round trips): the combining pattern of
+// wave_scan_incl (shifts by 1, 2, 4, 8 lanes inside each row of 16, then the
+// lane-15 and lane-31 broadcasts into the rows above), after which lane 63
+// holds the result; the sum adds in that fixed order.  Every lane of the wave
+// must be active.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
 {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    const T z = T(0);
+    v += dpp_read<0x111, 0xf, true>(z, v);   // row_shr:1
+    v += dpp_read<0x112, 0xf, true>(z, v);   // row_shr:2
+    v += dpp_read<0x114, 0xf, true>(z, v);   // row_shr:4
+    v += dpp_read<0x118, 0xf, true>(z, v);   // row_shr:8
+    v += dpp_read<0x142, 0xa, false>(z, v);  // row_bcast:15 into rows 1, 3
+    v += dpp_read<0x143, 0xc, false>(z, v);  // row_bcast:31 into rows 2, 3
+    return from_lane63(v);
 }
 
 template <typename T>
 __device__ __forceinline__ T wave_max(T v)
 {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-        T w = __shfl_xor(v, o, kWave);
-        v = w > v ? w : v;
-    }
-    return v;
+    // lanes with no source read their own value, which leaves them unchanged
+    T w;
+    w = dpp_read<0x111, 0xf, false>(v, v);
+    v = w > v ? w : v;
+    w = dpp_read<0x112, 0xf, false>(v, v);
+    v = w > v ? w : v;
+    w = dpp_read<0x114, 0xf, false>(v, v);
+    v = w > v ? w : v;
+    w = dpp_read<0x118, 0xf, false>(v, v);
+    v = w > v ? w : v;
+    w = dpp_read<0x142, 0xa, false>(v, v);
+    v = w > v ? w : v;
+    w = dpp_read<0x143, 0xc, false>(v, v);
+    v = w > v ? w : v;
+    return from_lane63(v);
 }
 
 // Inclusive prefix sum of v over the 64 lanes of a wave by DPP lane moves on
