@@ -330,8 +330,10 @@ md_status md_history(md_ctx* ctx, md_record* out, int32_t max_records, int32_t* 
  * parity tolerances; the force pass's summation order depends on
  * force_lanes, so bitwise reproducibility holds for a fixed tuning. */
 typedef struct {
-    int32_t force_lanes;    /* lanes sharing one atom's list in the force pass: 1, 2, 4, 8 */
-    int32_t force_block;    /* threads per workgroup of the force pass: 64..1024, multiple of 64 */
+    int32_t force_lanes;    /* lanes sharing one atom's list in the force pass: 1, 2, 4, 8
+                               (2 after md_init) */
+    int32_t force_block;    /* threads per workgroup of the force pass: 64..1024, multiple of 64
+                               (512 after md_init) */
     int32_t nl_block;       /* threads per workgroup of the list build: 64..1024, multiple of 64;
                                0 = automatic (a lane per home atom of a mean tile, or a wave
                                per home cell of the widest tile, at most 16 waves) */
