@@ -475,15 +475,17 @@ __device__ __forceinline__ void chunk_pairs(const KParams& p, const Stage& s, ui
 }
 
 // Chunks c = sub, sub+LANES, ... of one home atom's list, each loaded one
-// step ahead of its use.
+// step ahead of its use.  The first one is loaded whether or not the list
+// reaches it (row sub exists when it is inside the cap / 4 + 1 allocated
+// rows), so that its load does not wait for the count.
 template <int LANES, int kImage, bool kFits, bool kMask, class Op>
 __device__ __forceinline__ void walk_list(const KParams& p, const Stage& s, int slot_i, int sub,
                                           int cnt, double xi, double yi, double zi, Op& op)
 {
-    const int nchunk = (cnt + kChunk - 1) / kChunk;
     const uint64_t* col = p.nl64 + slot_i;
     int c = sub;
-    uint64_t next = c < nchunk ? col[(int64_t)c * p.npad] : 0;
+    uint64_t next = c <= p.cap / kChunk ? col[(int64_t)c * p.npad] : 0;
+    const int nchunk = (cnt + kChunk - 1) / kChunk;
     while (c < nchunk) {
         const uint64_t ch = next;
         const int cn = c + LANES;
